@@ -1,0 +1,227 @@
+/*
+ * yeeopt: adjoint FDTD hot path for inverse design of passive Si photonics
+ * on MI355X (gfx950).  C ABI.
+ *
+ * The library computes, for control variables C and projection strength
+ * beta (paper Sec. 3, Eqs. (2), (3)/(6), (7), (8)), the per-component
+ * anisotropic permittivity on the Yee grid; advances the Yee scheme with
+ * time-harmonic electric-current mode sources (Sec. 2 and Appendix A) once
+ * for every forward right-hand side (input source x wavelength) and once for
+ * every adjoint right-hand side (output port x wavelength, unit amplitude);
+ * reads amplitude and phase of the steady state in the design region and on
+ * the port planes; forms the modal coefficients alpha (Appendix A); and pulls
+ * dF/dalpha back to dF/dC through Eq. (1) and the parametrization's
+ * vector-Jacobian product, without forming the Jacobian.
+ *
+ * Conventions
+ *   - Grid: nx x ny x nz cells, the CPML included.  Yee sites in cell units:
+ *     E_x(i+1/2,j,k), E_y(i,j+1/2,k), E_z(i,j,k+1/2), Ht_x(i,j+1/2,k+1/2),
+ *     Ht_y(i+1/2,j,k+1/2), Ht_z(i+1/2,j+1/2,k); Ht = eta0 H.  The outer box is
+ *     a perfect electric conductor.  Dense 3-D arrays exchanged with the
+ *     caller are FP32 [3][nz][ny][nx], x fastest.
+ *   - Time: dt = courant * min(dx,dy,dz) / c.  E^n lives at n dt, Ht at
+ *     (n+1/2) dt.  Phasors follow E(t) = Re(Ehat exp(-i w t)).
+ *   - Planes: normal `axis` (0,1,2) at cell `index`; (c0,c1) are the other
+ *     two axes in increasing order with extents [lo0,lo0+n0) x [lo1,lo1+n1);
+ *     plane arrays are [2][n1][n0], components ordered cyclically
+ *     (axis x: (y,z); axis y: (z,x); axis z: (x,y)).
+ *   - Complex arrays are interleaved (re, im): complex64 on the device,
+ *     complex128 (double pairs) on the host.
+ *   - Design canvas: the design area (md x nd pixels at (i0, j0)) plus a
+ *     2-pixel margin, `supersample` sub-pixels per pixel, FP32
+ *     [S(nd+4)][S(md+4)]; sub-pixel (v,u) covers x in
+ *     [i0-2.5+u/S, i0-2.5+(u+1)/S) and the same in y.  Controls are FP32
+ *     [nc][mc] (x fastest) spread over the design area.
+ *
+ * Memory and streams
+ *   - The library never allocates device memory.  Every device pointer is
+ *     owned by the caller; a plan keeps non-owning pointers to its bound
+ *     workspace and the caller keeps it alive until yo_plan_destroy.
+ *   - Calls taking a hipStream_t are asynchronous on that stream, except
+ *     where noted; host arrays passed to them are copied before return.
+ *   - Errors: a negative yo_status and a thread-local message from
+ *     yo_last_error().  Device faults surface as YO_EHIP.
+ */
+#ifndef YEEOPT_H
+#define YEEOPT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *yo_stream;   /* same type as hipStream_t */
+typedef struct yo_plan yo_plan;
+typedef int yo_status;
+
+enum {
+    YO_OK = 0,
+    YO_EINVAL = -1,        /* bad argument or descriptor                        */
+    YO_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. too many ports)   */
+    YO_EHIP = -3,          /* HIP runtime error                                 */
+    YO_EWORKSPACE = -4,    /* no workspace bound or too small                   */
+    YO_EUNSTABLE = -5,     /* Courant number above the stability limit          */
+    YO_ESTATE = -6         /* call out of order (e.g. gradient before a run)    */
+};
+
+enum { YO_FORWARD = 1, YO_ADJOINT = 2, YO_BOTH = 3 };
+
+/* Grid and absorbing boundary (CPML on every face with npml > 0; the PML is
+ * graded as sigma = scale * 0.8 (m+1) (c dt / d_a) * xi^m with depth xi in
+ * [0,1], stretch 1 + (kappa_max - 1) xi^m and CFS shift a_max (1 - xi)). */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;          /* metres */
+    double courant;             /* c dt / min(dx, dy, dz) */
+    int npml[6];                /* cells on faces -x,+x,-y,+y,-z,+z */
+    double pml_m, pml_sigma_scale, pml_kappa_max, pml_a_max;
+} yo_grid;
+
+/* Design region and parametrization (paper Sec. 3).  The Si slab holds the
+ * E_x/E_y planes k_lo..k_hi; E_z planes k_lo..k_hi-1 are inside and the E_z
+ * planes k_lo-1 and k_hi lie on the slab faces. */
+typedef struct {
+    int i0, j0, md, nd;         /* design area pixels [i0,i0+md) x [j0,j0+nd) */
+    int k_lo, k_hi;
+    int mc, nc;                 /* control grid, x count and y count */
+    double filter_r;            /* Gaussian basis support radius, control pixels (sigma = r/2) */
+    int supersample;            /* S, even */
+    double eps_core, eps_clad;
+    double sobel_delta;         /* regulariser in n^2 = G^2 / (|G|^2 + delta) */
+} yo_design;
+
+typedef struct { int axis, index, lo0, lo1, n0, n1; } yo_plane;
+
+/* Per-wavelength time-stepping description. */
+typedef struct {
+    double omega;               /* angular frequency, rad/s */
+    double ramp_steps;          /* raised-cosine source ramp length in steps (0: none) */
+    int win_start, win_len;     /* E^n for n in [win_start, win_start+win_len) is fitted */
+} yo_freq;
+
+/* Create a plan (host only, no device work).  Validates the descriptors:
+ * YO_EUNSTABLE if c dt sqrt(sum 1/d_a^2) >= 1; YO_EINVAL for an odd
+ * supersample, a design canvas that leaves the grid or touches the CPML,
+ * a source or port plane outside the grid or inside the CPML, an empty or
+ * out-of-range window, or non-positive sizes.  The plan has n_src forward
+ * sources and n_ports output ports (their planes fixed here, their mode
+ * profiles set later); it owns (n_src + n_ports) * n_freq right-hand sides.
+ * Limits: n_ports <= 8, n_freq <= 16, n_src*n_freq <= 32,
+ * n_ports*n_freq <= 64 (YO_EUNSUPPORTED beyond). */
+yo_status yo_plan_create(const yo_grid *grid, const yo_design *design, int n_steps,
+                         int n_freq, const yo_freq *freqs, int n_src, const yo_plane *src_planes,
+                         int n_ports, const yo_plane *port_planes, yo_plan **out);
+void yo_plan_destroy(yo_plan *plan);
+
+/* Device bytes the plan needs (host only). */
+yo_status yo_workspace_bytes(const yo_plan *plan, size_t *bytes);
+
+/* Bind a caller-owned device buffer of at least yo_workspace_bytes bytes
+ * (256-byte aligned) and upload the plan's tables (PML profiles, step
+ * phases, filter taps) on `stream`.  YO_EWORKSPACE if too small. */
+yo_status yo_bind_workspace(yo_plan *plan, void *dev, size_t bytes, yo_stream stream);
+
+/* Background: dev_kappa = 1/eps_r per E component, FP32 [3][nz][ny][nx];
+ * dev_mask = background fill of the design canvas, FP32 [S(nd+4)][S(md+4)]
+ * (only its margin is used).  Both are copied into the workspace. */
+yo_status yo_set_background(yo_plan *plan, const float *dev_kappa, const float *dev_mask,
+                            yo_stream stream);
+
+/* Mode source of input `src` (Appendix A): the electric current J = n x h on
+ * its plane, i.e. J_t1 = -h_t2, J_t2 = h_t1.  host_h is complex128 [2][n1][n0]
+ * with h_t1 sampled at the E_t2 sites and h_t2 at the E_t1 sites. */
+yo_status yo_set_source_mode(yo_plan *plan, int src, const double *host_h, yo_stream stream);
+
+/* Output port `port` with mode (e, h) (Appendix A): monitor weights
+ * w_t1 = conj(h_t2)/(2N), w_t2 = -conj(h_t1)/(2N), N = (1/2) sum (e_t1 conj(h_t2)
+ * - e_t2 conj(h_t1)), so alpha = sum w . Ehat and alpha = 1 for Ehat = e.  The
+ * unit-amplitude adjoint source of this port is jhat = w.  host_e, host_h:
+ * complex128 [2][n1][n0] (e_t sampled at the E_t sites, h as above).
+ * YO_EINVAL if N = 0. */
+yo_status yo_set_port_mode(yo_plan *plan, int port, const double *host_e, const double *host_h,
+                           yo_stream stream);
+
+/* Parametrization (Sec. 3): dev_C FP32 [nc][mc] -> Eq. (2) level set with a
+ * truncated Gaussian basis, tanh projection Eq. (3)/(6), density mix,
+ * Yee-cell averages Eq. (8), Sobel normals, Eq. (7), extrusion through the
+ * slab; writes kappa on the design area plus a one-pixel ring.  Must follow
+ * yo_set_background.  Keeps what the gradient needs. */
+yo_status yo_set_design(yo_plan *plan, const float *dev_C, double beta, yo_stream stream);
+
+/* Time stepping.  `which` is YO_FORWARD, YO_ADJOINT or YO_BOTH.
+ * yo_run: zero the selected right-hand sides' fields, step n_steps times in
+ * one launch per step over all of them, then fit the steady-state phasors.
+ * The step launches are replayed from a captured HIP graph of `chunk` steps
+ * when use_graph != 0. */
+yo_status yo_run(yo_plan *plan, int which, int chunk, int use_graph, yo_stream stream);
+
+/* Lower-level pieces of yo_run (used by the batch executor and tests). */
+yo_status yo_reset(yo_plan *plan, int which, yo_stream stream);
+yo_status yo_advance(yo_plan *plan, int which, int n_steps, yo_stream stream);
+yo_status yo_finalize(yo_plan *plan, int which, yo_stream stream);
+
+/* Step several plans together: every launch covers every tile of every
+ * plan's selected right-hand sides; each plan keeps its own step counter and
+ * stops at its own n_steps.  Graph mode captures `chunk` launches once per
+ * distinct plan list and relaunches them. */
+yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n_plans, int n_steps,
+                          int chunk, int use_graph, yo_stream stream);
+
+/* Host-side step count of the last reset/advance of `plan`. */
+yo_status yo_steps_done(const yo_plan *plan, int *steps);
+
+/* Tile shape of the time-stepping kernel: rows per wave (4 or 8) and
+ * z-planes per wave (>= 1).  Results do not depend on it (bitwise). */
+yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk);
+
+/* Modal coefficients (Appendix A) of the forward right-hand sides:
+ * dev_alpha complex64 [n_src][n_ports][n_freq]. */
+yo_status yo_alpha(const yo_plan *plan, float *dev_alpha, yo_stream stream);
+
+/* Gradient (Eq. (1) and the chain's VJP): dev_coef = dF/dalpha (holomorphic
+ * Wirtinger derivative, e.g. conj(alpha) for F = |alpha|^2), complex64
+ * [n_src][n_ports][n_freq]; dev_dFdC FP32 [nc][mc] receives
+ * sum 2 Re(coef dalpha/dC).  Needs a finished YO_BOTH run and yo_set_design. */
+yo_status yo_gradient(yo_plan *plan, const float *dev_coef, float *dev_dFdC, yo_stream stream);
+
+/* Same, stopping after Eq. (1): dF/dkappa on the DFT box, FP32 [3][bz][by][bx]
+ * (box = design area plus its one-pixel ring x E planes k_lo-1..k_hi). */
+yo_status yo_gradient_kappa(yo_plan *plan, const float *dev_coef, float *dev_g, yo_stream stream);
+
+/* The parametrization's VJP alone: dev_gkappa = dF/dkappa on the DFT box,
+ * FP32 [3][bz][by][bx] (layout of yo_gradient_kappa) -> dev_dFdC FP32
+ * [nc][mc] through the extrusion, Eq. (7), the normals, the averages, the
+ * projection and the filter, for the design last set by yo_set_design. */
+yo_status yo_chain_vjp(yo_plan *plan, const float *dev_gkappa, float *dev_dFdC, yo_stream stream);
+
+/* Right-hand side numbering: forward (src s, freq f) -> f*n_src + s;
+ * adjoint (port p, freq f) -> n_src*n_freq + f*n_ports + p. */
+yo_status yo_rhs_count(const yo_plan *plan, int *n_rhs);
+
+/* Steady-state phasors of right-hand side `rhs`: region 0 = DFT box,
+ * complex64 [3][bz][by][bx]; region 1+p = plane of port p, complex64
+ * [2][n1][n0].  Valid after yo_finalize. */
+yo_status yo_get_dft(const yo_plan *plan, int rhs, int region, float *dev_out, yo_stream stream);
+
+/* Test hooks: current fields of `rhs` as FP32 [3][nz][ny][nx] (E^n and
+ * Ht^{n-1/2} after n steps). */
+yo_status yo_set_fields(yo_plan *plan, int rhs, const float *dev_E, const float *dev_H,
+                        yo_stream stream);
+yo_status yo_get_fields(const yo_plan *plan, int rhs, float *dev_E, float *dev_H,
+                        yo_stream stream);
+/* Current kappa (background plus design), FP32 [3][nz][ny][nx]. */
+yo_status yo_get_kappa(const yo_plan *plan, float *dev_kappa, yo_stream stream);
+
+/* Bytes of the time-stepping kernel's traffic model per cell-update for
+ * this plan (48 + 12/R + PML and DFT terms), host only. */
+yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
+                         double *cell_updates_per_step);
+
+const char *yo_last_error(void);
+const char *yo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* YEEOPT_H */

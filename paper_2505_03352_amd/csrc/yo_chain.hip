@@ -1,0 +1,504 @@
+// Parametrization chain (paper Sec. 3) and its vector-Jacobian product, plus
+// the small kernels around the time stepping: fills, pitched copies, the
+// steady-state fit, the modal overlap and the Eq. (1) gradient assembly.
+// All of this is 2-D or plane-sized work next to the 3-D time stepping; the
+// kernels are plain one-thread-per-output gathers (no atomics, fixed
+// summation order, so results do not depend on scheduling).
+#include "yo_internal.h"
+
+namespace {
+
+constexpr int BS = 256;
+
+inline int nblk(size_t n) { return (int)((n + BS - 1) / BS); }
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ------------------------------------------------------------- utilities
+__global__ void k_fill(float *p, size_t n, float v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_pitch_copy(const float *src, float *dst, int ncomp, int nz, int ny, int nx,
+                             int sp, int dp)
+{
+    const size_t rows = (size_t)ncomp * nz * ny;
+    const size_t n = rows * nx;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = i / nx;
+        const int x = (int)(i - row * nx);
+        dst[row * dp + x] = src[row * sp + x];
+    }
+}
+
+// Ehat = (g00 Re S + g01 Im S) + i (g10 Re S + g11 Im S): least-squares
+// amplitude/phase from the DFT sums S = sum E^n exp(+i w n dt)
+__global__ void k_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float2 s = a[i];
+        a[i] = make_float2(fmaf(g00, s.x, g01 * s.y), fmaf(g10, s.x, g11 * s.y));
+    }
+}
+
+// alpha = sum w * Ehat over one port plane; one block, fixed-order tree
+__global__ void k_alpha(const float2 *e, const float2 *w, int n, float2 *out)
+{
+    __shared__ float sr[BS], si[BS];
+    float ar = 0.0f, ai = 0.0f;
+    for (int i = threadIdx.x; i < n; i += BS) {
+        const float2 a = w[i], b = e[i];
+        ar = fmaf(a.x, b.x, fmaf(-a.y, b.y, ar));
+        ai = fmaf(a.x, b.y, fmaf(a.y, b.x, ai));
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sr[threadIdx.x] += sr[threadIdx.x + s];
+            si[threadIdx.x] += si[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = make_float2(sr[0], si[0]);
+}
+
+// ------------------------------------------------------------- forward chain
+// Eq. (2) with the truncated Gaussian basis (separable taps with clamped
+// control indices), then the tanh projection Eq. (3)/(6); the canvas margin
+// takes the background fill.
+__global__ void k_project(YoChainBufs c, const float *C, float beta)
+{
+    const int n = c.U * c.V;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const int v = i / c.U, u = i - v * c.U;
+    const int ud = u - 2 * c.S, vd = v - 2 * c.S;
+    if (ud < 0 || ud >= c.S * c.md || vd < 0 || vd >= c.S * c.nd) {
+        c.rho[i] = c.mask[i];
+        return;
+    }
+    const int xlo = c.tap_lo_x[ud], xn = c.tap_n_x[ud];
+    const int ylo = c.tap_lo_y[vd], yn = c.tap_n_y[vd];
+    float phi = 0.0f;
+    for (int ty = 0; ty < yn; ++ty) {
+        const int b = clampi(ylo + ty, 0, c.nc - 1);
+        float row = 0.0f;
+        for (int tx = 0; tx < xn; ++tx) {
+            const int a = clampi(xlo + tx, 0, c.mc - 1);
+            row = fmaf(c.tap_w_x[ud * c.tmax + tx], C[b * c.mc + a], row);
+        }
+        phi = fmaf(c.tap_w_y[vd * c.tmax + ty], row, phi);
+    }
+    phi -= 0.5f;
+    const float t = tanhf(beta * phi);
+    c.tanh_[vd * (c.S * c.md) + ud] = t;
+    c.rho[i] = 0.5f * (1.0f + t);
+}
+
+// Eq. (8): S x S box means centred on each E component (E_x window shifted
+// half a cell in x, E_y in y), of 1/eps, eps and rho.
+__global__ void k_box(YoChainBufs c)
+{
+    const int gsz = c.G0 * c.G1;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= 3 * gsz) return;
+    const int comp = i / gsz, pix = i - comp * gsz;
+    const int n = pix / c.G0, m = pix - n * c.G0;
+    const int half = c.S / 2;
+    const int shx = comp == 0 ? half : 0, shy = comp == 1 ? half : 0;
+    const float de = c.eps_core - c.eps_clad;
+    float p = 0.0f, q = 0.0f, r = 0.0f;
+    for (int b = 0; b < c.S; ++b) {
+        const int v = clampi(c.S * n + shy + b, 0, c.V - 1);
+        for (int a = 0; a < c.S; ++a) {
+            const int u = clampi(c.S * m + shx + a, 0, c.U - 1);
+            const float rho = c.rho[v * c.U + u];
+            const float eps = fmaf(de, rho, c.eps_clad);
+            p += 1.0f / eps;
+            q += eps;
+            r += rho;
+        }
+    }
+    const float inv = 1.0f / (float)(c.S * c.S);
+    c.P[i] = p * inv;
+    c.Q[i] = q * inv;
+    c.R[i] = r * inv;
+}
+
+__device__ __forceinline__ void sobel(const float *R, int G0, int G1, int n, int m, float &gx,
+                                      float &gy)
+{
+    const float w[3] = {1.0f, 2.0f, 1.0f};
+    float sx = 0.0f, sy = 0.0f;
+#pragma unroll
+    for (int dn = -1; dn <= 1; ++dn) {
+#pragma unroll
+        for (int dm = -1; dm <= 1; ++dm) {
+            const float v = R[clampi(n + dn, 0, G1 - 1) * G0 + clampi(m + dm, 0, G0 - 1)];
+            sx = fmaf(w[dn + 1] * (float)dm, v, sx);
+            sy = fmaf(w[dm + 1] * (float)dn, v, sy);
+        }
+    }
+    gx = sx * 0.125f;
+    gy = sy * 0.125f;
+}
+
+// Sobel normals, Eq. (7), extrusion through the slab into the 3-D kappa.
+__global__ void k_smooth(YoChainBufs c, float *kappa, int nx, int ny, int nz, int nxp, int i0,
+                         int j0, int k_lo, int k_hi)
+{
+    const int wm = c.md + 2, wn = c.nd + 2;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= wm * wn) return;
+    const int n = 1 + i / wm, m = 1 + i % wm;
+    const int gsz = c.G0 * c.G1;
+    const int pix = n * c.G0 + m;
+    float gxx, gyx, gxy, gyy;
+    sobel(c.R, c.G0, c.G1, n, m, gxx, gyx);             // on the E_x grid
+    sobel(c.R + gsz, c.G0, c.G1, n, m, gxy, gyy);       // on the E_y grid
+    const float n2x = gxx * gxx / (gxx * gxx + gyx * gyx + c.delta);
+    const float n2y = gyy * gyy / (gxy * gxy + gyy * gyy + c.delta);
+    const float kx = fmaf(n2x, c.P[pix], (1.0f - n2x) / c.Q[pix]);
+    const float ky = fmaf(n2y, c.P[gsz + pix], (1.0f - n2y) / c.Q[gsz + pix]);
+    const float kzi = 1.0f / c.Q[2 * gsz + pix];
+    const float kzf = 0.5f * (c.P[2 * gsz + pix] + 1.0f / c.eps_clad);
+    c.aux[0 * gsz + pix] = n2x;
+    c.aux[1 * gsz + pix] = n2y;
+    c.aux[2 * gsz + pix] = gxx;
+    c.aux[3 * gsz + pix] = gyx;
+    c.aux[4 * gsz + pix] = gxy;
+    c.aux[5 * gsz + pix] = gyy;
+    const int x = i0 - 2 + m, y = j0 - 2 + n;
+    const size_t plane = (size_t)ny * nxp, comp = plane * nz;
+    for (int k = k_lo; k <= k_hi; ++k) {
+        const size_t o = (size_t)k * plane + (size_t)y * nxp + x;
+        kappa[o] = kx;
+        kappa[comp + o] = ky;
+    }
+    for (int k = k_lo; k < k_hi; ++k) kappa[2 * comp + (size_t)k * plane + (size_t)y * nxp + x] = kzi;
+    kappa[2 * comp + (size_t)(k_lo - 1) * plane + (size_t)y * nxp + x] = kzf;
+    kappa[2 * comp + (size_t)k_hi * plane + (size_t)y * nxp + x] = kzf;
+}
+
+// ------------------------------------------------------------- Eq. (1)
+// dF/deps_c(r) = sum_{f,s,p} 2 Re[coef_{s,p,f} (-2 i sin theta_f) E_F E_A]
+//             = sum 4 sin theta_f Im[coef E_F E_A];  dF/dkappa = -dF/deps / kappa^2
+// One thread per in-plane box cell, looping over the box planes; also forms
+// the z sums of the extrusion's transpose.
+__global__ void k_grad(const YoGradArgs a)
+{
+    const int bx = a.box[3], by = a.box[4], bz = a.box[5];
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= bx * by) return;
+    const int bj = i / bx, bi = i - bj * bx;
+    const size_t bsz = (size_t)bx * by * bz;
+    const size_t plane = (size_t)a.ny * a.nxp, comp = plane * a.nz;
+    float sx = 0.0f, sy = 0.0f, szi = 0.0f, szf = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+        for (int bk = 0; bk < bz; ++bk) {
+            const size_t o = ((size_t)c * bz + bk) * (size_t)bx * by + i;
+            float ge = 0.0f;
+            for (int f = 0; f < a.n_freq; ++f) {
+                const float s4 = 4.0f * a.sinth[f];
+                for (int s = 0; s < a.n_src; ++s) {
+                    const float2 ef = a.EF[f * a.n_src + s][o];
+                    for (int p = 0; p < a.n_ports; ++p) {
+                        const float2 ea = a.EA[f * a.n_ports + p][o];
+                        const float2 cf = a.coef[(s * a.n_ports + p) * a.n_freq + f];
+                        // prod = ef * ea
+                        const float pr = fmaf(ef.x, ea.x, -ef.y * ea.y);
+                        const float pi = fmaf(ef.x, ea.y, ef.y * ea.x);
+                        // Im(cf * prod)
+                        const float im = fmaf(cf.x, pi, cf.y * pr);
+                        ge = fmaf(s4, im, ge);
+                    }
+                }
+            }
+            const int x = a.box[0] + bi, y = a.box[1] + bj, z = a.box[2] + bk;
+            const float kap = a.kappa[c * comp + (size_t)z * plane + (size_t)y * a.nxp + x];
+            const float gk = -ge / (kap * kap);
+            if (a.gbox) a.gbox[o] = gk;
+            if (c < 2) {
+                if (z >= a.k_lo && z <= a.k_hi) {
+                    if (c == 0) sx += gk; else sy += gk;
+                }
+            } else {
+                if (z >= a.k_lo && z < a.k_hi) szi += gk;
+                if (z == a.k_lo - 1 || z == a.k_hi) szf += gk;
+            }
+        }
+    }
+    (void)bsz;
+    if (a.gmap) {
+        // box cell (bi, bj) is component-grid pixel (bi + 1, bj + 1)
+        const int gsz = a.G0 * a.G1;
+        const int pix = (bj + 1) * a.G0 + (bi + 1);
+        a.gmap[pix] = sx;
+        a.gmap[gsz + pix] = sy;
+        a.gmap[2 * gsz + pix] = szi;
+        a.gmap[3 * gsz + pix] = szf;
+    }
+}
+
+// Transpose of the extrusion through the slab: dF/dkappa on the box -> the
+// four z-summed maps (E_x planes, E_y planes, interior E_z, face E_z).
+__global__ void k_zsum(const float *gbox, int x0, int y0, int z0, int bx, int by, int bz,
+                       int k_lo, int k_hi, float *gmap, int G0, int G1)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= bx * by) return;
+    const int bj = i / bx, bi = i - bj * bx;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    for (int bk = 0; bk < bz; ++bk) {
+        const int z = z0 + bk;
+        const size_t o = (size_t)bk * bx * by + i;
+        const size_t cs = (size_t)bx * by * bz;
+        if (z >= k_lo && z <= k_hi) {
+            s0 += gbox[o];
+            s1 += gbox[cs + o];
+        }
+        if (z >= k_lo && z < k_hi) s2 += gbox[2 * cs + o];
+        if (z == k_lo - 1 || z == k_hi) s3 += gbox[2 * cs + o];
+    }
+    const int gsz = G0 * G1, pix = (bj + 1) * G0 + (bi + 1);
+    gmap[pix] = s0;
+    gmap[gsz + pix] = s1;
+    gmap[2 * gsz + pix] = s2;
+    gmap[3 * gsz + pix] = s3;
+    (void)x0; (void)y0;
+}
+
+// ------------------------------------------------------------- chain VJP
+// Eq. (7) partials and the normal-vector partials (written region only).
+__global__ void k_vjp_pointwise(YoChainBufs c)
+{
+    const int gsz = c.G0 * c.G1;
+    const int pix = blockIdx.x * BS + threadIdx.x;
+    if (pix >= gsz) return;
+    const int n = pix / c.G0, m = pix - n * c.G0;
+    const bool w = (n >= 1 && n <= c.nd + 2 && m >= 1 && m <= c.md + 2);
+    float gP[3] = {0, 0, 0}, gQ[3] = {0, 0, 0}, gG[4] = {0, 0, 0, 0};
+    if (w) {
+        for (int comp = 0; comp < 2; ++comp) {
+            const float g = c.gmap[comp * gsz + pix];
+            const float n2 = c.aux[comp * gsz + pix];
+            const float Gx = c.aux[(2 + 2 * comp) * gsz + pix];
+            const float Gy = c.aux[(3 + 2 * comp) * gsz + pix];
+            const float P = c.P[comp * gsz + pix], Q = c.Q[comp * gsz + pix];
+            gP[comp] = g * n2;
+            gQ[comp] = -g * (1.0f - n2) / (Q * Q);
+            const float gn = g * (P - 1.0f / Q);
+            const float D = Gx * Gx + Gy * Gy + c.delta;
+            const float D2 = D * D;
+            if (comp == 0) {
+                gG[0] = gn * 2.0f * Gx * (Gy * Gy + c.delta) / D2;
+                gG[1] = -gn * 2.0f * Gy * Gx * Gx / D2;
+            } else {
+                gG[3] = gn * 2.0f * Gy * (Gx * Gx + c.delta) / D2;
+                gG[2] = -gn * 2.0f * Gx * Gy * Gy / D2;
+            }
+        }
+        const float Qz = c.Q[2 * gsz + pix];
+        gP[2] = 0.5f * c.gmap[3 * gsz + pix];
+        gQ[2] = -c.gmap[2 * gsz + pix] / (Qz * Qz);
+    }
+    for (int k = 0; k < 3; ++k) {
+        c.gPQ[k * gsz + pix] = gP[k];
+        c.gPQ[(3 + k) * gsz + pix] = gQ[k];
+    }
+    for (int k = 0; k < 4; ++k) c.gG[k * gsz + pix] = gG[k];
+}
+
+// Transpose of the clamped Sobel stencils: gather every (pixel, tap) whose
+// clamped source is this pixel.
+__global__ void k_vjp_sobel(YoChainBufs c)
+{
+    const int gsz = c.G0 * c.G1;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= 2 * gsz) return;
+    const int comp = i / gsz, pix = i - comp * gsz;
+    const int nq = pix / c.G0, mq = pix - nq * c.G0;
+    const float *gx = c.gG + (2 * comp) * gsz;
+    const float *gy = c.gG + (2 * comp + 1) * gsz;
+    const float w[3] = {1.0f, 2.0f, 1.0f};
+    float acc = 0.0f;
+    for (int n = nq - 1; n <= nq + 1; ++n) {
+        if (n < 0 || n >= c.G1) continue;
+        for (int m = mq - 1; m <= mq + 1; ++m) {
+            if (m < 0 || m >= c.G0) continue;
+            const float ax = gx[n * c.G0 + m], ay = gy[n * c.G0 + m];
+            for (int dn = -1; dn <= 1; ++dn) {
+                if (clampi(n + dn, 0, c.G1 - 1) != nq) continue;
+                for (int dm = -1; dm <= 1; ++dm) {
+                    if (clampi(m + dm, 0, c.G0 - 1) != mq) continue;
+                    acc = fmaf(w[dn + 1] * (float)dm * 0.125f, ax, acc);
+                    acc = fmaf(w[dm + 1] * (float)dn * 0.125f, ay, acc);
+                }
+            }
+        }
+    }
+    c.gR[i] = acc;
+}
+
+// number of window sub-pixels of pixel m (shift sh) that clamp onto u
+__device__ __forceinline__ int win_count(int m, int sh, int S, int u, int n_hr)
+{
+    int cnt = 0;
+    for (int a = 0; a < S; ++a) cnt += (clampi(S * m + sh + a, 0, n_hr - 1) == u);
+    return cnt;
+}
+
+// Transpose of the box means to the canvas, the density mix and the
+// projection derivative (beta/2)(1 - tanh^2) on the design area.
+__global__ void k_vjp_canvas(YoChainBufs c, float beta)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= c.U * c.V) return;
+    const int v = i / c.U, u = i - v * c.U;
+    const int ud = u - 2 * c.S, vd = v - 2 * c.S;
+    if (ud < 0 || ud >= c.S * c.md || vd < 0 || vd >= c.S * c.nd) return;
+    const int gsz = c.G0 * c.G1;
+    const int half = c.S / 2;
+    const float invS2 = 1.0f / (float)(c.S * c.S);
+    float gi = 0.0f, ge = 0.0f, gr = 0.0f;
+    for (int comp = 0; comp < 3; ++comp) {
+        const int shx = comp == 0 ? half : 0, shy = comp == 1 ? half : 0;
+        const int mc0 = (u - shx) / c.S, nc0 = (v - shy) / c.S;
+        for (int n = nc0 - 1; n <= nc0 + 1; ++n) {
+            if (n < 0 || n >= c.G1) continue;
+            const int cy = win_count(n, shy, c.S, v, c.V);
+            if (!cy) continue;
+            for (int m = mc0 - 1; m <= mc0 + 1; ++m) {
+                if (m < 0 || m >= c.G0) continue;
+                const int cx = win_count(m, shx, c.S, u, c.U);
+                if (!cx) continue;
+                const float wgt = (float)(cx * cy) * invS2;
+                const int pix = n * c.G0 + m;
+                gi = fmaf(wgt, c.gPQ[comp * gsz + pix], gi);
+                ge = fmaf(wgt, c.gPQ[(3 + comp) * gsz + pix], ge);
+                if (comp < 2) gr = fmaf(wgt, c.gR[comp * gsz + pix], gr);
+            }
+        }
+    }
+    const float de = c.eps_core - c.eps_clad;
+    const float eps = fmaf(de, c.rho[i], c.eps_clad);
+    const float grho = fmaf(gi, -de / (eps * eps), fmaf(ge, de, gr));
+    const float t = c.tanh_[vd * (c.S * c.md) + ud];
+    c.gphi[vd * (c.S * c.md) + ud] = grho * 0.5f * beta * (1.0f - t * t);
+}
+
+// Transpose of the separable filter, x then y.  tmp[vd][a] = sum_ud gphi W_x(ud, a)
+__global__ void k_vjp_filter_x(YoChainBufs c)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const int nvd = c.S * c.nd, nud = c.S * c.md;
+    if (i >= nvd * c.mc) return;
+    const int vd = i / c.mc, a = i - vd * c.mc;
+    float acc = 0.0f;
+    for (int ud = c.urange_x[2 * a]; ud <= c.urange_x[2 * a + 1]; ++ud) {
+        const int lo = c.tap_lo_x[ud], nt = c.tap_n_x[ud];
+        float w = 0.0f;
+        for (int t = 0; t < nt; ++t)
+            if (clampi(lo + t, 0, c.mc - 1) == a) w += c.tap_w_x[ud * c.tmax + t];
+        acc = fmaf(w, c.gphi[vd * nud + ud], acc);
+    }
+    c.tmp[i] = acc;
+}
+
+__global__ void k_vjp_filter_y(YoChainBufs c, float *dFdC)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= c.nc * c.mc) return;
+    const int b = i / c.mc, a = i - b * c.mc;
+    float acc = 0.0f;
+    for (int vd = c.urange_y[2 * b]; vd <= c.urange_y[2 * b + 1]; ++vd) {
+        const int lo = c.tap_lo_y[vd], nt = c.tap_n_y[vd];
+        float w = 0.0f;
+        for (int t = 0; t < nt; ++t)
+            if (clampi(lo + t, 0, c.nc - 1) == b) w += c.tap_w_y[vd * c.tmax + t];
+        acc = fmaf(w, c.tmp[vd * c.mc + a], acc);
+    }
+    dFdC[i] = acc;
+}
+
+}  // namespace
+
+hipError_t yo_launch_fill(float *p, size_t n, float v, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    int blocks = nblk(n);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(BS), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_pitch_copy(const float *src, float *dst, int ncomp, int nz, int ny, int nx,
+                                int sp, int dp, hipStream_t s)
+{
+    const size_t n = (size_t)ncomp * nz * ny * nx;
+    if (!n) return hipSuccess;
+    int blocks = nblk(n);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_pitch_copy, dim3(blocks), dim3(BS), 0, s, src, dst, ncomp, nz, ny, nx,
+                       sp, dp);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11,
+                              hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    int blocks = nblk(n);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(BS), 0, s, a, n, g00, g01, g10, g11);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_alpha(const float2 *mon, const float2 *w, int n, float2 *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(BS), 0, s, mon, w, n, out);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_chain_forward(const YoChainBufs &c, const float *C, float beta, float *kappa,
+                                   int nx, int ny, int nz, int nxp, int i0, int j0, int k_lo,
+                                   int k_hi, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_project, dim3(nblk((size_t)c.U * c.V)), dim3(BS), 0, s, c, C, beta);
+    hipLaunchKernelGGL(k_box, dim3(nblk((size_t)3 * c.G0 * c.G1)), dim3(BS), 0, s, c);
+    hipLaunchKernelGGL(k_smooth, dim3(nblk((size_t)(c.md + 2) * (c.nd + 2))), dim3(BS), 0, s, c,
+                       kappa, nx, ny, nz, nxp, i0, j0, k_lo, k_hi);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_grad_assemble(const YoGradArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad, dim3(nblk((size_t)a.box[3] * a.box[4])), dim3(BS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_chain_vjp(const YoChainBufs &c, float beta, float *dFdC, hipStream_t s)
+{
+    const size_t gsz = (size_t)c.G0 * c.G1;
+    hipLaunchKernelGGL(k_vjp_pointwise, dim3(nblk(gsz)), dim3(BS), 0, s, c);
+    hipLaunchKernelGGL(k_vjp_sobel, dim3(nblk(2 * gsz)), dim3(BS), 0, s, c);
+    hipLaunchKernelGGL(k_vjp_canvas, dim3(nblk((size_t)c.U * c.V)), dim3(BS), 0, s, c, beta);
+    hipLaunchKernelGGL(k_vjp_filter_x, dim3(nblk((size_t)c.S * c.nd * c.mc)), dim3(BS), 0, s, c);
+    hipLaunchKernelGGL(k_vjp_filter_y, dim3(nblk((size_t)c.nc * c.mc)), dim3(BS), 0, s, c, dFdC);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_zsum(const float *gbox, const int *box, int k_lo, int k_hi, float *gmap, int G0,
+                          int G1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zsum, dim3(nblk((size_t)box[3] * box[4])), dim3(BS), 0, s, gbox, box[0],
+                       box[1], box[2], box[3], box[4], box[5], k_lo, k_hi, gmap, G0, G1);
+    return hipGetLastError();
+}

@@ -1,0 +1,136 @@
+// Internal device descriptors and kernel entry points of libyeeopt (not part
+// of the public ABI).  Host runtime and kernels share these layouts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define YO_MAX_PORTS 8
+#define YO_MAX_SLOTS 32
+#define YO_TX 62          // owned x-cells per wave (lanes 1..62; lanes 0 and 63 are halo)
+#define YO_WAVES_PER_BLOCK 4
+
+struct YoPlaneD {
+    int axis, index, lo0, lo1, n0, n1;
+};
+
+// One right-hand side: its own field state, absorbing-layer memories, DFT
+// sums, source plane and per-step phase table.
+struct YoRhsD {
+    float *E[2];             // double-buffered [3][nz][ny][nxp]
+    float *H[2];
+    float *psiE[3];          // per axis: [2][slab] (single buffer)
+    float *psiH[2][3];       // [buffer][axis]: [2][slab]
+    float2 *dft_box;         // [3][bz][by][bx]
+    float2 *dft_mon;         // concatenated port planes [2][n1][n0]
+    const float4 *steptab;   // [n_steps]: (ramp cos, ramp sin) at (n+1/2)dt, (cos, sin) at n dt
+    const float2 *src_j;     // [2][n1][n0], nullptr if no source
+    YoPlaneD src;
+    int win_start, win_len;
+    float ginv[4];           // inverse Gram matrix of the steady-state fit
+    int freq;
+    int pad_;
+};
+
+// One plan (one geometry): shared material and geometry description.
+struct YoPlanD {
+    int nx, ny, nz, nxp;
+    float sx, sy, sz, pad0;
+    int plo[3], phi[3];      // PML cells low/high per axis
+    const float *kappa;      // [3][nz][ny][nxp]
+    const float *prof[3];    // per axis [6][n_a]: bE cE kiE bH cH kiH
+    int box[6];              // x0 y0 z0 bx by bz
+    int n_ports;
+    int n_steps;
+    YoPlaneD ports[YO_MAX_PORTS];
+    int mon_off[YO_MAX_PORTS];
+    int *step_ctr;           // device step counter of this plan
+    int n_rhs;
+    int pad1;
+    const YoRhsD *rhs;       // [n_rhs]
+};
+
+// Tiles are packed as ty | tx << 11 | tz << 22 (one tile = one wave's work:
+// 62 x-cells, TY rows, kc z-planes).
+#define YO_TILE(tz, tx, ty) ((ty) | ((tx) << 11) | ((tz) << 22))
+
+struct YoSlot {
+    const YoPlanD *plan;
+    const int *tiles;        // tile list of this launch's class (interior or CPML)
+    int rhs0, nrhs;
+    int ntile, kc;
+};
+
+struct YoStepArgs {
+    int n_slots;
+    int k_offset;            // launch index inside the chunk; step = counter + k_offset
+    int total_waves;
+    int pad_;
+    int prefix[YO_MAX_SLOTS + 1];
+    YoSlot slot[YO_MAX_SLOTS];
+};
+
+struct YoCtrArgs {
+    int n;
+    int add;
+    int *ctr[YO_MAX_SLOTS];
+};
+
+// Parametrization buffers of one plan.
+struct YoChainBufs {
+    int md, nd, mc, nc, S, U, V, G0, G1;   // G0 = md+4 (x), G1 = nd+4 (y)
+    int tmax;                               // filter taps per sub-pixel (max)
+    float eps_core, eps_clad, delta;
+    // filter tables
+    int *tap_lo_x, *tap_n_x, *tap_lo_y, *tap_n_y;   // [S md], [S nd]
+    float *tap_w_x, *tap_w_y;                        // [S md][tmax], [S nd][tmax]
+    int *urange_x, *urange_y;                        // per control: [2] first/last sub-pixel
+    // forward state
+    float *mask;      // [V][U]
+    float *rho;       // [V][U]
+    float *tanh_;     // [S nd][S md]
+    float *P, *Q, *R; // [3][G1][G0]
+    float *aux;       // [6][G1][G0]: n2x n2y Gx_x Gy_x Gx_y Gy_y
+    // backward
+    float *gmap;      // [4][G1][G0]: gx gy gz_in gz_face
+    float *gPQ;       // [6][G1][G0]: gP(x,y,z) gQ(x,y,z)
+    float *gG;        // [4][G1][G0]: gGx_x gGy_x gGx_y gGy_y
+    float *gR;        // [2][G1][G0]
+    float *gphi;      // [S nd][S md]
+    float *tmp;       // [S nd][mc]
+};
+
+// ---- kernel launchers (yo_kernels.hip) ----
+hipError_t yo_launch_step(int ty, int pml, const YoStepArgs &args, int blocks, hipStream_t s);
+hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);
+hipError_t yo_launch_fill(float *p, size_t n, float v, hipStream_t s);
+hipError_t yo_launch_pitch_copy(const float *src, float *dst, int ncomp, int nz, int ny, int nx,
+                                int src_pitch, int dst_pitch, hipStream_t s);
+hipError_t yo_launch_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11,
+                              hipStream_t s);
+hipError_t yo_launch_alpha(const float2 *mon_dft, const float2 *weights, int n, float2 *out,
+                           hipStream_t s);
+hipError_t yo_launch_chain_forward(const YoChainBufs &c, const float *C, float beta,
+                                   float *kappa, int nx, int ny, int nz, int nxp, int i0, int j0,
+                                   int k_lo, int k_hi, hipStream_t s);
+#define YO_MAX_GF 32
+#define YO_MAX_GA 64
+#define YO_MAX_FREQ 16
+struct YoGradArgs {
+    const float2 *EF[YO_MAX_GF];   // forward box phasors, index f*n_src + s
+    const float2 *EA[YO_MAX_GA];   // adjoint box phasors, index f*n_ports + p
+    float sinth[YO_MAX_FREQ];      // sin(w dt / 2) per frequency
+    const float2 *coef;            // [n_src][n_ports][n_freq]
+    const float *kappa;            // [3][nz][ny][nxp]
+    float *gbox;                   // optional [3][bz][by][bx] dF/dkappa
+    float *gmap;                   // optional [4][G1][G0] z-summed maps
+    int n_src, n_ports, n_freq;
+    int nxp, ny, nz;
+    int box[6];
+    int k_lo, k_hi, G0, G1;
+};
+hipError_t yo_launch_grad_assemble(const YoGradArgs &a, hipStream_t s);
+hipError_t yo_launch_chain_vjp(const YoChainBufs &c, float beta, float *dFdC, hipStream_t s);
+hipError_t yo_launch_zsum(const float *gbox, const int *box, int k_lo, int k_hi, float *gmap, int G0,
+                          int G1, hipStream_t s);

@@ -1,0 +1,1106 @@
+// Host runtime of libyeeopt: plan validation, workspace layout, FP64
+// coefficient tables (CPML profiles, per-step source and DFT phases, the
+// steady-state fit, filter taps), mode-to-source/monitor conversion
+// (Appendix A), tile tables, HIP-graph capture of step chunks, and the C ABI.
+// The library never allocates device memory: every device buffer lives in a
+// caller-owned workspace.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "yeeopt.h"
+#include "yo_internal.h"
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+thread_local std::string g_err;
+
+yo_status fail(yo_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(YO_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+struct Layout {
+    Region fields, kappa, psi, dft_box, dft_mon, src_j, port_w, steptab, prof, desc_plan,
+        desc_rhs, ctr, tiles, chain_f, chain_i;
+    size_t total = 0;
+    size_t add(Region &r, size_t bytes)
+    {
+        r.off = total;
+        r.bytes = bytes;
+        total += align256(bytes);
+        return r.off;
+    }
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+std::mutex g_graph_mu;
+std::map<std::string, GraphEntry> g_graphs;
+int g_next_plan_id = 1;
+
+}  // namespace
+
+struct yo_plan {
+    int id = 0;
+    int generation = 0;
+    yo_grid grid{};
+    yo_design des{};
+    int n_steps = 0, n_freq = 0, n_src = 0, n_ports = 0, n_rhs = 0, n_fwd = 0;
+    std::vector<yo_freq> freqs;
+    std::vector<yo_plane> src_planes, port_planes;
+    double dt = 0, sx = 0, sy = 0, sz = 0;
+    int nxp = 0;
+    int plo[3] = {0, 0, 0}, phi[3] = {0, 0, 0};
+    size_t cells_p = 0;          // padded cells per component
+    size_t psi_per_rhs = 0;      // floats
+    size_t psi_axis_off[3] = {0, 0, 0}, psi_axis_n[3] = {0, 0, 0};   // per RHS, per axis slab size (floats per comp)
+    size_t bsz = 0;              // box cells
+    int box[6] = {0, 0, 0, 0, 0, 0};
+    size_t mon_total = 0;        // complex entries per RHS
+    std::vector<size_t> mon_off, src_off, port_off;
+    size_t src_total = 0, port_total = 0;
+    // chain sizes
+    int S = 0, U = 0, V = 0, G0 = 0, G1 = 0, tmax = 0;
+    size_t tiles_cap = 0;
+    Layout L;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    // host mirrors
+    YoPlanD hplan{};
+    std::vector<YoRhsD> hrhs;
+    YoChainBufs chain{};
+    std::vector<int> tap_lo_x, tap_n_x, tap_lo_y, tap_n_y, urange_x, urange_y;
+    std::vector<float> tap_w_x, tap_w_y;
+    std::vector<float4> steptab;
+    std::vector<float> prof;
+    std::vector<float2> src_j_host, port_w_host;
+    std::vector<int> tiles_host;
+    std::vector<float> ginv;     // [n_freq][4]
+    std::vector<double> omega_dt;
+    std::vector<char> src_set, port_set;
+    int ty = 4, kc = 16;
+    int n_tile_int = 0, n_tile_pml = 0;
+    bool bg_set = false, design_set = false;
+    double beta = 0;
+    int steps_done = 0;
+    int active = 0;              // which right-hand sides the last reset selected
+    bool finalized = false;
+    hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+template <class T>
+T *wsp(yo_plan *p, const Region &r, size_t extra_bytes = 0)
+{
+    return reinterpret_cast<T *>(p->ws + r.off + extra_bytes);
+}
+
+bool plane_ok(const yo_plan *p, const yo_plane &pl)
+{
+    const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    if (pl.axis < 0 || pl.axis > 2 || pl.n0 <= 0 || pl.n1 <= 0) return false;
+    const int c0 = pl.axis == 0 ? 1 : 0;
+    const int c1 = pl.axis == 2 ? 1 : 2;
+    auto inside = [&](int a, int lo, int cnt) {
+        return lo >= p->plo[a] && lo + cnt <= n[a] - p->phi[a];
+    };
+    return inside(pl.axis, pl.index, 1) && inside(c0, pl.lo0, pl.n0) && inside(c1, pl.lo1, pl.n1);
+}
+
+// depth into the absorbing layer at coordinate u (cells)
+double pml_depth(double u, int n, int lo, int hi)
+{
+    if (lo > 0 && u < lo) return (lo - u) / lo;
+    if (hi > 0 && u > n - hi) return (u - (n - hi)) / hi;
+    return 0.0;
+}
+
+void build_profiles(yo_plan *p)
+{
+    const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    const double s[3] = {p->sx, p->sy, p->sz};
+    size_t tot = 6 * (size_t)(n[0] + n[1] + n[2]);
+    p->prof.assign(tot, 0.0f);
+    size_t off = 0;
+    const double m = p->grid.pml_m;
+    for (int a = 0; a < 3; ++a) {
+        for (int which = 0; which < 2; ++which) {
+            const double shift = which ? 0.5 : 0.0;
+            const double smax = p->grid.pml_sigma_scale * 0.8 * (m + 1.0) * s[a];
+            for (int u = 0; u < n[a]; ++u) {
+                const double xi = pml_depth(u + shift, n[a], p->plo[a], p->phi[a]);
+                double b = 1.0, c = 0.0, ki = 1.0;
+                if (xi > 0.0) {
+                    const double gr = std::pow(xi, m);
+                    const double sig = smax * gr;
+                    const double kp = 1.0 + (p->grid.pml_kappa_max - 1.0) * gr;
+                    const double aa = p->grid.pml_a_max * (1.0 - xi);
+                    b = std::exp(-(sig / kp + aa));
+                    c = sig > 0.0 ? sig * (b - 1.0) / (kp * (sig + kp * aa)) : 0.0;
+                    ki = 1.0 / kp;
+                }
+                p->prof[off + (3 * which + 0) * n[a] + u] = (float)b;
+                p->prof[off + (3 * which + 1) * n[a] + u] = (float)c;
+                p->prof[off + (3 * which + 2) * n[a] + u] = (float)ki;
+            }
+        }
+        off += 6 * (size_t)n[a];
+    }
+}
+
+void build_steptab(yo_plan *p)
+{
+    p->steptab.resize((size_t)p->n_freq * p->n_steps);
+    p->ginv.assign(4 * (size_t)p->n_freq, 0.0f);
+    for (int f = 0; f < p->n_freq; ++f) {
+        const double w = p->omega_dt[f];
+        const double T = p->freqs[f].ramp_steps;
+        for (int n = 0; n < p->n_steps; ++n) {
+            const double t = n + 0.5;
+            double r = 1.0;
+            if (T > 0.0 && t < T) r = 0.5 * (1.0 - std::cos(M_PI * t / T));
+            float4 v;
+            v.x = (float)(r * std::cos(w * t));
+            v.y = (float)(r * std::sin(w * t));
+            v.z = (float)std::cos(w * n);
+            v.w = (float)std::sin(w * n);
+            p->steptab[(size_t)f * p->n_steps + n] = v;
+        }
+        double g00 = 0, g01 = 0, g11 = 0;
+        for (int n = p->freqs[f].win_start; n < p->freqs[f].win_start + p->freqs[f].win_len; ++n) {
+            const double c = std::cos(w * n), s = std::sin(w * n);
+            g00 += c * c;
+            g01 += c * s;
+            g11 += s * s;
+        }
+        const double det = g00 * g11 - g01 * g01;
+        p->ginv[4 * f + 0] = (float)(g11 / det);
+        p->ginv[4 * f + 1] = (float)(-g01 / det);
+        p->ginv[4 * f + 2] = (float)(-g01 / det);
+        p->ginv[4 * f + 3] = (float)(g00 / det);
+    }
+}
+
+// Gaussian-basis taps of one axis: sub-pixel u of the design is centred at
+// x = ((u + 1/2)/S) (n_ctl/n_px) - 1/2 control pixels; taps are the controls
+// within distance r, weights exp(-d^2/(2 sigma^2)), sigma = r/2, normalised.
+void build_taps(int S, int n_px, int n_ctl, double r, int tmax, std::vector<int> &lo,
+                std::vector<int> &cnt, std::vector<float> &w, std::vector<int> &range)
+{
+    const int n = S * n_px;
+    lo.assign(n, 0);
+    cnt.assign(n, 0);
+    w.assign((size_t)n * tmax, 0.0f);
+    range.assign(2 * (size_t)n_ctl, 0);
+    for (int a = 0; a < n_ctl; ++a) {
+        range[2 * a] = n;
+        range[2 * a + 1] = -1;
+    }
+    const double sigma = r / 2.0;
+    for (int u = 0; u < n; ++u) {
+        const double x = ((u + 0.5) / S) * (double)n_ctl / n_px - 0.5;
+        const int l = (int)std::ceil(x - r), h = (int)std::floor(x + r);
+        double z = 0.0;
+        std::vector<double> g;
+        for (int i = l; i <= h; ++i) {
+            const double d = x - i;
+            g.push_back(std::exp(-d * d / (2.0 * sigma * sigma)));
+            z += g.back();
+        }
+        lo[u] = l;
+        cnt[u] = h - l + 1;
+        for (int t = 0; t <= h - l; ++t) {
+            w[(size_t)u * tmax + t] = (float)(g[t] / z);
+            const int a = std::min(std::max(l + t, 0), n_ctl - 1);
+            range[2 * a] = std::min(range[2 * a], u);
+            range[2 * a + 1] = std::max(range[2 * a + 1], u);
+        }
+    }
+}
+
+void build_tiles(yo_plan *p)
+{
+    const int ntx = (p->grid.nx + YO_TX - 1) / YO_TX;
+    const int nty = (p->grid.ny + p->ty - 1) / p->ty;
+    const int ntz = (p->grid.nz + p->kc - 1) / p->kc;
+    std::vector<int> in, pm;
+    for (int tz = 0; tz < ntz; ++tz)
+        for (int tx = 0; tx < ntx; ++tx)
+            for (int ty = 0; ty < nty; ++ty) {
+                const int xa = tx * YO_TX - 1, xb = tx * YO_TX + YO_TX;
+                const int ja = ty * p->ty - 1, jb = ty * p->ty + p->ty;
+                const int ka = tz * p->kc - 1, kb = std::min(tz * p->kc + p->kc, p->grid.nz);
+                const bool pml = (xa < p->plo[0]) || (xb >= p->grid.nx - p->phi[0]) ||
+                                 (ja < p->plo[1]) || (jb >= p->grid.ny - p->phi[1]) ||
+                                 (ka < p->plo[2]) || (kb >= p->grid.nz - p->phi[2]);
+                (pml ? pm : in).push_back(YO_TILE(tz, tx, ty));
+            }
+    p->n_tile_int = (int)in.size();
+    p->n_tile_pml = (int)pm.size();
+    p->tiles_host = in;
+    p->tiles_host.insert(p->tiles_host.end(), pm.begin(), pm.end());
+}
+
+size_t tiles_capacity(const yo_grid &g, int ty_min, int kc_min)
+{
+    const size_t ntx = (g.nx + YO_TX - 1) / YO_TX;
+    const size_t nty = (g.ny + ty_min - 1) / ty_min;
+    const size_t ntz = (g.nz + kc_min - 1) / kc_min;
+    return ntx * nty * ntz;
+}
+
+yo_status upload(yo_plan *p, const Region &r, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes > r.bytes) return fail(YO_EWORKSPACE, "internal: region too small");
+    if (!bytes) return YO_OK;
+    HIPCHK(hipMemcpyAsync(p->ws + r.off, src, bytes, hipMemcpyHostToDevice, s));
+    return YO_OK;
+}
+
+yo_status upload_desc(yo_plan *p, hipStream_t s)
+{
+    yo_status st = upload(p, p->L.desc_plan, &p->hplan, sizeof(YoPlanD), s);
+    if (st) return st;
+    return upload(p, p->L.desc_rhs, p->hrhs.data(), sizeof(YoRhsD) * p->hrhs.size(), s);
+}
+
+void set_rhs_range(const yo_plan *p, int which, int &r0, int &r1)
+{
+    r0 = (which & YO_FORWARD) ? 0 : p->n_fwd;
+    r1 = (which & YO_ADJOINT) ? p->n_rhs : p->n_fwd;
+}
+
+size_t fields_per_rhs(const yo_plan *p) { return 12 * p->cells_p; }   // 2 buffers x (E, H) x 3
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *yo_last_error(void) { return g_err.c_str(); }
+const char *yo_version(void) { return "yeeopt 0.1 (gfx950)"; }
+
+yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps, int n_freq,
+                         const yo_freq *freqs, int n_src, const yo_plane *src_planes,
+                         int n_ports, const yo_plane *port_planes, yo_plan **out)
+{
+    if (!grid || !des || !out || (n_freq > 0 && !freqs)) return fail(YO_EINVAL, "null argument");
+    *out = nullptr;
+    const yo_grid &g = *grid;
+    if (g.nx < 4 || g.ny < 4 || g.nz < 4) return fail(YO_EINVAL, "grid must be at least 4^3");
+    if ((size_t)3 * g.nz * g.ny * (size_t)(g.nx + 64) >= (1ull << 31))
+        return fail(YO_EUNSUPPORTED, "grid too large for one right-hand side");
+    if (!(g.dx > 0 && g.dy > 0 && g.dz > 0 && g.courant > 0)) return fail(YO_EINVAL, "bad spacing");
+    for (int f = 0; f < 6; ++f)
+        if (g.npml[f] < 0) return fail(YO_EINVAL, "negative npml");
+    if (g.npml[0] + g.npml[1] >= g.nx || g.npml[2] + g.npml[3] >= g.ny || g.npml[4] + g.npml[5] >= g.nz)
+        return fail(YO_EINVAL, "CPML fills the grid");
+    if (g.nx >= 2048 * YO_TX || g.ny >= 2048 * 4 || g.nz >= 512 * 4)
+        return fail(YO_EUNSUPPORTED, "grid too large for the tile encoding");
+    const double dmin = std::min(g.dx, std::min(g.dy, g.dz));
+    const double cdt = g.courant * dmin;
+    const double lim = cdt * std::sqrt(1 / (g.dx * g.dx) + 1 / (g.dy * g.dy) + 1 / (g.dz * g.dz));
+    if (!(lim < 1.0)) return fail(YO_EUNSTABLE, "Courant number %.4f above the limit (c dt |1/d| = %.4f)", g.courant, lim);
+    if (n_steps < 1) return fail(YO_EINVAL, "n_steps < 1");
+    if (n_freq < 1 || n_freq > YO_MAX_FREQ) return fail(n_freq < 1 ? YO_EINVAL : YO_EUNSUPPORTED, "n_freq out of range");
+    if (n_src < 0 || n_ports < 0 || n_ports > YO_MAX_PORTS) return fail(YO_EUNSUPPORTED, "too many ports");
+    if (n_src * n_freq > YO_MAX_GF || n_ports * n_freq > YO_MAX_GA)
+        return fail(YO_EUNSUPPORTED, "too many right-hand sides");
+    if (n_src + n_ports < 1) return fail(YO_EINVAL, "no sources and no ports");
+    const yo_design &d = *des;
+    if (d.supersample < 2 || (d.supersample & 1)) return fail(YO_EINVAL, "supersample must be even and >= 2");
+    if (d.md < 1 || d.nd < 1 || d.mc < 1 || d.nc < 1 || !(d.filter_r > 0))
+        return fail(YO_EINVAL, "bad design sizes");
+    if (!(d.eps_core > 0 && d.eps_clad > 0 && d.sobel_delta > 0)) return fail(YO_EINVAL, "bad materials");
+    if (d.k_hi < d.k_lo) return fail(YO_EINVAL, "empty slab");
+    if (d.i0 - 1 < g.npml[0] || d.i0 + d.md + 1 > g.nx - g.npml[1] || d.j0 - 1 < g.npml[2] ||
+        d.j0 + d.nd + 1 > g.ny - g.npml[3] || d.k_lo - 1 < g.npml[4] || d.k_hi + 1 > g.nz - g.npml[5])
+        return fail(YO_EINVAL, "design region (plus its one-cell ring) must lie outside the CPML");
+    for (int f = 0; f < n_freq; ++f) {
+        const yo_freq &q = freqs[f];
+        if (!(q.omega > 0) || q.ramp_steps < 0) return fail(YO_EINVAL, "bad frequency %d", f);
+        if (q.win_len < 2 || q.win_start < 0 || q.win_start + q.win_len > n_steps)
+            return fail(YO_EINVAL, "window of frequency %d outside [0, n_steps)", f);
+    }
+
+    yo_plan *p = new yo_plan();
+    p->id = g_next_plan_id++;
+    p->grid = g;
+    p->des = d;
+    p->n_steps = n_steps;
+    p->n_freq = n_freq;
+    p->n_src = n_src;
+    p->n_ports = n_ports;
+    p->n_fwd = n_src * n_freq;
+    p->n_rhs = (n_src + n_ports) * n_freq;
+    p->freqs.assign(freqs, freqs + n_freq);
+    p->dt = cdt / kC0;
+    p->sx = cdt / g.dx;
+    p->sy = cdt / g.dy;
+    p->sz = cdt / g.dz;
+    for (int a = 0; a < 3; ++a) {
+        p->plo[a] = g.npml[2 * a];
+        p->phi[a] = g.npml[2 * a + 1];
+    }
+    p->omega_dt.resize(n_freq);
+    for (int f = 0; f < n_freq; ++f) p->omega_dt[f] = freqs[f].omega * p->dt;
+    for (int s = 0; s < n_src; ++s) {
+        if (!src_planes || !plane_ok(p, src_planes[s])) {
+            delete p;
+            return fail(YO_EINVAL, "source plane %d outside the grid interior", s);
+        }
+        p->src_planes.push_back(src_planes[s]);
+    }
+    for (int q = 0; q < n_ports; ++q) {
+        if (!port_planes || !plane_ok(p, port_planes[q])) {
+            delete p;
+            return fail(YO_EINVAL, "port plane %d outside the grid interior", q);
+        }
+        p->port_planes.push_back(port_planes[q]);
+    }
+    p->src_set.assign(n_src, 0);
+    p->port_set.assign(n_ports, 0);
+
+    p->nxp = (g.nx + 31) & ~31;
+    p->cells_p = (size_t)g.nz * g.ny * p->nxp;
+    // CPML slabs (per right-hand side): per axis, E 2 comps + H 2 buffers x 2 comps
+    const size_t W[3] = {(size_t)p->plo[0] + p->phi[0], (size_t)p->plo[1] + p->phi[1],
+                         (size_t)p->plo[2] + p->phi[2]};
+    const size_t slab[3] = {(size_t)g.nz * g.ny * W[0], (size_t)g.nz * W[1] * p->nxp,
+                            W[2] * g.ny * p->nxp};
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        p->psi_axis_off[a] = off;
+        p->psi_axis_n[a] = slab[a];
+        off += 6 * slab[a];
+    }
+    p->psi_per_rhs = off;
+    p->box[0] = d.i0 - 1;
+    p->box[1] = d.j0 - 1;
+    p->box[2] = d.k_lo - 1;
+    p->box[3] = d.md + 2;
+    p->box[4] = d.nd + 2;
+    p->box[5] = d.k_hi - d.k_lo + 3;
+    p->bsz = (size_t)p->box[3] * p->box[4] * p->box[5];
+    for (auto &pl : p->port_planes) {
+        p->mon_off.push_back(p->mon_total);
+        p->mon_total += 2 * (size_t)pl.n0 * pl.n1;
+    }
+    for (auto &pl : p->src_planes) {
+        p->src_off.push_back(p->src_total);
+        p->src_total += 2 * (size_t)pl.n0 * pl.n1;
+    }
+    for (auto &pl : p->port_planes) {
+        p->port_off.push_back(p->port_total);
+        p->port_total += 2 * (size_t)pl.n0 * pl.n1;
+    }
+    p->S = d.supersample;
+    p->U = p->S * (d.md + 4);
+    p->V = p->S * (d.nd + 4);
+    p->G0 = d.md + 4;
+    p->G1 = d.nd + 4;
+    p->tmax = 2 * (int)std::ceil(d.filter_r) + 2;
+    p->tiles_cap = tiles_capacity(g, 4, 4);
+
+    Layout &L = p->L;
+    L.add(L.fields, sizeof(float) * fields_per_rhs(p) * p->n_rhs);
+    L.add(L.kappa, sizeof(float) * 3 * p->cells_p);
+    L.add(L.psi, sizeof(float) * p->psi_per_rhs * p->n_rhs);
+    L.add(L.dft_box, sizeof(float2) * 3 * p->bsz * p->n_rhs);
+    L.add(L.dft_mon, sizeof(float2) * std::max<size_t>(p->mon_total, 1) * p->n_rhs);
+    L.add(L.src_j, sizeof(float2) * std::max<size_t>(p->src_total, 1));
+    L.add(L.port_w, sizeof(float2) * std::max<size_t>(p->port_total, 1));
+    L.add(L.steptab, sizeof(float4) * (size_t)n_freq * n_steps);
+    L.add(L.prof, sizeof(float) * 6 * (size_t)(g.nx + g.ny + g.nz));
+    L.add(L.desc_plan, sizeof(YoPlanD));
+    L.add(L.desc_rhs, sizeof(YoRhsD) * p->n_rhs);
+    L.add(L.ctr, 256);
+    L.add(L.tiles, sizeof(int) * p->tiles_cap);
+    const size_t G = (size_t)p->G0 * p->G1;
+    const size_t UV = (size_t)p->U * p->V;
+    const size_t DD = (size_t)(p->S * d.md) * (p->S * d.nd);
+    const size_t nf = 2 * UV + DD /*tanh*/ + 9 * G + 6 * G + 4 * G + 6 * G + 4 * G + 2 * G + DD /*gphi*/ +
+                      (size_t)(p->S * d.nd) * d.mc /*tmp*/ + (size_t)p->tmax * p->S * (d.md + d.nd);
+    L.add(L.chain_f, sizeof(float) * nf + 64 * 16);
+    const size_t ni = 2 * (size_t)p->S * (d.md + d.nd) + 2 * (size_t)(d.mc + d.nc);
+    L.add(L.chain_i, sizeof(int) * ni + 64 * 8);
+
+    build_profiles(p);
+    build_steptab(p);
+    build_taps(p->S, d.md, d.mc, d.filter_r, p->tmax, p->tap_lo_x, p->tap_n_x, p->tap_w_x, p->urange_x);
+    build_taps(p->S, d.nd, d.nc, d.filter_r, p->tmax, p->tap_lo_y, p->tap_n_y, p->tap_w_y, p->urange_y);
+    for (int v : p->tap_n_x)
+        if (v > p->tmax) { delete p; return fail(YO_EINVAL, "internal: filter taps"); }
+    for (int v : p->tap_n_y)
+        if (v > p->tmax) { delete p; return fail(YO_EINVAL, "internal: filter taps"); }
+    build_tiles(p);
+    *out = p;
+    return YO_OK;
+}
+
+void yo_plan_destroy(yo_plan *p)
+{
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        const std::string tag = "#" + std::to_string(p->id) + ":";
+        for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+            if (it->first.find(tag) != std::string::npos) {
+                if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+                if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+                it = g_graphs.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    delete p;
+}
+
+yo_status yo_workspace_bytes(const yo_plan *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(YO_EINVAL, "null argument");
+    *bytes = p->L.total;
+    return YO_OK;
+}
+
+yo_status yo_rhs_count(const yo_plan *p, int *n)
+{
+    if (!p || !n) return fail(YO_EINVAL, "null argument");
+    *n = p->n_rhs;
+    return YO_OK;
+}
+
+yo_status yo_steps_done(const yo_plan *p, int *steps)
+{
+    if (!p || !steps) return fail(YO_EINVAL, "null argument");
+    *steps = p->steps_done;
+    return YO_OK;
+}
+
+static yo_status rebuild_descriptors(yo_plan *p)
+{
+    const yo_grid &g = p->grid;
+    YoPlanD &P = p->hplan;
+    memset(&P, 0, sizeof P);
+    P.nx = g.nx; P.ny = g.ny; P.nz = g.nz; P.nxp = p->nxp;
+    P.sx = (float)p->sx; P.sy = (float)p->sy; P.sz = (float)p->sz;
+    for (int a = 0; a < 3; ++a) { P.plo[a] = p->plo[a]; P.phi[a] = p->phi[a]; }
+    P.kappa = wsp<float>(p, p->L.kappa);
+    float *prof = wsp<float>(p, p->L.prof);
+    P.prof[0] = prof;
+    P.prof[1] = prof + 6 * (size_t)g.nx;
+    P.prof[2] = prof + 6 * (size_t)(g.nx + g.ny);
+    for (int i = 0; i < 6; ++i) P.box[i] = p->box[i];
+    P.n_ports = p->n_ports;
+    P.n_steps = p->n_steps;
+    for (int q = 0; q < p->n_ports; ++q) {
+        const yo_plane &pl = p->port_planes[q];
+        P.ports[q] = YoPlaneD{pl.axis, pl.index, pl.lo0, pl.lo1, pl.n0, pl.n1};
+        P.mon_off[q] = (int)p->mon_off[q];
+    }
+    P.step_ctr = wsp<int>(p, p->L.ctr);
+    P.n_rhs = p->n_rhs;
+    P.rhs = wsp<YoRhsD>(p, p->L.desc_rhs);
+
+    p->hrhs.assign(p->n_rhs, YoRhsD{});
+    float *fields = wsp<float>(p, p->L.fields);
+    float *psi = wsp<float>(p, p->L.psi);
+    float2 *dbox = wsp<float2>(p, p->L.dft_box);
+    float2 *dmon = wsp<float2>(p, p->L.dft_mon);
+    const float2 *srcj = wsp<float2>(p, p->L.src_j);
+    const float2 *portw = wsp<float2>(p, p->L.port_w);
+    const float4 *stab = wsp<float4>(p, p->L.steptab);
+    for (int r = 0; r < p->n_rhs; ++r) {
+        YoRhsD &R = p->hrhs[r];
+        float *f = fields + fields_per_rhs(p) * r;
+        R.E[0] = f;
+        R.E[1] = f + 3 * p->cells_p;
+        R.H[0] = f + 6 * p->cells_p;
+        R.H[1] = f + 9 * p->cells_p;
+        float *ps = psi + p->psi_per_rhs * r;
+        for (int a = 0; a < 3; ++a) {
+            float *base = ps + p->psi_axis_off[a];
+            const size_t n = p->psi_axis_n[a];
+            R.psiE[a] = n ? base : nullptr;
+            R.psiH[0][a] = n ? base + 2 * n : nullptr;
+            R.psiH[1][a] = n ? base + 4 * n : nullptr;
+        }
+        R.dft_box = dbox + 3 * p->bsz * r;
+        R.dft_mon = dmon + std::max<size_t>(p->mon_total, 1) * r;
+        int f_idx, srcp;
+        const float2 *jp;
+        YoPlaneD pl;
+        if (r < p->n_fwd) {
+            f_idx = r / std::max(p->n_src, 1);
+            srcp = r % std::max(p->n_src, 1);
+            const yo_plane &q = p->src_planes[srcp];
+            pl = YoPlaneD{q.axis, q.index, q.lo0, q.lo1, q.n0, q.n1};
+            jp = p->src_set[srcp] ? srcj + p->src_off[srcp] : nullptr;
+        } else {
+            const int ra = r - p->n_fwd;
+            f_idx = ra / p->n_ports;
+            srcp = ra % p->n_ports;
+            const yo_plane &q = p->port_planes[srcp];
+            pl = YoPlaneD{q.axis, q.index, q.lo0, q.lo1, q.n0, q.n1};
+            jp = p->port_set[srcp] ? portw + p->port_off[srcp] : nullptr;
+        }
+        R.steptab = stab + (size_t)f_idx * p->n_steps;
+        R.src_j = jp;
+        R.src = pl;
+        R.win_start = p->freqs[f_idx].win_start;
+        R.win_len = p->freqs[f_idx].win_len;
+        for (int i = 0; i < 4; ++i) R.ginv[i] = p->ginv[4 * f_idx + i];
+        R.freq = f_idx;
+    }
+    return YO_OK;
+}
+
+static void set_chain_ptrs(yo_plan *p)
+{
+    YoChainBufs &c = p->chain;
+    const yo_design &d = p->des;
+    c.md = d.md; c.nd = d.nd; c.mc = d.mc; c.nc = d.nc; c.S = p->S; c.U = p->U; c.V = p->V;
+    c.G0 = p->G0; c.G1 = p->G1; c.tmax = p->tmax;
+    c.eps_core = (float)d.eps_core; c.eps_clad = (float)d.eps_clad; c.delta = (float)d.sobel_delta;
+    const size_t G = (size_t)p->G0 * p->G1;
+    const size_t UV = (size_t)p->U * p->V;
+    const size_t DD = (size_t)(p->S * d.md) * (p->S * d.nd);
+    float *f = wsp<float>(p, p->L.chain_f);
+    auto take = [&](size_t n) {
+        float *r = f;
+        f += (n + 63) & ~(size_t)63;
+        return r;
+    };
+    c.mask = take(UV);
+    c.rho = take(UV);
+    c.tanh_ = take(DD);
+    c.P = take(3 * G);
+    c.Q = take(3 * G);
+    c.R = take(3 * G);
+    c.aux = take(6 * G);
+    c.gmap = take(4 * G);
+    c.gPQ = take(6 * G);
+    c.gG = take(4 * G);
+    c.gR = take(2 * G);
+    c.gphi = take(DD);
+    c.tmp = take((size_t)(p->S * d.nd) * d.mc);
+    c.tap_w_x = take((size_t)p->tmax * p->S * d.md);
+    c.tap_w_y = take((size_t)p->tmax * p->S * d.nd);
+    int *ip = wsp<int>(p, p->L.chain_i);
+    auto takei = [&](size_t n) {
+        int *r = ip;
+        ip += (n + 63) & ~(size_t)63;
+        return r;
+    };
+    c.tap_lo_x = takei(p->S * d.md);
+    c.tap_n_x = takei(p->S * d.md);
+    c.tap_lo_y = takei(p->S * d.nd);
+    c.tap_n_y = takei(p->S * d.nd);
+    c.urange_x = takei(2 * d.mc);
+    c.urange_y = takei(2 * d.nc);
+}
+
+yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream stream)
+{
+    if (!p || !dev) return fail(YO_EINVAL, "null argument");
+    if (((uintptr_t)dev) & 255) return fail(YO_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < p->L.total)
+        return fail(YO_EWORKSPACE, "workspace of %zu bytes, %zu needed", bytes, p->L.total);
+    hipStream_t s = (hipStream_t)stream;
+    p->ws = (char *)dev;
+    p->ws_bytes = bytes;
+    p->generation++;
+    rebuild_descriptors(p);
+    set_chain_ptrs(p);
+    yo_status st;
+    // a fresh workspace holds garbage: clear the state and table regions first
+    HIPCHK(yo_launch_fill((float *)p->ws, p->L.total / sizeof(float), 0.0f, s));
+    if ((st = upload(p, p->L.prof, p->prof.data(), p->prof.size() * sizeof(float), s))) return st;
+    if ((st = upload(p, p->L.steptab, p->steptab.data(), p->steptab.size() * sizeof(float4), s))) return st;
+    if ((st = upload(p, p->L.tiles, p->tiles_host.data(), p->tiles_host.size() * sizeof(int), s))) return st;
+    const YoChainBufs &c = p->chain;
+    HIPCHK(hipMemcpyAsync(c.tap_lo_x, p->tap_lo_x.data(), p->tap_lo_x.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.tap_n_x, p->tap_n_x.data(), p->tap_n_x.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.tap_lo_y, p->tap_lo_y.data(), p->tap_lo_y.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.tap_n_y, p->tap_n_y.data(), p->tap_n_y.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.urange_x, p->urange_x.data(), p->urange_x.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.urange_y, p->urange_y.data(), p->urange_y.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.tap_w_x, p->tap_w_x.data(), p->tap_w_x.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.tap_w_y, p->tap_w_y.data(), p->tap_w_y.size() * 4, hipMemcpyHostToDevice, s));
+    if ((st = upload_desc(p, s))) return st;
+    // copies from pageable host memory are staged; make them complete before
+    // the host vectors can change
+    HIPCHK(hipStreamSynchronize(s));
+    p->bg_set = false;
+    p->design_set = false;
+    p->steps_done = 0;
+    p->finalized = false;
+    return YO_OK;
+}
+
+yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (rows != 4 && rows != 8) return fail(YO_EINVAL, "rows must be 4 or 8");
+    if (zchunk < 4) return fail(YO_EINVAL, "zchunk must be >= 4");
+    p->ty = rows;
+    p->kc = zchunk;
+    build_tiles(p);
+    if (p->tiles_host.size() > p->tiles_cap) return fail(YO_EINVAL, "internal: tile table");
+    if (p->ws) {
+        // synchronous: the graph cache keys on the tiling, and old graphs may still run
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(p->ws + p->L.tiles.off, p->tiles_host.data(), p->tiles_host.size() * 4,
+                         hipMemcpyHostToDevice));
+    }
+    return YO_OK;
+}
+
+yo_status yo_set_background(yo_plan *p, const float *kappa, const float *mask, yo_stream stream)
+{
+    if (!p || !kappa || !mask) return fail(YO_EINVAL, "null argument");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    const yo_grid &g = p->grid;
+    HIPCHK(yo_launch_pitch_copy(kappa, wsp<float>(p, p->L.kappa), 3, g.nz, g.ny, g.nx, g.nx, p->nxp, s));
+    HIPCHK(hipMemcpyAsync(p->chain.mask, mask, sizeof(float) * p->U * p->V, hipMemcpyDeviceToDevice, s));
+    p->bg_set = true;
+    p->design_set = false;
+    return YO_OK;
+}
+
+static std::complex<double> cget(const double *a, size_t i) { return {a[2 * i], a[2 * i + 1]}; }
+
+yo_status yo_set_source_mode(yo_plan *p, int src, const double *h, yo_stream stream)
+{
+    if (!p || !h) return fail(YO_EINVAL, "null argument");
+    if (src < 0 || src >= p->n_src) return fail(YO_EINVAL, "source index out of range");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    const yo_plane &pl = p->src_planes[src];
+    const size_t n = (size_t)pl.n0 * pl.n1;
+    if (p->src_j_host.size() < p->src_total) p->src_j_host.assign(p->src_total, float2{0, 0});
+    // J = n x h: J_t1 = -h_t2 (h_t2 stored at the E_t1 sites), J_t2 = h_t1
+    for (size_t i = 0; i < n; ++i) {
+        const auto h1 = cget(h, i), h2 = cget(h, n + i);
+        p->src_j_host[p->src_off[src] + i] = float2{(float)-h2.real(), (float)-h2.imag()};
+        p->src_j_host[p->src_off[src] + n + i] = float2{(float)h1.real(), (float)h1.imag()};
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(p->ws + p->L.src_j.off + sizeof(float2) * p->src_off[src],
+                          p->src_j_host.data() + p->src_off[src], sizeof(float2) * 2 * n,
+                          hipMemcpyHostToDevice, s));
+    p->src_set[src] = 1;
+    rebuild_descriptors(p);
+    yo_status st = upload_desc(p, s);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(s));
+    return YO_OK;
+}
+
+yo_status yo_set_port_mode(yo_plan *p, int port, const double *e, const double *h, yo_stream stream)
+{
+    if (!p || !e || !h) return fail(YO_EINVAL, "null argument");
+    if (port < 0 || port >= p->n_ports) return fail(YO_EINVAL, "port index out of range");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    const yo_plane &pl = p->port_planes[port];
+    const size_t n = (size_t)pl.n0 * pl.n1;
+    // N = 1/2 sum (e_t1 conj(h_t2) - e_t2 conj(h_t1)); cell area cancels
+    std::complex<double> N = 0.0;
+    for (size_t i = 0; i < n; ++i)
+        N += cget(e, i) * std::conj(cget(h, n + i)) - cget(e, n + i) * std::conj(cget(h, i));
+    N *= 0.5;
+    if (std::abs(N) == 0.0) return fail(YO_EINVAL, "mode normalisation N is zero");
+    if (p->port_w_host.size() < p->port_total) p->port_w_host.assign(p->port_total, float2{0, 0});
+    for (size_t i = 0; i < n; ++i) {
+        const std::complex<double> w1 = std::conj(cget(h, n + i)) / (2.0 * N);
+        const std::complex<double> w2 = -std::conj(cget(h, i)) / (2.0 * N);
+        p->port_w_host[p->port_off[port] + i] = float2{(float)w1.real(), (float)w1.imag()};
+        p->port_w_host[p->port_off[port] + n + i] = float2{(float)w2.real(), (float)w2.imag()};
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(p->ws + p->L.port_w.off + sizeof(float2) * p->port_off[port],
+                          p->port_w_host.data() + p->port_off[port], sizeof(float2) * 2 * n,
+                          hipMemcpyHostToDevice, s));
+    p->port_set[port] = 1;
+    rebuild_descriptors(p);
+    yo_status st = upload_desc(p, s);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(s));
+    return YO_OK;
+}
+
+yo_status yo_set_design(yo_plan *p, const float *C, double beta, yo_stream stream)
+{
+    if (!p || !C) return fail(YO_EINVAL, "null argument");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (!p->bg_set) return fail(YO_ESTATE, "yo_set_background first");
+    if (!(beta > 0)) return fail(YO_EINVAL, "beta must be positive");
+    const yo_design &d = p->des;
+    HIPCHK(yo_launch_chain_forward(p->chain, C, (float)beta, wsp<float>(p, p->L.kappa), p->grid.nx,
+                                   p->grid.ny, p->grid.nz, p->nxp, d.i0, d.j0, d.k_lo, d.k_hi,
+                                   (hipStream_t)stream));
+    p->beta = beta;
+    p->design_set = true;
+    return YO_OK;
+}
+
+yo_status yo_reset(yo_plan *p, int which, yo_stream stream)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (which < 1 || which > 3) return fail(YO_EINVAL, "which must be YO_FORWARD, YO_ADJOINT or YO_BOTH");
+    hipStream_t s = (hipStream_t)stream;
+    int r0, r1;
+    set_rhs_range(p, which, r0, r1);
+    if (r1 > r0) {
+        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.fields) + fields_per_rhs(p) * r0,
+                              fields_per_rhs(p) * (r1 - r0), 0.0f, s));
+        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.psi) + p->psi_per_rhs * r0,
+                              p->psi_per_rhs * (r1 - r0), 0.0f, s));
+        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.dft_box) + 6 * p->bsz * r0, 6 * p->bsz * (r1 - r0),
+                              0.0f, s));
+        const size_t mt = std::max<size_t>(p->mon_total, 1);
+        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.dft_mon) + 2 * mt * r0, 2 * mt * (r1 - r0), 0.0f, s));
+    }
+    YoCtrArgs ca{};
+    ca.n = 1;
+    ca.add = 0;
+    ca.ctr[0] = wsp<int>(p, p->L.ctr);
+    HIPCHK(yo_launch_ctr(ca, 1, s));
+    p->steps_done = 0;
+    p->active = which;
+    p->finalized = false;
+    return YO_OK;
+}
+
+// Launch `n_launch` steps (k_offset 0..n_launch-1) of a plan list, then add
+// n_launch to every plan's counter.  Plans must share the tiling rows.
+static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
+                              hipStream_t s)
+{
+    for (int base = 0; base < n; base += YO_MAX_SLOTS) {
+        const int cnt = std::min(YO_MAX_SLOTS, n - base);
+        YoStepArgs a[2];
+        int blocks[2];
+        for (int cls = 0; cls < 2; ++cls) {
+            memset(&a[cls], 0, sizeof(YoStepArgs));
+            a[cls].n_slots = cnt;
+            int tot = 0;
+            for (int i = 0; i < cnt; ++i) {
+                yo_plan *p = plans[base + i];
+                int r0, r1;
+                set_rhs_range(p, which[base + i], r0, r1);
+                YoSlot &sl = a[cls].slot[i];
+                sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
+                sl.tiles = wsp<int>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
+                sl.rhs0 = r0;
+                sl.nrhs = std::max(r1 - r0, 1);
+                sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
+                sl.kc = p->kc;
+                a[cls].prefix[i] = tot;
+                tot += sl.nrhs * sl.ntile;
+            }
+            a[cls].prefix[cnt] = tot;
+            a[cls].total_waves = tot;
+            blocks[cls] = (tot + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
+        }
+        const int ty = plans[base]->ty;
+        for (int k = 0; k < n_launch; ++k) {
+            for (int cls = 0; cls < 2; ++cls) {
+                a[cls].k_offset = k;
+                HIPCHK(yo_launch_step(ty, cls, a[cls], blocks[cls], s));
+            }
+        }
+        YoCtrArgs ca{};
+        ca.n = cnt;
+        ca.add = n_launch;
+        for (int i = 0; i < cnt; ++i) ca.ctr[i] = wsp<int>(plans[base + i], plans[base + i]->L.ctr);
+        HIPCHK(yo_launch_ctr(ca, 0, s));
+    }
+    return YO_OK;
+}
+
+yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_steps, int chunk,
+                          int use_graph, yo_stream stream)
+{
+    if (!plans || !which || n < 1) return fail(YO_EINVAL, "empty plan list");
+    if (n_steps < 0) return fail(YO_EINVAL, "negative step count");
+    for (int i = 0; i < n; ++i) {
+        yo_plan *p = plans[i];
+        if (!p || !p->ws) return fail(YO_EWORKSPACE, "plan %d has no workspace", i);
+        if (which[i] != p->active) return fail(YO_ESTATE, "plan %d: which differs from its reset", i);
+        if (p->ty != plans[0]->ty) return fail(YO_EINVAL, "plans in one call must share the tiling rows");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == p) return fail(YO_EINVAL, "plan listed twice");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (chunk < 1) chunk = 1;
+    int done = 0;
+    if (use_graph && n_steps >= chunk) {
+        std::string key = "c" + std::to_string(chunk) + "t" + std::to_string(plans[0]->ty);
+        for (int i = 0; i < n; ++i)
+            key += "#" + std::to_string(plans[i]->id) + ":" + std::to_string(plans[i]->generation) +
+                   "w" + std::to_string(which[i]) + "k" + std::to_string(plans[i]->kc);
+        GraphEntry ge;
+        {
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            auto it = g_graphs.find(key);
+            if (it != g_graphs.end()) ge = it->second;
+        }
+        if (!ge.exec) {
+            yo_plan *p0 = plans[0];
+            if (!p0->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p0->cap_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(p0->cap_stream, hipStreamCaptureModeThreadLocal));
+            yo_status st = launch_steps(plans, which, n, chunk, p0->cap_stream);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(p0->cap_stream, &graph);
+            if (st) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(YO_EHIP, "graph capture: %s", hipGetErrorString(e));
+            hipGraphExec_t exec = nullptr;
+            HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            ge.graph = graph;
+            ge.exec = exec;
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            g_graphs[key] = ge;
+        }
+        while (n_steps - done >= chunk) {
+            HIPCHK(hipGraphLaunch(ge.exec, s));
+            done += chunk;
+        }
+    }
+    while (done < n_steps) {
+        const int k = std::min(chunk, n_steps - done);
+        yo_status st = launch_steps(plans, which, n, k, s);
+        if (st) return st;
+        done += k;
+    }
+    for (int i = 0; i < n; ++i)
+        plans[i]->steps_done = std::min(plans[i]->n_steps, plans[i]->steps_done + n_steps);
+    return YO_OK;
+}
+
+yo_status yo_advance(yo_plan *p, int which, int n_steps, yo_stream stream)
+{
+    return yo_advance_many(&p, &which, 1, n_steps, std::max(n_steps, 1), 0, stream);
+}
+
+yo_status yo_finalize(yo_plan *p, int which, yo_stream stream)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (which != p->active) return fail(YO_ESTATE, "finalize: which differs from the reset");
+    if (p->steps_done < p->n_steps) return fail(YO_ESTATE, "finalize before all steps ran");
+    hipStream_t s = (hipStream_t)stream;
+    int r0, r1;
+    set_rhs_range(p, which, r0, r1);
+    const size_t mt = std::max<size_t>(p->mon_total, 1);
+    for (int r = r0; r < r1; ++r) {
+        const YoRhsD &R = p->hrhs[r];
+        HIPCHK(yo_launch_finalize(R.dft_box, 3 * p->bsz, R.ginv[0], R.ginv[1], R.ginv[2], R.ginv[3], s));
+        HIPCHK(yo_launch_finalize(R.dft_mon, mt, R.ginv[0], R.ginv[1], R.ginv[2], R.ginv[3], s));
+    }
+    p->finalized = true;
+    return YO_OK;
+}
+
+yo_status yo_run(yo_plan *p, int which, int chunk, int use_graph, yo_stream stream)
+{
+    yo_status st = yo_reset(p, which, stream);
+    if (st) return st;
+    st = yo_advance_many(&p, &which, 1, p->n_steps, chunk, use_graph, stream);
+    if (st) return st;
+    return yo_finalize(p, which, stream);
+}
+
+yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
+{
+    if (!p || !alpha) return fail(YO_EINVAL, "null argument");
+    if (!p->finalized || !(p->active & YO_FORWARD)) return fail(YO_ESTATE, "no finished forward run");
+    hipStream_t s = (hipStream_t)stream;
+    const float2 *w = reinterpret_cast<const float2 *>(p->ws + p->L.port_w.off);
+    for (int sidx = 0; sidx < p->n_src; ++sidx)
+        for (int q = 0; q < p->n_ports; ++q) {
+            if (!p->port_set[q]) return fail(YO_ESTATE, "port %d mode not set", q);
+            for (int f = 0; f < p->n_freq; ++f) {
+                const int r = f * p->n_src + sidx;
+                const yo_plane &pl = p->port_planes[q];
+                float2 *out = reinterpret_cast<float2 *>(alpha) + ((size_t)sidx * p->n_ports + q) * p->n_freq + f;
+                HIPCHK(yo_launch_alpha(p->hrhs[r].dft_mon + p->mon_off[q], w + p->port_off[q],
+                                       2 * pl.n0 * pl.n1, out, s));
+            }
+        }
+    return YO_OK;
+}
+
+static yo_status grad_common(yo_plan *p, const float *coef, float *gbox, float *gmap, hipStream_t s)
+{
+    if (!p->finalized || p->active != YO_BOTH) return fail(YO_ESTATE, "needs a finished YO_BOTH run");
+    YoGradArgs a;
+    memset(&a, 0, sizeof a);
+    for (int f = 0; f < p->n_freq; ++f) {
+        for (int si = 0; si < p->n_src; ++si) a.EF[f * p->n_src + si] = p->hrhs[f * p->n_src + si].dft_box;
+        for (int q = 0; q < p->n_ports; ++q)
+            a.EA[f * p->n_ports + q] = p->hrhs[p->n_fwd + f * p->n_ports + q].dft_box;
+        a.sinth[f] = (float)std::sin(0.5 * p->omega_dt[f]);
+    }
+    a.coef = reinterpret_cast<const float2 *>(coef);
+    a.kappa = wsp<float>(p, p->L.kappa);
+    a.gbox = gbox;
+    a.gmap = gmap;
+    a.n_src = p->n_src;
+    a.n_ports = p->n_ports;
+    a.n_freq = p->n_freq;
+    a.nxp = p->nxp;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    for (int i = 0; i < 6; ++i) a.box[i] = p->box[i];
+    a.k_lo = p->des.k_lo;
+    a.k_hi = p->des.k_hi;
+    a.G0 = p->G0;
+    a.G1 = p->G1;
+    HIPCHK(yo_launch_grad_assemble(a, s));
+    return YO_OK;
+}
+
+yo_status yo_gradient_kappa(yo_plan *p, const float *coef, float *g, yo_stream stream)
+{
+    if (!p || !coef || !g) return fail(YO_EINVAL, "null argument");
+    return grad_common(p, coef, g, nullptr, (hipStream_t)stream);
+}
+
+yo_status yo_gradient(yo_plan *p, const float *coef, float *dFdC, yo_stream stream)
+{
+    if (!p || !coef || !dFdC) return fail(YO_EINVAL, "null argument");
+    if (!p->design_set) return fail(YO_ESTATE, "yo_set_design first");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(yo_launch_fill(p->chain.gmap, 4 * (size_t)p->G0 * p->G1, 0.0f, s));
+    yo_status st = grad_common(p, coef, nullptr, p->chain.gmap, s);
+    if (st) return st;
+    HIPCHK(yo_launch_chain_vjp(p->chain, (float)p->beta, dFdC, s));
+    return YO_OK;
+}
+
+yo_status yo_chain_vjp(yo_plan *p, const float *gk, float *dFdC, yo_stream stream)
+{
+    if (!p || !gk || !dFdC) return fail(YO_EINVAL, "null argument");
+    if (!p->design_set) return fail(YO_ESTATE, "yo_set_design first");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(yo_launch_fill(p->chain.gmap, 4 * (size_t)p->G0 * p->G1, 0.0f, s));
+    HIPCHK(yo_launch_zsum(gk, p->box, p->des.k_lo, p->des.k_hi, p->chain.gmap, p->G0, p->G1, s));
+    HIPCHK(yo_launch_chain_vjp(p->chain, (float)p->beta, dFdC, s));
+    return YO_OK;
+}
+
+yo_status yo_get_dft(const yo_plan *p, int rhs, int region, float *out, yo_stream stream)
+{
+    if (!p || !out) return fail(YO_EINVAL, "null argument");
+    if (rhs < 0 || rhs >= p->n_rhs) return fail(YO_EINVAL, "rhs out of range");
+    if (region < 0 || region > p->n_ports) return fail(YO_EINVAL, "region out of range");
+    const YoRhsD &R = p->hrhs[rhs];
+    const void *src;
+    size_t bytes;
+    if (region == 0) {
+        src = R.dft_box;
+        bytes = sizeof(float2) * 3 * p->bsz;
+    } else {
+        const yo_plane &pl = p->port_planes[region - 1];
+        src = R.dft_mon + p->mon_off[region - 1];
+        bytes = sizeof(float2) * 2 * pl.n0 * pl.n1;
+    }
+    HIPCHK(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return YO_OK;
+}
+
+yo_status yo_set_fields(yo_plan *p, int rhs, const float *E, const float *H, yo_stream stream)
+{
+    if (!p || !E || !H) return fail(YO_EINVAL, "null argument");
+    if (rhs < 0 || rhs >= p->n_rhs) return fail(YO_EINVAL, "rhs out of range");
+    const yo_grid &g = p->grid;
+    const YoRhsD &R = p->hrhs[rhs];
+    const int par = p->steps_done & 1;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(yo_launch_pitch_copy(E, R.E[par], 3, g.nz, g.ny, g.nx, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_pitch_copy(H, R.H[par], 3, g.nz, g.ny, g.nx, g.nx, p->nxp, s));
+    return YO_OK;
+}
+
+yo_status yo_get_fields(const yo_plan *p, int rhs, float *E, float *H, yo_stream stream)
+{
+    if (!p || !E || !H) return fail(YO_EINVAL, "null argument");
+    if (rhs < 0 || rhs >= p->n_rhs) return fail(YO_EINVAL, "rhs out of range");
+    const yo_grid &g = p->grid;
+    const YoRhsD &R = p->hrhs[rhs];
+    const int par = p->steps_done & 1;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(yo_launch_pitch_copy(R.E[par], E, 3, g.nz, g.ny, g.nx, p->nxp, g.nx, s));
+    HIPCHK(yo_launch_pitch_copy(R.H[par], H, 3, g.nz, g.ny, g.nx, p->nxp, g.nx, s));
+    return YO_OK;
+}
+
+yo_status yo_get_kappa(const yo_plan *p, float *kappa, yo_stream stream)
+{
+    if (!p || !kappa) return fail(YO_EINVAL, "null argument");
+    const yo_grid &g = p->grid;
+    HIPCHK(yo_launch_pitch_copy(reinterpret_cast<const float *>(p->ws + p->L.kappa.off), kappa, 3,
+                                g.nz, g.ny, g.nx, p->nxp, g.nx, (hipStream_t)stream));
+    return YO_OK;
+}
+
+yo_status yo_model_bytes(const yo_plan *p, int which, double *bytes, double *cells)
+{
+    if (!p || !bytes || !cells) return fail(YO_EINVAL, "null argument");
+    int r0, r1;
+    set_rhs_range(p, which, r0, r1);
+    const double R = r1 - r0;
+    const yo_grid &g = p->grid;
+    const double N = (double)g.nx * g.ny * g.nz;
+    // cells inside each axis' absorbing slabs
+    const double pml = (double)(p->plo[0] + p->phi[0]) * g.ny * g.nz +
+                       (double)(p->plo[1] + p->phi[1]) * g.nx * g.nz +
+                       (double)(p->plo[2] + p->phi[2]) * g.nx * g.ny;
+    double win = 0.0;
+    for (auto &f : p->freqs) win += (double)f.win_len / p->n_steps;
+    win /= p->n_freq;
+    *bytes = R * (48.0 * N + 32.0 * pml + 48.0 * (double)p->bsz * win) + 12.0 * N;
+    *cells = R * N;
+    return YO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point the header declares, and plan creation validates descriptors."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2505_03352_amd import _abi
+from paper_2505_03352_amd.plan import Plan, freqs_of, grid_design_of
+from workloads import configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "yeeopt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(yo_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert b"gfx950" in L.yo_version()
+
+
+def _create(dev, **over):
+    grid, design = grid_design_of(dev)
+    grid.update(over.pop("grid", {}))
+    design.update(over.pop("design", {}))
+    freqs = over.pop("freqs", freqs_of(dev))
+    srcs = over.pop("srcs", [m.plane for m in dev.sources])
+    ports = over.pop("ports", [m.plane for m in dev.ports])
+    return Plan(grid, design, over.pop("n_steps", dev.n_steps), freqs, srcs, ports, device="cpu")
+
+
+def test_plan_create_and_workspace_size():
+    dev = configs.realistic()
+    p = _create(dev)
+    # fields alone: 6 rhs x 2 buffers x 6 components x padded cells x 4 B
+    cells = dev.nz * dev.ny * ((dev.nx + 31) // 32 * 32)
+    assert p.workspace_bytes > 6 * 12 * cells * 4
+    assert p.workspace_bytes < 6 * 12 * cells * 4 * 1.5
+    assert p.n_rhs == 6
+    p.close()
+
+
+def test_multiport_fits_one_gpu():
+    dev = configs.multiport()
+    p = _create(dev)
+    assert p.n_rhs == 25
+    assert p.workspace_bytes < 60e9
+    p.close()
+
+
+def test_unstable_courant_rejected():
+    dev = configs.tiny()
+    with pytest.raises(_abi.YeeOptError) as e:
+        _create(dev, grid={"courant": 0.6})
+    assert e.value.status == _abi.YO_EUNSTABLE
+
+
+def test_design_touching_pml_rejected():
+    dev = configs.tiny()
+    with pytest.raises(_abi.YeeOptError) as e:
+        _create(dev, design={"i0": 8})
+    assert e.value.status == _abi.YO_EINVAL
+
+
+def test_plane_inside_pml_rejected():
+    dev = configs.tiny()
+    from workloads import Plane
+    bad = Plane(0, 3, 20, 10, 5, 5)
+    with pytest.raises(_abi.YeeOptError) as e:
+        _create(dev, srcs=[bad])
+    assert e.value.status == _abi.YO_EINVAL
+
+
+def test_odd_supersample_rejected():
+    dev = configs.tiny()
+    with pytest.raises(_abi.YeeOptError):
+        _create(dev, design={"supersample": 3})
+
+
+def test_window_outside_run_rejected():
+    dev = configs.tiny()
+    f = freqs_of(dev)
+    f[0].win_start = dev.n_steps - 10
+    f[0].win_len = 20
+    with pytest.raises(_abi.YeeOptError):
+        _create(dev, freqs=f)
+
+
+def test_too_many_ports_unsupported():
+    dev = configs.tiny()
+    ports = [dev.ports[0].plane] * 9
+    with pytest.raises(_abi.YeeOptError) as e:
+        _create(dev, ports=ports)
+    assert e.value.status == _abi.YO_EUNSUPPORTED
+
+
+def test_calls_before_bind_fail_cleanly():
+    dev = configs.tiny()
+    p = _create(dev)
+    L = _abi.lib()
+    assert L.yo_reset(p.handle, _abi.YO_BOTH, None) == _abi.YO_EWORKSPACE
+    assert L.yo_finalize(p.handle, _abi.YO_BOTH, None) == _abi.YO_EWORKSPACE
+    assert L.yo_set_tiling(p.handle, 5, 16) == _abi.YO_EINVAL
+    assert L.yo_set_tiling(p.handle, 8, 8) == _abi.YO_OK
+    p.close()
+
+
+def test_model_bytes_matches_traffic_model():
+    dev = configs.realistic()
+    p = _create(dev)
+    b, c = p.model_bytes(_abi.YO_BOTH)
+    assert c == 6 * dev.cells
+    per = b / c
+    assert 48 + 2 <= per <= 70
+    p.close()
