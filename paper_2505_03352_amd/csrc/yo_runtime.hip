@@ -1028,6 +1028,68 @@ yo_status yo_chain_vjp(yo_plan *p, const float *gk, float *dFdC, yo_stream strea
     return YO_OK;
 }
 
+yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, double *bytes,
+                         double *cells, yo_stream stream)
+{
+    if (!p || !avg_ms || !bytes || !cells) return fail(YO_EINVAL, "null argument");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (cls < 0 || cls > 1 || n_launch < 1) return fail(YO_EINVAL, "bad class or count");
+    if (!p->active) return fail(YO_ESTATE, "yo_reset first");
+    hipStream_t s = (hipStream_t)stream;
+    int r0, r1;
+    set_rhs_range(p, p->active, r0, r1);
+    YoStepArgs a;
+    memset(&a, 0, sizeof a);
+    a.n_slots = 1;
+    YoSlot &sl = a.slot[0];
+    sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
+    sl.tiles = wsp<int>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
+    sl.rhs0 = r0;
+    sl.nrhs = std::max(r1 - r0, 1);
+    sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
+    sl.kc = p->kc;
+    a.prefix[1] = a.total_waves = sl.nrhs * sl.ntile;
+    const int blocks = (a.total_waves + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
+    // owned cells of this class and those inside each axis' absorbing slabs
+    const yo_grid &g = p->grid;
+    double own = 0.0, in_pml = 0.0;
+    const int first = cls ? p->n_tile_int : 0;
+    const int last = cls ? p->n_tile_int + p->n_tile_pml : p->n_tile_int;
+    for (int t = first; t < last; ++t) {
+        const int code = p->tiles_host[t];
+        const int ty = code & 2047, tx = (code >> 11) & 2047, tz = code >> 22;
+        const int x0 = tx * YO_TX, x1 = std::min(x0 + YO_TX, g.nx);
+        const int y0 = ty * p->ty, y1 = std::min(y0 + p->ty, g.ny);
+        const int z0 = tz * p->kc, z1 = std::min(z0 + p->kc, g.nz);
+        own += (double)(x1 - x0) * (y1 - y0) * (z1 - z0);
+        if (cls) {
+            for (int z = z0; z < z1; ++z)
+                for (int y = y0; y < y1; ++y)
+                    for (int x = x0; x < x1; ++x) {
+                        in_pml += (x < p->plo[0] || x >= g.nx - p->phi[0]);
+                        in_pml += (y < p->plo[1] || y >= g.ny - p->phi[1]);
+                        in_pml += (z < p->plo[2] || z >= g.nz - p->phi[2]);
+                    }
+        }
+    }
+    const double R = r1 - r0;
+    *bytes = own * (48.0 * R + 12.0) + 32.0 * R * in_pml;
+    *cells = own * R;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    for (int k = 0; k < n_launch; ++k) HIPCHK(yo_launch_step(p->ty, cls, a, blocks, s));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / n_launch;
+    return YO_OK;
+}
+
 yo_status yo_get_dft(const yo_plan *p, int rhs, int region, float *out, yo_stream stream)
 {
     if (!p || !out) return fail(YO_EINVAL, "null argument");

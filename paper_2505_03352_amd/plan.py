@@ -25,7 +25,15 @@ def _ptr(t: torch.Tensor):
         raise ValueError("device tensor expected")
     if not t.is_contiguous():
         raise ValueError("contiguous tensor expected")
+    if t.is_conj() or t.is_neg():
+        # a lazy conjugate/negative view: data_ptr() holds the unconjugated values
+        raise ValueError("resolve conjugate/negative views before passing them to the library")
     return ct.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, device, dtype) -> torch.Tensor:
+    """Materialised, contiguous device copy (resolves lazy conj/neg views)."""
+    return t.to(device, dtype).resolve_conj().resolve_neg().contiguous()
 
 
 def _host_c128(a) -> np.ndarray:
@@ -126,8 +134,8 @@ class Plan:
 
     # ----------------------------------------------------------- setup
     def set_background(self, kappa: torch.Tensor, mask: torch.Tensor, stream=None):
-        kappa = kappa.to(self.device, torch.float32).contiguous()
-        mask = mask.to(self.device, torch.float32).contiguous()
+        kappa = _dev(kappa, self.device, torch.float32)
+        mask = _dev(mask, self.device, torch.float32)
         assert tuple(kappa.shape) == self.shape and tuple(mask.shape) == self.canvas_shape
         call("yo_set_background", self._h, _ptr(kappa), _ptr(mask), _stream(stream))
         self._keep = [kappa, mask]
@@ -146,7 +154,7 @@ class Plan:
              h.ctypes.data_as(ct.c_void_p), _stream(stream))
 
     def set_design(self, C: torch.Tensor, beta: float, stream=None):
-        C = C.to(self.device, torch.float32).contiguous()
+        C = _dev(C, self.device, torch.float32)
         assert tuple(C.shape) == self.control_shape
         call("yo_set_design", self._h, _ptr(C), float(beta), _stream(stream))
         self.beta = float(beta)
@@ -181,21 +189,21 @@ class Plan:
         return out
 
     def gradient(self, coef: torch.Tensor, stream=None) -> torch.Tensor:
-        coef = coef.to(self.device, torch.complex64).contiguous()
+        coef = _dev(coef, self.device, torch.complex64)
         assert tuple(coef.shape) == (self.n_src, self.n_ports, self.n_freq)
         out = torch.empty(self.control_shape, dtype=torch.float32, device=self.device)
         call("yo_gradient", self._h, _ptr(coef), _ptr(out), _stream(stream))
         return out
 
     def gradient_kappa(self, coef: torch.Tensor, stream=None) -> torch.Tensor:
-        coef = coef.to(self.device, torch.complex64).contiguous()
+        coef = _dev(coef, self.device, torch.complex64)
         x0, y0, z0, bx, by, bz = self.box
         out = torch.empty((3, bz, by, bx), dtype=torch.float32, device=self.device)
         call("yo_gradient_kappa", self._h, _ptr(coef), _ptr(out), _stream(stream))
         return out
 
     def chain_vjp(self, gkappa: torch.Tensor, stream=None) -> torch.Tensor:
-        gkappa = gkappa.to(self.device, torch.float32).contiguous()
+        gkappa = _dev(gkappa, self.device, torch.float32)
         x0, y0, z0, bx, by, bz = self.box
         assert tuple(gkappa.shape) == (3, bz, by, bx)
         out = torch.empty(self.control_shape, dtype=torch.float32, device=self.device)
@@ -214,8 +222,8 @@ class Plan:
         return out
 
     def set_fields(self, rhs: int, E: torch.Tensor, H: torch.Tensor, stream=None):
-        E = E.to(self.device, torch.float32).contiguous()
-        H = H.to(self.device, torch.float32).contiguous()
+        E = _dev(E, self.device, torch.float32)
+        H = _dev(H, self.device, torch.float32)
         call("yo_set_fields", self._h, rhs, _ptr(E), _ptr(H), _stream(stream))
         torch.cuda.current_stream().synchronize()
 
@@ -229,6 +237,14 @@ class Plan:
         out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
         call("yo_get_kappa", self._h, _ptr(out), _stream(stream))
         return out
+
+    def time_kernel(self, cls: int = 0, n_launch: int = 20, stream=None):
+        """(avg ms per launch, algorithmic bytes per launch, cell-updates per
+        launch) of one class of the time-stepping kernel, by HIP events."""
+        ms, b, c = ct.c_float(), ct.c_double(), ct.c_double()
+        call("yo_time_kernel", self._h, int(cls), int(n_launch), ct.byref(ms), ct.byref(b),
+             ct.byref(c), _stream(stream))
+        return float(ms.value), float(b.value), float(c.value)
 
     def model_bytes(self, which=YO_BOTH):
         b, c = ct.c_double(), ct.c_double()

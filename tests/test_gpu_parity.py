@@ -338,3 +338,50 @@ def test_realistic_full_size_short_run_fields_match_oracle():
     eH = np.abs(H - r.H).max() / np.abs(r.H).max()
     say(f"  max rel err E {eE:.2e} H {eH:.2e}")
     assert eE < 1e-4 and eH < 1e-4
+
+
+def test_autograd_function_matches_library_and_finite_differences():
+    """torch conventions: L = sum |alpha|^2 gives C.grad = the library's
+    gradient with coef = conj(alpha); and it matches central differences of
+    forward-only runs."""
+    from paper_2505_03352_amd import fn
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro(n_steps=1200)
+    p = plan_for(dev)
+    C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda").requires_grad_(True)
+    say("autograd forward/backward")
+    a = fn.modal_coefficients(C, p, dev.beta, chunk=100)
+    L = (a.abs() ** 2).sum()
+    L.backward()
+    g_auto = C.grad.detach().cpu().numpy()
+    g_lib = p.gradient(torch.conj(a.detach())).cpu().numpy()
+    assert np.allclose(g_auto, g_lib, rtol=1e-6, atol=1e-9 * np.abs(g_lib).max())
+    # central differences on a few controls (forward-only runs)
+    q = plan_for(dev)
+    h = 1e-2
+    gmax = np.abs(g_auto).max()
+    for idx in [(1, 2), (3, 4), (2, 1)]:
+        vals = []
+        for sgn in (1, -1):
+            Cp = dev.C.copy()
+            Cp[idx] += sgn * h
+            q.set_design(torch.as_tensor(Cp, dtype=torch.float32), dev.beta)
+            q.run(1, chunk=100)
+            vals.append(float((q.alpha().abs() ** 2).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        say(f"  FD {idx}: autograd {g_auto[idx]:.5e} fd {fd:.5e}")
+        assert abs(fd - g_auto[idx]) < 2e-2 * gmax
+    p.close()
+    q.close()
+
+
+def test_conjugate_views_are_resolved():
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro(n_steps=400)
+    p = plan_for(dev)
+    p.run(3, chunk=100)
+    a = p.alpha()
+    g1 = p.gradient(torch.conj(a)).cpu().numpy()                 # lazy view
+    g2 = p.gradient(torch.conj(a).resolve_conj()).cpu().numpy()  # materialised
+    assert np.array_equal(g1, g2)
+    p.close()
