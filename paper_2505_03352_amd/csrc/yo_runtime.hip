@@ -281,11 +281,24 @@ size_t tiles_capacity(const yo_grid &g, int ty_min, int kc_min)
     return ntx * nty * ntz;
 }
 
+// Host tables go up with synchronous copies after the caller's stream has
+// drained: pageable-memory copies are not reliably ordered behind kernels
+// still running on the stream (a large workspace fill, or a solve that reads
+// the descriptors being replaced).
 yo_status upload(yo_plan *p, const Region &r, const void *src, size_t bytes, hipStream_t s)
 {
     if (bytes > r.bytes) return fail(YO_EWORKSPACE, "internal: region too small");
     if (!bytes) return YO_OK;
-    HIPCHK(hipMemcpyAsync(p->ws + r.off, src, bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(p->ws + r.off, src, bytes, hipMemcpyHostToDevice));
+    return YO_OK;
+}
+
+yo_status upload_to(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (!bytes) return YO_OK;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return YO_OK;
 }
 
@@ -653,14 +666,14 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     if ((st = upload(p, p->L.steptab, p->steptab.data(), p->steptab.size() * sizeof(float4), s))) return st;
     if ((st = upload(p, p->L.tiles, p->tiles_host.data(), p->tiles_host.size() * sizeof(int), s))) return st;
     const YoChainBufs &c = p->chain;
-    HIPCHK(hipMemcpyAsync(c.tap_lo_x, p->tap_lo_x.data(), p->tap_lo_x.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.tap_n_x, p->tap_n_x.data(), p->tap_n_x.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.tap_lo_y, p->tap_lo_y.data(), p->tap_lo_y.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.tap_n_y, p->tap_n_y.data(), p->tap_n_y.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.urange_x, p->urange_x.data(), p->urange_x.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.urange_y, p->urange_y.data(), p->urange_y.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.tap_w_x, p->tap_w_x.data(), p->tap_w_x.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.tap_w_y, p->tap_w_y.data(), p->tap_w_y.size() * 4, hipMemcpyHostToDevice, s));
+    if ((st = upload_to(c.tap_lo_x, p->tap_lo_x.data(), p->tap_lo_x.size() * 4, s))) return st;
+    if ((st = upload_to(c.tap_n_x, p->tap_n_x.data(), p->tap_n_x.size() * 4, s))) return st;
+    if ((st = upload_to(c.tap_lo_y, p->tap_lo_y.data(), p->tap_lo_y.size() * 4, s))) return st;
+    if ((st = upload_to(c.tap_n_y, p->tap_n_y.data(), p->tap_n_y.size() * 4, s))) return st;
+    if ((st = upload_to(c.urange_x, p->urange_x.data(), p->urange_x.size() * 4, s))) return st;
+    if ((st = upload_to(c.urange_y, p->urange_y.data(), p->urange_y.size() * 4, s))) return st;
+    if ((st = upload_to(c.tap_w_x, p->tap_w_x.data(), p->tap_w_x.size() * 4, s))) return st;
+    if ((st = upload_to(c.tap_w_y, p->tap_w_y.data(), p->tap_w_y.size() * 4, s))) return st;
     if ((st = upload_desc(p, s))) return st;
     // copies from pageable host memory are staged; make them complete before
     // the host vectors can change
@@ -720,9 +733,9 @@ yo_status yo_set_source_mode(yo_plan *p, int src, const double *h, yo_stream str
         p->src_j_host[p->src_off[src] + n + i] = float2{(float)h1.real(), (float)h1.imag()};
     }
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemcpyAsync(p->ws + p->L.src_j.off + sizeof(float2) * p->src_off[src],
-                          p->src_j_host.data() + p->src_off[src], sizeof(float2) * 2 * n,
-                          hipMemcpyHostToDevice, s));
+    yo_status st0 = upload_to(p->ws + p->L.src_j.off + sizeof(float2) * p->src_off[src],
+                              p->src_j_host.data() + p->src_off[src], sizeof(float2) * 2 * n, s);
+    if (st0) return st0;
     p->src_set[src] = 1;
     rebuild_descriptors(p);
     yo_status st = upload_desc(p, s);
@@ -752,9 +765,9 @@ yo_status yo_set_port_mode(yo_plan *p, int port, const double *e, const double *
         p->port_w_host[p->port_off[port] + n + i] = float2{(float)w2.real(), (float)w2.imag()};
     }
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemcpyAsync(p->ws + p->L.port_w.off + sizeof(float2) * p->port_off[port],
-                          p->port_w_host.data() + p->port_off[port], sizeof(float2) * 2 * n,
-                          hipMemcpyHostToDevice, s));
+    yo_status st0 = upload_to(p->ws + p->L.port_w.off + sizeof(float2) * p->port_off[port],
+                              p->port_w_host.data() + p->port_off[port], sizeof(float2) * 2 * n, s);
+    if (st0) return st0;
     p->port_set[port] = 1;
     rebuild_descriptors(p);
     yo_status st = upload_desc(p, s);
