@@ -319,6 +319,8 @@ size_t fields_per_rhs(const yo_plan *p) { return 12 * p->cells_p; }   // 2 buffe
 
 }  // namespace
 
+static yo_status set_chain_ptrs(yo_plan *p);
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -466,9 +468,9 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     const size_t DD = (size_t)(p->S * d.md) * (p->S * d.nd);
     const size_t nf = 2 * UV + DD /*tanh*/ + 9 * G + 6 * G + 4 * G + 6 * G + 4 * G + 2 * G + DD /*gphi*/ +
                       (size_t)(p->S * d.nd) * d.mc /*tmp*/ + (size_t)p->tmax * p->S * (d.md + d.nd);
-    L.add(L.chain_f, sizeof(float) * nf + 64 * 16);
+    L.add(L.chain_f, sizeof(float) * (nf + 64 * 16));   // each of 15 buffers padded to 64 floats
     const size_t ni = 2 * (size_t)p->S * (d.md + d.nd) + 2 * (size_t)(d.mc + d.nc);
-    L.add(L.chain_i, sizeof(int) * ni + 64 * 8);
+    L.add(L.chain_i, sizeof(int) * (ni + 64 * 8));     // each of 6 tables padded to 64 ints
 
     build_profiles(p);
     build_steptab(p);
@@ -479,6 +481,18 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     for (int v : p->tap_n_y)
         if (v > p->tmax) { delete p; return fail(YO_EINVAL, "internal: filter taps"); }
     build_tiles(p);
+    {
+        // carve the parametrization buffers once against a stand-in base to
+        // prove the layout holds them; the real pointers are set at bind time
+        p->ws = reinterpret_cast<char *>((uintptr_t)1 << 20);
+        const yo_status st = set_chain_ptrs(p);
+        p->ws = nullptr;
+        p->chain = YoChainBufs{};
+        if (st) {
+            delete p;
+            return st;
+        }
+    }
     *out = p;
     return YO_OK;
 }
@@ -602,7 +616,7 @@ static yo_status rebuild_descriptors(yo_plan *p)
     return YO_OK;
 }
 
-static void set_chain_ptrs(yo_plan *p)
+static yo_status set_chain_ptrs(yo_plan *p)
 {
     YoChainBufs &c = p->chain;
     const yo_design &d = p->des;
@@ -645,6 +659,10 @@ static void set_chain_ptrs(yo_plan *p)
     c.tap_n_y = takei(p->S * d.nd);
     c.urange_x = takei(2 * d.mc);
     c.urange_y = takei(2 * d.nc);
+    if ((char *)f > p->ws + p->L.chain_f.off + p->L.chain_f.bytes ||
+        (char *)ip > p->ws + p->L.chain_i.off + p->L.chain_i.bytes)
+        return fail(YO_EWORKSPACE, "internal: parametrization buffers exceed their region");
+    return YO_OK;
 }
 
 yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream stream)
@@ -658,8 +676,8 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     p->ws_bytes = bytes;
     p->generation++;
     rebuild_descriptors(p);
-    set_chain_ptrs(p);
-    yo_status st;
+    yo_status st = set_chain_ptrs(p);
+    if (st) return st;
     // a fresh workspace holds garbage: clear the state and table regions first
     HIPCHK(yo_launch_fill((float *)p->ws, p->L.total / sizeof(float), 0.0f, s));
     if ((st = upload(p, p->L.prof, p->prof.data(), p->prof.size() * sizeof(float), s))) return st;
