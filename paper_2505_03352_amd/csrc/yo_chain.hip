@@ -22,16 +22,32 @@ __global__ void k_fill(float *p, size_t n, float v)
         p[i] = v;
 }
 
-__global__ void k_pitch_copy(const float *src, float *dst, int ncomp, int nz, int ny, int nx,
-                             int sp, int dp)
+// dense [ncomp][nz][ny][nx] -> ghost layout (interior only; ghosts untouched)
+__global__ void k_to_ghost(const float *src, float *dst, int ncomp, int nz, int ny, int nx, int nxp)
 {
-    const size_t rows = (size_t)ncomp * nz * ny;
-    const size_t n = rows * nx;
+    const size_t n = (size_t)ncomp * nz * ny * nx;
+    const size_t gcomp = (size_t)(nz + 2) * (ny + 2) * nxp;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
-        const size_t row = i / nx;
-        const int x = (int)(i - row * nx);
-        dst[row * dp + x] = src[row * sp + x];
+        size_t q = i;
+        const int x = (int)(q % nx); q /= nx;
+        const int y = (int)(q % ny); q /= ny;
+        const int z = (int)(q % nz); q /= nz;
+        dst[q * gcomp + yo_goff(x, y, z, ny, nxp)] = src[i];
+    }
+}
+
+__global__ void k_from_ghost(const float *src, float *dst, int ncomp, int nz, int ny, int nx, int nxp)
+{
+    const size_t n = (size_t)ncomp * nz * ny * nx;
+    const size_t gcomp = (size_t)(nz + 2) * (ny + 2) * nxp;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        size_t q = i;
+        const int x = (int)(q % nx); q /= nx;
+        const int y = (int)(q % ny); q /= ny;
+        const int z = (int)(q % nz); q /= nz;
+        dst[i] = src[q * gcomp + yo_goff(x, y, z, ny, nxp)];
     }
 }
 
@@ -176,15 +192,16 @@ __global__ void k_smooth(YoChainBufs c, float *kappa, int nx, int ny, int nz, in
     c.aux[4 * gsz + pix] = gxy;
     c.aux[5 * gsz + pix] = gyy;
     const int x = i0 - 2 + m, y = j0 - 2 + n;
-    const size_t plane = (size_t)ny * nxp, comp = plane * nz;
+    const size_t comp = (size_t)(nz + 2) * (ny + 2) * nxp;
     for (int k = k_lo; k <= k_hi; ++k) {
-        const size_t o = (size_t)k * plane + (size_t)y * nxp + x;
+        const size_t o = yo_goff(x, y, k, ny, nxp);
         kappa[o] = kx;
         kappa[comp + o] = ky;
     }
-    for (int k = k_lo; k < k_hi; ++k) kappa[2 * comp + (size_t)k * plane + (size_t)y * nxp + x] = kzi;
-    kappa[2 * comp + (size_t)(k_lo - 1) * plane + (size_t)y * nxp + x] = kzf;
-    kappa[2 * comp + (size_t)k_hi * plane + (size_t)y * nxp + x] = kzf;
+    for (int k = k_lo; k < k_hi; ++k) kappa[2 * comp + yo_goff(x, y, k, ny, nxp)] = kzi;
+    kappa[2 * comp + yo_goff(x, y, k_lo - 1, ny, nxp)] = kzf;
+    kappa[2 * comp + yo_goff(x, y, k_hi, ny, nxp)] = kzf;
+    (void)nx;
 }
 
 // ------------------------------------------------------------- Eq. (1)
@@ -199,7 +216,7 @@ __global__ void k_grad(const YoGradArgs a)
     if (i >= bx * by) return;
     const int bj = i / bx, bi = i - bj * bx;
     const size_t bsz = (size_t)bx * by * bz;
-    const size_t plane = (size_t)a.ny * a.nxp, comp = plane * a.nz;
+    const size_t comp = (size_t)(a.nz + 2) * (a.ny + 2) * a.nxp;
     float sx = 0.0f, sy = 0.0f, szi = 0.0f, szf = 0.0f;
     for (int c = 0; c < 3; ++c) {
         for (int bk = 0; bk < bz; ++bk) {
@@ -222,7 +239,7 @@ __global__ void k_grad(const YoGradArgs a)
                 }
             }
             const int x = a.box[0] + bi, y = a.box[1] + bj, z = a.box[2] + bk;
-            const float kap = a.kappa[c * comp + (size_t)z * plane + (size_t)y * a.nxp + x];
+            const float kap = a.kappa[c * comp + yo_goff(x, y, z, a.ny, a.nxp)];
             const float gk = -ge / (kap * kap);
             if (a.gbox) a.gbox[o] = gk;
             if (c < 2) {
@@ -439,15 +456,26 @@ hipError_t yo_launch_fill(float *p, size_t n, float v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t yo_launch_pitch_copy(const float *src, float *dst, int ncomp, int nz, int ny, int nx,
-                                int sp, int dp, hipStream_t s)
+hipError_t yo_launch_to_ghost(const float *dense, float *ghost, int ncomp, int nz, int ny, int nx,
+                              int nxp, hipStream_t s)
 {
     const size_t n = (size_t)ncomp * nz * ny * nx;
     if (!n) return hipSuccess;
     int blocks = nblk(n);
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_pitch_copy, dim3(blocks), dim3(BS), 0, s, src, dst, ncomp, nz, ny, nx,
-                       sp, dp);
+    hipLaunchKernelGGL(k_to_ghost, dim3(blocks), dim3(BS), 0, s, dense, ghost, ncomp, nz, ny, nx, nxp);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int nz, int ny, int nx,
+                                int nxp, hipStream_t s)
+{
+    const size_t n = (size_t)ncomp * nz * ny * nx;
+    if (!n) return hipSuccess;
+    int blocks = nblk(n);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_from_ghost, dim3(blocks), dim3(BS), 0, s, ghost, dense, ncomp, nz, ny, nx,
+                       nxp);
     return hipGetLastError();
 }
 

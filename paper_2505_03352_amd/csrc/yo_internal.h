@@ -11,6 +11,12 @@
 #define YO_TX 62          // owned x-cells per wave (lanes 1..62; lanes 0 and 63 are halo)
 #define YO_WAVES_PER_BLOCK 4
 
+// Field arrays carry one ghost layer on every face: component c of cell
+// (x, j, k), x in [-1, nx], j in [-1, ny], k in [-1, nz], sits at
+//   c * comp + ((k + 1) * (ny + 2) + (j + 1)) * nxp + (x + 1).
+// Ghosts are zero and never written, which realises the perfect-conductor
+// box (values outside the grid read as zero) without branches.
+
 struct YoPlaneD {
     int axis, index, lo0, lo1, n0, n1;
 };
@@ -18,7 +24,7 @@ struct YoPlaneD {
 // One right-hand side: its own field state, absorbing-layer memories, DFT
 // sums, source plane and per-step phase table.
 struct YoRhsD {
-    float *E[2];             // double-buffered [3][nz][ny][nxp]
+    float *E[2];             // double-buffered, ghost layout
     float *H[2];
     float *psiE[3];          // per axis: [2][slab] (single buffer)
     float *psiH[2][3];       // [buffer][axis]: [2][slab]
@@ -35,31 +41,31 @@ struct YoRhsD {
 
 // One plan (one geometry): shared material and geometry description.
 struct YoPlanD {
-    int nx, ny, nz, nxp;
+    int nx, ny, nz, nxp;     // nxp: padded row pitch of the ghost layout
     float sx, sy, sz, pad0;
     int plo[3], phi[3];      // PML cells low/high per axis
-    const float *kappa;      // [3][nz][ny][nxp]
+    const float *kappa;      // ghost layout (ghost values unused)
     const float *prof[3];    // per axis [6][n_a]: bE cE kiE bH cH kiH
     int box[6];              // x0 y0 z0 bx by bz
     int n_ports;
     int n_steps;
     YoPlaneD ports[YO_MAX_PORTS];
     int mon_off[YO_MAX_PORTS];
+    int mon_total;
     int *step_ctr;           // device step counter of this plan
     int n_rhs;
     int pad1;
     const YoRhsD *rhs;       // [n_rhs]
 };
 
-// Tiles are packed as ty | tx << 11 | tz << 22 (one tile = one wave's work:
-// 62 x-cells, TY rows, kc z-planes).
-#define YO_TILE(tz, tx, ty) ((ty) | ((tx) << 11) | ((tz) << 22))
-
+// A tile is one wave's work: owned x in [x0, x0+xn) (xn <= 62), rows
+// [j0, j0+jn) (jn <= TY), planes [k0, k1).  Packed as int4
+// (x0 | xn << 16, j0 | jn << 16, k0 | k1 << 16, 0).
 struct YoSlot {
     const YoPlanD *plan;
-    const int *tiles;        // tile list of this launch's class (interior or CPML)
+    const int4 *tiles;       // tile list of this launch's class (interior or CPML)
     int rhs0, nrhs;
-    int ntile, kc;
+    int ntile, pad_;
 };
 
 struct YoStepArgs {
@@ -69,6 +75,20 @@ struct YoStepArgs {
     int pad_;
     int prefix[YO_MAX_SLOTS + 1];
     YoSlot slot[YO_MAX_SLOTS];
+};
+
+// Work list of the small per-step kernels (DFT accumulation and source
+// injection): per slot, the plan, its right-hand side range and the number
+// of points per right-hand side.
+struct YoAuxArgs {
+    int n_slots;
+    int k_offset;
+    int total_blocks;
+    int pad_;
+    int prefix[YO_MAX_SLOTS + 1];   // blocks
+    const YoPlanD *plan[YO_MAX_SLOTS];
+    int rhs0[YO_MAX_SLOTS], nrhs[YO_MAX_SLOTS];
+    int npts[YO_MAX_SLOTS];         // points per right-hand side
 };
 
 struct YoCtrArgs {
@@ -101,12 +121,17 @@ struct YoChainBufs {
     float *tmp;       // [S nd][mc]
 };
 
-// ---- kernel launchers (yo_kernels.hip) ----
+// ---- kernel launchers ----
 hipError_t yo_launch_step(int ty, int pml, const YoStepArgs &args, int blocks, hipStream_t s);
+hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
+hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);
 hipError_t yo_launch_fill(float *p, size_t n, float v, hipStream_t s);
-hipError_t yo_launch_pitch_copy(const float *src, float *dst, int ncomp, int nz, int ny, int nx,
-                                int src_pitch, int dst_pitch, hipStream_t s);
+// dense [ncomp][nz][ny][nx] <-> ghost layout ([ncomp][nz+2][ny+2][nxp], origin +1)
+hipError_t yo_launch_to_ghost(const float *dense, float *ghost, int ncomp, int nz, int ny, int nx,
+                              int nxp, hipStream_t s);
+hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int nz, int ny, int nx,
+                                int nxp, hipStream_t s);
 hipError_t yo_launch_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11,
                               hipStream_t s);
 hipError_t yo_launch_alpha(const float2 *mon_dft, const float2 *weights, int n, float2 *out,
@@ -122,7 +147,7 @@ struct YoGradArgs {
     const float2 *EA[YO_MAX_GA];   // adjoint box phasors, index f*n_ports + p
     float sinth[YO_MAX_FREQ];      // sin(w dt / 2) per frequency
     const float2 *coef;            // [n_src][n_ports][n_freq]
-    const float *kappa;            // [3][nz][ny][nxp]
+    const float *kappa;            // ghost layout
     float *gbox;                   // optional [3][bz][by][bx] dF/dkappa
     float *gmap;                   // optional [4][G1][G0] z-summed maps
     int n_src, n_ports, n_freq;
@@ -134,3 +159,9 @@ hipError_t yo_launch_grad_assemble(const YoGradArgs &a, hipStream_t s);
 hipError_t yo_launch_chain_vjp(const YoChainBufs &c, float beta, float *dFdC, hipStream_t s);
 hipError_t yo_launch_zsum(const float *gbox, const int *box, int k_lo, int k_hi, float *gmap, int G0,
                           int G1, hipStream_t s);
+
+// ghost-layout offset of (x, j, k) within one component
+__host__ __device__ inline size_t yo_goff(int x, int j, int k, int ny, int nxp)
+{
+    return ((size_t)(k + 1) * (ny + 2) + (size_t)(j + 1)) * nxp + (size_t)(x + 1);
+}

@@ -104,7 +104,7 @@ struct yo_plan {
     std::vector<float4> steptab;
     std::vector<float> prof;
     std::vector<float2> src_j_host, port_w_host;
-    std::vector<int> tiles_host;
+    std::vector<int4> tiles_host;
     std::vector<float> ginv;     // [n_freq][4]
     std::vector<double> omega_dt;
     std::vector<char> src_set, port_set;
@@ -250,22 +250,48 @@ void build_taps(int S, int n_px, int n_ctl, double r, int tmax, std::vector<int>
     }
 }
 
+// Split [0, n) into pieces of at most `w`, with cuts at the two edges of the
+// interior region [lo, hi) so that no piece straddles them.
+void split_axis(int n, int lo, int hi, int w, std::vector<std::pair<int, int>> &out,
+                std::vector<char> &interior)
+{
+    out.clear();
+    interior.clear();
+    const int cuts[4] = {0, lo, hi, n};
+    for (int seg = 0; seg < 3; ++seg) {
+        for (int a = cuts[seg]; a < cuts[seg + 1]; a += w) {
+            out.emplace_back(a, std::min(w, cuts[seg + 1] - a));
+            interior.push_back(seg == 1);
+        }
+    }
+}
+
+// Tile table: tiles of the interior class first, then the CPML class.  The
+// interior region along each axis is [lo + 1, n - hi) for a CPML of lo/hi
+// cells: there neither an owned site nor a recomputed halo site (one below)
+// meets a nonzero CPML coefficient.
 void build_tiles(yo_plan *p)
 {
-    const int ntx = (p->grid.nx + YO_TX - 1) / YO_TX;
-    const int nty = (p->grid.ny + p->ty - 1) / p->ty;
-    const int ntz = (p->grid.nz + p->kc - 1) / p->kc;
-    std::vector<int> in, pm;
-    for (int tz = 0; tz < ntz; ++tz)
-        for (int tx = 0; tx < ntx; ++tx)
-            for (int ty = 0; ty < nty; ++ty) {
-                const int xa = tx * YO_TX - 1, xb = tx * YO_TX + YO_TX;
-                const int ja = ty * p->ty - 1, jb = ty * p->ty + p->ty;
-                const int ka = tz * p->kc - 1, kb = std::min(tz * p->kc + p->kc, p->grid.nz);
-                const bool pml = (xa < p->plo[0]) || (xb >= p->grid.nx - p->phi[0]) ||
-                                 (ja < p->plo[1]) || (jb >= p->grid.ny - p->phi[1]) ||
-                                 (ka < p->plo[2]) || (kb >= p->grid.nz - p->phi[2]);
-                (pml ? pm : in).push_back(YO_TILE(tz, tx, ty));
+    const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    std::vector<std::pair<int, int>> ax[3];
+    std::vector<char> in_ax[3];
+    const int width[3] = {YO_TX, p->ty, p->kc};
+    for (int a = 0; a < 3; ++a) {
+        const int lo = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
+        const int hi = n[a] - p->phi[a];
+        split_axis(n[a], std::min(lo, hi), hi, width[a], ax[a], in_ax[a]);
+    }
+    std::vector<int4> in, pm;
+    for (size_t iz = 0; iz < ax[2].size(); ++iz)
+        for (size_t ix = 0; ix < ax[0].size(); ++ix)
+            for (size_t iy = 0; iy < ax[1].size(); ++iy) {
+                int4 t;
+                t.x = ax[0][ix].first | (ax[0][ix].second << 16);
+                t.y = ax[1][iy].first | (ax[1][iy].second << 16);
+                t.z = ax[2][iz].first | ((ax[2][iz].first + ax[2][iz].second) << 16);
+                t.w = 0;
+                const bool inner = in_ax[0][ix] && in_ax[1][iy] && in_ax[2][iz];
+                (inner ? in : pm).push_back(t);
             }
     p->n_tile_int = (int)in.size();
     p->n_tile_pml = (int)pm.size();
@@ -275,9 +301,9 @@ void build_tiles(yo_plan *p)
 
 size_t tiles_capacity(const yo_grid &g, int ty_min, int kc_min)
 {
-    const size_t ntx = (g.nx + YO_TX - 1) / YO_TX;
-    const size_t nty = (g.ny + ty_min - 1) / ty_min;
-    const size_t ntz = (g.nz + kc_min - 1) / kc_min;
+    const size_t ntx = g.nx / YO_TX + 4;
+    const size_t nty = g.ny / ty_min + 4;
+    const size_t ntz = g.nz / kc_min + 4;
     return ntx * nty * ntz;
 }
 
@@ -342,7 +368,7 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
         if (g.npml[f] < 0) return fail(YO_EINVAL, "negative npml");
     if (g.npml[0] + g.npml[1] >= g.nx || g.npml[2] + g.npml[3] >= g.ny || g.npml[4] + g.npml[5] >= g.nz)
         return fail(YO_EINVAL, "CPML fills the grid");
-    if (g.nx >= 2048 * YO_TX || g.ny >= 2048 * 4 || g.nz >= 512 * 4)
+    if (g.nx > 65000 || g.ny > 65000 || g.nz > 65000)
         return fail(YO_EUNSUPPORTED, "grid too large for the tile encoding");
     const double dmin = std::min(g.dx, std::min(g.dy, g.dz));
     const double cdt = g.courant * dmin;
@@ -408,8 +434,9 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     p->src_set.assign(n_src, 0);
     p->port_set.assign(n_ports, 0);
 
-    p->nxp = (g.nx + 31) & ~31;
-    p->cells_p = (size_t)g.nz * g.ny * p->nxp;
+    // ghost layout: one zero layer on every face, rows padded to 128 bytes
+    p->nxp = (g.nx + 2 + 31) & ~31;
+    p->cells_p = (size_t)(g.nz + 2) * (g.ny + 2) * p->nxp;
     // CPML slabs (per right-hand side): per axis, E 2 comps + H 2 buffers x 2 comps
     const size_t W[3] = {(size_t)p->plo[0] + p->phi[0], (size_t)p->plo[1] + p->phi[1],
                          (size_t)p->plo[2] + p->phi[2]};
@@ -462,7 +489,7 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     L.add(L.desc_plan, sizeof(YoPlanD));
     L.add(L.desc_rhs, sizeof(YoRhsD) * p->n_rhs);
     L.add(L.ctr, 256);
-    L.add(L.tiles, sizeof(int) * p->tiles_cap);
+    L.add(L.tiles, sizeof(int4) * p->tiles_cap);
     const size_t G = (size_t)p->G0 * p->G1;
     const size_t UV = (size_t)p->U * p->V;
     const size_t DD = (size_t)(p->S * d.md) * (p->S * d.nd);
@@ -554,6 +581,7 @@ static yo_status rebuild_descriptors(yo_plan *p)
     for (int i = 0; i < 6; ++i) P.box[i] = p->box[i];
     P.n_ports = p->n_ports;
     P.n_steps = p->n_steps;
+    P.mon_total = (int)p->mon_total;
     for (int q = 0; q < p->n_ports; ++q) {
         const yo_plane &pl = p->port_planes[q];
         P.ports[q] = YoPlaneD{pl.axis, pl.index, pl.lo0, pl.lo1, pl.n0, pl.n1};
@@ -682,7 +710,7 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     HIPCHK(yo_launch_fill((float *)p->ws, p->L.total / sizeof(float), 0.0f, s));
     if ((st = upload(p, p->L.prof, p->prof.data(), p->prof.size() * sizeof(float), s))) return st;
     if ((st = upload(p, p->L.steptab, p->steptab.data(), p->steptab.size() * sizeof(float4), s))) return st;
-    if ((st = upload(p, p->L.tiles, p->tiles_host.data(), p->tiles_host.size() * sizeof(int), s))) return st;
+    if ((st = upload(p, p->L.tiles, p->tiles_host.data(), p->tiles_host.size() * sizeof(int4), s))) return st;
     const YoChainBufs &c = p->chain;
     if ((st = upload_to(c.tap_lo_x, p->tap_lo_x.data(), p->tap_lo_x.size() * 4, s))) return st;
     if ((st = upload_to(c.tap_n_x, p->tap_n_x.data(), p->tap_n_x.size() * 4, s))) return st;
@@ -715,7 +743,7 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk)
     if (p->ws) {
         // synchronous: the graph cache keys on the tiling, and old graphs may still run
         HIPCHK(hipDeviceSynchronize());
-        HIPCHK(hipMemcpy(p->ws + p->L.tiles.off, p->tiles_host.data(), p->tiles_host.size() * 4,
+        HIPCHK(hipMemcpy(p->ws + p->L.tiles.off, p->tiles_host.data(), p->tiles_host.size() * sizeof(int4),
                          hipMemcpyHostToDevice));
     }
     return YO_OK;
@@ -727,7 +755,7 @@ yo_status yo_set_background(yo_plan *p, const float *kappa, const float *mask, y
     if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
     hipStream_t s = (hipStream_t)stream;
     const yo_grid &g = p->grid;
-    HIPCHK(yo_launch_pitch_copy(kappa, wsp<float>(p, p->L.kappa), 3, g.nz, g.ny, g.nx, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_to_ghost(kappa, wsp<float>(p, p->L.kappa), 3, g.nz, g.ny, g.nx, p->nxp, s));
     HIPCHK(hipMemcpyAsync(p->chain.mask, mask, sizeof(float) * p->U * p->V, hipMemcpyDeviceToDevice, s));
     p->bg_set = true;
     p->design_set = false;
@@ -838,10 +866,39 @@ yo_status yo_reset(yo_plan *p, int which, yo_stream stream)
     return YO_OK;
 }
 
+// Work lists of the per-step DFT and source kernels for a group of plans.
+static void aux_args(yo_plan *const *plans, const int *which, int cnt, bool dft, YoAuxArgs &a)
+{
+    memset(&a, 0, sizeof a);
+    a.n_slots = cnt;
+    int tot = 0;
+    for (int i = 0; i < cnt; ++i) {
+        yo_plan *p = plans[i];
+        int r0, r1;
+        set_rhs_range(p, which[i], r0, r1);
+        int npts = 0;
+        if (dft) {
+            npts = (int)(3 * p->bsz + p->mon_total);
+        } else {
+            for (int r = r0; r < r1; ++r) npts = std::max(npts, 2 * p->hrhs[r].src.n0 * p->hrhs[r].src.n1);
+        }
+        a.plan[i] = wsp<YoPlanD>(p, p->L.desc_plan);
+        a.rhs0[i] = r0;
+        a.nrhs[i] = std::max(r1 - r0, 0);
+        a.npts[i] = npts;
+        a.prefix[i] = tot;
+        tot += (int)(((long)npts * a.nrhs[i] + 255) / 256);
+    }
+    a.prefix[cnt] = tot;
+    a.total_blocks = tot;
+}
+
 // Launch `n_launch` steps (k_offset 0..n_launch-1) of a plan list, then add
-// n_launch to every plan's counter.  Plans must share the tiling rows.
+// n_launch to every plan's counter.  Per step: DFT of E^n (when `with_dft`),
+// the interior tiles, the CPML tiles, the source.  Plans must share the
+// tiling rows.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
-                              hipStream_t s)
+                              bool with_dft, hipStream_t s)
 {
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
@@ -857,11 +914,10 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
                 set_rhs_range(p, which[base + i], r0, r1);
                 YoSlot &sl = a[cls].slot[i];
                 sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
-                sl.tiles = wsp<int>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
+                sl.tiles = wsp<int4>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
                 sl.rhs0 = r0;
                 sl.nrhs = std::max(r1 - r0, 1);
                 sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
-                sl.kc = p->kc;
                 a[cls].prefix[i] = tot;
                 tot += sl.nrhs * sl.ntile;
             }
@@ -869,12 +925,21 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
             a[cls].total_waves = tot;
             blocks[cls] = (tot + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
         }
+        YoAuxArgs ad, as;
+        aux_args(plans + base, which + base, cnt, true, ad);
+        aux_args(plans + base, which + base, cnt, false, as);
         const int ty = plans[base]->ty;
         for (int k = 0; k < n_launch; ++k) {
+            if (with_dft) {
+                ad.k_offset = k;
+                HIPCHK(yo_launch_dft(ad, s));
+            }
             for (int cls = 0; cls < 2; ++cls) {
                 a[cls].k_offset = k;
                 HIPCHK(yo_launch_step(ty, cls, a[cls], blocks[cls], s));
             }
+            as.k_offset = k;
+            HIPCHK(yo_launch_source(as, s));
         }
         YoCtrArgs ca{};
         ca.n = cnt;
@@ -883,6 +948,21 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
         HIPCHK(yo_launch_ctr(ca, 0, s));
     }
     return YO_OK;
+}
+
+// does any plan's DFT window meet the steps [steps_done, steps_done + count)?
+static bool chunk_needs_dft(yo_plan *const *plans, const int *which, int n, int count)
+{
+    for (int i = 0; i < n; ++i) {
+        const yo_plan *p = plans[i];
+        const int a = p->steps_done, b = std::min(p->steps_done + count, p->n_steps);
+        for (int f = 0; f < p->n_freq; ++f) {
+            const int ws = p->freqs[f].win_start, we = ws + p->freqs[f].win_len;
+            if (a < we && b > ws) return true;
+        }
+        (void)which;
+    }
+    return false;
 }
 
 yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_steps, int chunk,
@@ -900,50 +980,60 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
     }
     hipStream_t s = (hipStream_t)stream;
     if (chunk < 1) chunk = 1;
+    // steps_done is advanced per chunk so chunk_needs_dft sees the current steps
+    std::vector<int> start(n);
+    for (int i = 0; i < n; ++i) start[i] = plans[i]->steps_done;
+    auto bump = [&](int k) {
+        for (int i = 0; i < n; ++i) plans[i]->steps_done += k;
+    };
     int done = 0;
     if (use_graph && n_steps >= chunk) {
         std::string key = "c" + std::to_string(chunk) + "t" + std::to_string(plans[0]->ty);
         for (int i = 0; i < n; ++i)
             key += "#" + std::to_string(plans[i]->id) + ":" + std::to_string(plans[i]->generation) +
                    "w" + std::to_string(which[i]) + "k" + std::to_string(plans[i]->kc);
-        GraphEntry ge;
-        {
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            auto it = g_graphs.find(key);
-            if (it != g_graphs.end()) ge = it->second;
-        }
-        if (!ge.exec) {
-            yo_plan *p0 = plans[0];
-            if (!p0->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p0->cap_stream, hipStreamNonBlocking));
-            HIPCHK(hipStreamBeginCapture(p0->cap_stream, hipStreamCaptureModeThreadLocal));
-            yo_status st = launch_steps(plans, which, n, chunk, p0->cap_stream);
-            hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamEndCapture(p0->cap_stream, &graph);
-            if (st) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return st;
-            }
-            if (e != hipSuccess) return fail(YO_EHIP, "graph capture: %s", hipGetErrorString(e));
-            hipGraphExec_t exec = nullptr;
-            HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-            ge.graph = graph;
-            ge.exec = exec;
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            g_graphs[key] = ge;
-        }
+        GraphEntry ge[2];
         while (n_steps - done >= chunk) {
-            HIPCHK(hipGraphLaunch(ge.exec, s));
+            const int variant = chunk_needs_dft(plans, which, n, chunk) ? 1 : 0;
+            const std::string kv = key + (variant ? "|dft" : "|nodft");
+            if (!ge[variant].exec) {
+                std::lock_guard<std::mutex> lk(g_graph_mu);
+                auto it = g_graphs.find(kv);
+                if (it != g_graphs.end()) ge[variant] = it->second;
+            }
+            if (!ge[variant].exec) {
+                yo_plan *p0 = plans[0];
+                if (!p0->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p0->cap_stream, hipStreamNonBlocking));
+                HIPCHK(hipStreamBeginCapture(p0->cap_stream, hipStreamCaptureModeThreadLocal));
+                yo_status st = launch_steps(plans, which, n, chunk, variant == 1, p0->cap_stream);
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamEndCapture(p0->cap_stream, &graph);
+                if (st) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return st;
+                }
+                if (e != hipSuccess) return fail(YO_EHIP, "graph capture: %s", hipGetErrorString(e));
+                hipGraphExec_t exec = nullptr;
+                HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                ge[variant].graph = graph;
+                ge[variant].exec = exec;
+                std::lock_guard<std::mutex> lk(g_graph_mu);
+                g_graphs[kv] = ge[variant];
+            }
+            HIPCHK(hipGraphLaunch(ge[variant].exec, s));
             done += chunk;
+            bump(chunk);
         }
     }
     while (done < n_steps) {
         const int k = std::min(chunk, n_steps - done);
-        yo_status st = launch_steps(plans, which, n, k, s);
+        yo_status st = launch_steps(plans, which, n, k, chunk_needs_dft(plans, which, n, k), s);
         if (st) return st;
         done += k;
+        bump(k);
     }
     for (int i = 0; i < n; ++i)
-        plans[i]->steps_done = std::min(plans[i]->n_steps, plans[i]->steps_done + n_steps);
+        plans[i]->steps_done = std::min(plans[i]->n_steps, start[i] + n_steps);
     return YO_OK;
 }
 
@@ -1074,11 +1164,10 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     a.n_slots = 1;
     YoSlot &sl = a.slot[0];
     sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
-    sl.tiles = wsp<int>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
+    sl.tiles = wsp<int4>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
     sl.rhs0 = r0;
     sl.nrhs = std::max(r1 - r0, 1);
     sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
-    sl.kc = p->kc;
     a.prefix[1] = a.total_waves = sl.nrhs * sl.ntile;
     const int blocks = (a.total_waves + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
     // owned cells of this class and those inside each axis' absorbing slabs
@@ -1087,11 +1176,10 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     const int first = cls ? p->n_tile_int : 0;
     const int last = cls ? p->n_tile_int + p->n_tile_pml : p->n_tile_int;
     for (int t = first; t < last; ++t) {
-        const int code = p->tiles_host[t];
-        const int ty = code & 2047, tx = (code >> 11) & 2047, tz = code >> 22;
-        const int x0 = tx * YO_TX, x1 = std::min(x0 + YO_TX, g.nx);
-        const int y0 = ty * p->ty, y1 = std::min(y0 + p->ty, g.ny);
-        const int z0 = tz * p->kc, z1 = std::min(z0 + p->kc, g.nz);
+        const int4 tt = p->tiles_host[t];
+        const int x0 = tt.x & 0xffff, x1 = x0 + (tt.x >> 16);
+        const int y0 = tt.y & 0xffff, y1 = y0 + (tt.y >> 16);
+        const int z0 = tt.z & 0xffff, z1 = tt.z >> 16;
         own += (double)(x1 - x0) * (y1 - y0) * (z1 - z0);
         if (cls) {
             for (int z = z0; z < z1; ++z)
@@ -1149,8 +1237,8 @@ yo_status yo_set_fields(yo_plan *p, int rhs, const float *E, const float *H, yo_
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(yo_launch_pitch_copy(E, R.E[par], 3, g.nz, g.ny, g.nx, g.nx, p->nxp, s));
-    HIPCHK(yo_launch_pitch_copy(H, R.H[par], 3, g.nz, g.ny, g.nx, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_to_ghost(E, R.E[par], 3, g.nz, g.ny, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_to_ghost(H, R.H[par], 3, g.nz, g.ny, g.nx, p->nxp, s));
     return YO_OK;
 }
 
@@ -1162,8 +1250,8 @@ yo_status yo_get_fields(const yo_plan *p, int rhs, float *E, float *H, yo_stream
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(yo_launch_pitch_copy(R.E[par], E, 3, g.nz, g.ny, g.nx, p->nxp, g.nx, s));
-    HIPCHK(yo_launch_pitch_copy(R.H[par], H, 3, g.nz, g.ny, g.nx, p->nxp, g.nx, s));
+    HIPCHK(yo_launch_from_ghost(R.E[par], E, 3, g.nz, g.ny, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_from_ghost(R.H[par], H, 3, g.nz, g.ny, g.nx, p->nxp, s));
     return YO_OK;
 }
 
@@ -1171,8 +1259,8 @@ yo_status yo_get_kappa(const yo_plan *p, float *kappa, yo_stream stream)
 {
     if (!p || !kappa) return fail(YO_EINVAL, "null argument");
     const yo_grid &g = p->grid;
-    HIPCHK(yo_launch_pitch_copy(reinterpret_cast<const float *>(p->ws + p->L.kappa.off), kappa, 3,
-                                g.nz, g.ny, g.nx, p->nxp, g.nx, (hipStream_t)stream));
+    HIPCHK(yo_launch_from_ghost(reinterpret_cast<const float *>(p->ws + p->L.kappa.off), kappa, 3,
+                                g.nz, g.ny, g.nx, p->nxp, (hipStream_t)stream));
     return YO_OK;
 }
 
