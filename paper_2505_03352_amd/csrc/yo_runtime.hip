@@ -259,9 +259,16 @@ void split_axis(int n, int lo, int hi, int w, std::vector<std::pair<int, int>> &
     interior.clear();
     const int cuts[4] = {0, lo, hi, n};
     for (int seg = 0; seg < 3; ++seg) {
-        for (int a = cuts[seg]; a < cuts[seg + 1]; a += w) {
-            out.emplace_back(a, std::min(w, cuts[seg + 1] - a));
+        const int len = cuts[seg + 1] - cuts[seg];
+        if (len <= 0) continue;
+        // as few pieces as the width allows, sized as evenly as possible
+        const int pieces = (len + w - 1) / w;
+        int a = cuts[seg];
+        for (int q = 0; q < pieces; ++q) {
+            const int sz = len / pieces + (q < len % pieces ? 1 : 0);
+            out.emplace_back(a, sz);
             interior.push_back(seg == 1);
+            a += sz;
         }
     }
 }
@@ -919,7 +926,9 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
                 sl.nrhs = std::max(r1 - r0, 1);
                 sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
                 a[cls].prefix[i] = tot;
-                tot += sl.nrhs * sl.ntile;
+                // waves come in groups of YO_WAVES_PER_BLOCK tiles per right-hand side
+                const int groups = (sl.ntile + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
+                tot += sl.nrhs * groups * YO_WAVES_PER_BLOCK;
             }
             a[cls].prefix[cnt] = tot;
             a[cls].total_waves = tot;
@@ -1168,7 +1177,8 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     sl.rhs0 = r0;
     sl.nrhs = std::max(r1 - r0, 1);
     sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
-    a.prefix[1] = a.total_waves = sl.nrhs * sl.ntile;
+    a.prefix[1] = a.total_waves =
+        sl.nrhs * ((sl.ntile + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK) * YO_WAVES_PER_BLOCK;
     const int blocks = (a.total_waves + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
     // owned cells of this class and those inside each axis' absorbing slabs
     const yo_grid &g = p->grid;

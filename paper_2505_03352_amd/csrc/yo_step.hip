@@ -308,10 +308,17 @@ __global__ __launch_bounds__(256) void k_yee_step(const YoStepArgs a)
     const YoPlanD &P = *sl.plan;
     const int step = *P.step_ctr + a.k_offset;
     if (step >= P.n_steps) return;
-    // right-hand sides of one tile are adjacent waves (they share kappa)
+    // A block's four waves take four consecutive tiles (adjacent row blocks)
+    // of one right-hand side, so the halo rows one wave recomputes are the
+    // rows its neighbour loads at the same time; consecutive blocks take the
+    // same tiles for the next right-hand sides, which share kappa.
     const int local = wave - a.prefix[s];
-    const int r = sl.rhs0 + local % sl.nrhs;
-    const int4 t = sl.tiles[local / sl.nrhs];
+    const int grp = local / (YO_WAVES_PER_BLOCK * sl.nrhs);
+    const int in_grp = local - grp * (YO_WAVES_PER_BLOCK * sl.nrhs);
+    const int r = sl.rhs0 + in_grp / YO_WAVES_PER_BLOCK;
+    const int ti = grp * YO_WAVES_PER_BLOCK + in_grp % YO_WAVES_PER_BLOCK;
+    if (ti >= sl.ntile) return;
+    const int4 t = sl.tiles[ti];
     wave_step<TY, PML>(P, P.rhs[r], step, t, lane);
 }
 
