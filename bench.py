@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="plain launches instead of HIP-graph replays (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -125,7 +127,7 @@ def main():
 
     def step(Cc):
         plan.set_design(Cc, beta)
-        plan.run(YO_BOTH, chunk=args.chunk, use_graph=True)
+        plan.run(YO_BOTH, chunk=args.chunk, use_graph=not args.eager)
         a = plan.alpha()
         g = plan.gradient(torch.conj(a))
         Cn = torch.clamp(Cc + 1e-3 * g / (g.abs().max() + 1e-30), 0.0, 1.0)
