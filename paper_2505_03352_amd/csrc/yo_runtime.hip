@@ -444,6 +444,10 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     // ghost layout: one zero layer on every face, rows padded to 128 bytes
     p->nxp = (g.nx + 2 + 31) & ~31;
     p->cells_p = (size_t)(g.nz + 2) * (g.ny + 2) * p->nxp;
+    if (3 * p->cells_p * sizeof(float) >= ((size_t)1 << 31)) {
+        delete p;
+        return fail(YO_EUNSUPPORTED, "one field array (3 components) must stay below 2 GiB");
+    }
     // CPML slabs (per right-hand side): per axis, E 2 comps + H 2 buffers x 2 comps
     const size_t W[3] = {(size_t)p->plo[0] + p->phi[0], (size_t)p->plo[1] + p->phi[1],
                          (size_t)p->plo[2] + p->phi[2]};

@@ -49,6 +49,24 @@ __device__ __forceinline__ float shfl_prev(float v)   // value of lane-1
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Raw buffer access: the resource (base, size) and the row offset are
+// wave-uniform scalars, the only per-lane operand is the column offset, so a
+// load costs no vector address arithmetic.  Reads past the buffer return 0.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc rsrc_of(const float *p, size_t n_floats)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0,
+                                             (int)(n_floats * sizeof(float)), 0x00020000);
+}
+__device__ __forceinline__ float bload(Rsrc r, int voff, int soff)
+{
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, voff, soff, 0);
+}
+
 __device__ __forceinline__ int slab_index(int u, int n, int lo, int hi)
 {
     if (u < 0 || u >= n) return -1;
@@ -86,25 +104,26 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
                                           const int4 t, const int lane)
 {
     const int nx = P.nx, ny = P.ny, nz = P.nz, nxp = P.nxp;
-    const size_t rows = (size_t)(ny + 2);
+    const int rows = ny + 2;
     const size_t comp = (size_t)(nz + 2) * rows * nxp;
+    const int compb = (int)(comp * sizeof(float));          // component stride in bytes
     const int par = step & 1;
-    const float *__restrict__ Eo = R.E[par];
-    float *__restrict__ En = R.E[par ^ 1];
-    const float *__restrict__ Ho = R.H[par];
-    float *__restrict__ Hn = R.H[par ^ 1];
-    const float *__restrict__ K = P.kappa;
+    const Rsrc Eo = rsrc_of(R.E[par], 3 * comp);
+    const Rsrc En = rsrc_of(R.E[par ^ 1], 3 * comp);
+    const Rsrc Ho = rsrc_of(R.H[par], 3 * comp);
+    const Rsrc Hn = rsrc_of(R.H[par ^ 1], 3 * comp);
+    const Rsrc K = rsrc_of(P.kappa, 3 * comp);
     const float sx = P.sx, sy = P.sy, sz = P.sz;
 
     const int x0 = t.x & 0xffff, xn = t.x >> 16;
     const int j0 = t.y & 0xffff, jn = t.y >> 16;
     const int k0 = t.z & 0xffff, k1 = t.z >> 16;
     const int x = x0 - 1 + lane;
-    const int xo = clampi(x, -1, nx) + 1;                 // storage column (ghost clamped)
+    const int xo = (clampi(x, -1, nx) + 1) * (int)sizeof(float);   // column byte offset (ghost clamped)
     const bool own_x = (lane >= 1) && (lane <= xn);
-    // wave-uniform row offset of (j, k) in the ghost layout
-    auto ro = [&](int j, int k) -> size_t {
-        return ((size_t)(k + 1) * rows + (size_t)(clampi(j, -1, ny) + 1)) * nxp;
+    // wave-uniform byte offset of row (j, k) in the ghost layout
+    auto ro = [&](int j, int k) -> int {
+        return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * nxp * (int)sizeof(float);
     };
 
     // ---- CPML data of this lane along x (CPML class only) ----
@@ -127,9 +146,9 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 
 #pragma unroll
     for (int r = 0; r < TY + 2; ++r) {
-        const size_t o = ro(j0 - 1 + r, k0 - 1) + xo;
+        const int o = ro(j0 - 1 + r, k0 - 1);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Ec[c][r] = Eo[c * comp + o];
+        for (int c = 0; c < 3; ++c) Ec[c][r] = bload(Eo, xo, c * compb + o);
     }
 #pragma unroll
     for (int r = 0; r < TY; ++r) { Hp[0][r] = 0.0f; Hp[1][r] = 0.0f; }
@@ -140,21 +159,21 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
         float Ho_[3][TY + 1], Kv[3][TY];
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r) {
-            const size_t o = ro(j0 - 1 + r, k + 1) + xo;
+            const int o = ro(j0 - 1 + r, k + 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Enx[c][r] = Eo[c * comp + o];
+            for (int c = 0; c < 3; ++c) Enx[c][r] = bload(Eo, xo, c * compb + o);
         }
 #pragma unroll
         for (int r = 0; r <= TY; ++r) {
-            const size_t o = ro(j0 - 1 + r, k) + xo;
+            const int o = ro(j0 - 1 + r, k);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Ho_[c][r] = Ho[c * comp + o];
+            for (int c = 0; c < 3; ++c) Ho_[c][r] = bload(Ho, xo, c * compb + o);
         }
 #pragma unroll
         for (int r = 1; r <= TY; ++r) {
-            const size_t o = ro(j0 - 1 + r, k) + xo;
+            const int o = ro(j0 - 1 + r, k);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Kv[c][r - 1] = K[c * comp + o];
+            for (int c = 0; c < 3; ++c) Kv[c][r - 1] = bload(K, xo, c * compb + o);
         }
         int pz = -1;
         if (PML) pz = slab_index(k, nz, P.plo[2], P.phi[2]);
@@ -213,10 +232,10 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             Hc[1][r] = hy;
             Hc[2][r] = hz;
             if (own) {
-                float *hrow = Hn + ro(j, k) + xo;
-                hrow[0] = hx;
-                hrow[comp] = hy;
-                hrow[2 * comp] = hz;
+                const int o = ro(j, k);
+                bstore(hx, Hn, xo, o);
+                bstore(hy, Hn, xo, compb + o);
+                bstore(hz, Hn, xo, 2 * compb + o);
             }
         }
         // ---------------- E at plane k, rows j0 .. j0+jn-1 ----------------
@@ -272,10 +291,10 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             ey = (x == 0 || k == 0) ? 0.0f : ey;
             ez = (x == 0 || j == 0) ? 0.0f : ez;
             if (own_x) {
-                float *erow = En + ro(j, k) + xo;
-                erow[0] = ex;
-                erow[comp] = ey;
-                erow[2 * comp] = ez;
+                const int o = ro(j, k);
+                bstore(ex, En, xo, o);
+                bstore(ey, En, xo, compb + o);
+                bstore(ez, En, xo, 2 * compb + o);
             }
         }
 #pragma unroll
