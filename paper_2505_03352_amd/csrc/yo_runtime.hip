@@ -288,10 +288,12 @@ void build_tiles(yo_plan *p)
         const int hi = n[a] - p->phi[a];
         split_axis(n[a], std::min(lo, hi), hi, width[a], ax[a], in_ax[a]);
     }
+    // x fastest: the four waves of a block take neighbouring x-strips of the
+    // same rows, so together they stream contiguous row segments
     std::vector<int4> in, pm;
     for (size_t iz = 0; iz < ax[2].size(); ++iz)
-        for (size_t ix = 0; ix < ax[0].size(); ++ix)
-            for (size_t iy = 0; iy < ax[1].size(); ++iy) {
+        for (size_t iy = 0; iy < ax[1].size(); ++iy)
+            for (size_t ix = 0; ix < ax[0].size(); ++ix) {
                 int4 t;
                 t.x = ax[0][ix].first | (ax[0][ix].second << 16);
                 t.y = ax[1][iy].first | (ax[1][iy].second << 16);

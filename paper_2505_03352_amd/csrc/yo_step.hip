@@ -327,10 +327,10 @@ __global__ __launch_bounds__(256) void k_yee_step(const YoStepArgs a)
     const YoPlanD &P = *sl.plan;
     const int step = *P.step_ctr + a.k_offset;
     if (step >= P.n_steps) return;
-    // A block's four waves take four consecutive tiles (adjacent row blocks)
-    // of one right-hand side, so the halo rows one wave recomputes are the
-    // rows its neighbour loads at the same time; consecutive blocks take the
-    // same tiles for the next right-hand sides, which share kappa.
+    // A block's four waves take four consecutive tiles (neighbouring x-strips
+    // of the same rows) of one right-hand side, so together they stream
+    // contiguous row segments; consecutive blocks take the same tiles for the
+    // next right-hand sides, which share kappa.
     const int local = wave - a.prefix[s];
     const int grp = local / (YO_WAVES_PER_BLOCK * sl.nrhs);
     const int in_grp = local - grp * (YO_WAVES_PER_BLOCK * sl.nrhs);
