@@ -180,7 +180,7 @@ def main():
                                "1.50/1.55/1.60 um, 1 forward + 1 adjoint each (6 right-hand "
                                "sides), 10000 steps, forward+adjoint+gradient per step",
                    "cells": dev.cells, "rhs": plan.n_rhs, "time_steps": dev.n_steps,
-                   "tiling": [tuned["rows"], tuned["zchunk"]] if tuned else None},
+                   "tiling": [tuned["rows"], tuned["zchunk"], tuned["flags"]] if tuned else None},
         "gradients_per_hour": round(3.6e6 / ms, 1),
         "hbm_frac_whole_step": round(eff_gbs / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -171,9 +171,12 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n_plans, 
 /* Host-side step count of the last reset/advance of `plan`. */
 yo_status yo_steps_done(const yo_plan *plan, int *steps);
 
-/* Tile shape of the time-stepping kernel: rows per wave (4 or 8) and
- * z-planes per wave (>= 1).  Results do not depend on it (bitwise). */
-yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk);
+/* Tile shape of the time-stepping kernel: rows per wave (4 or 8), z-planes
+ * per wave (>= 4) and flags (bit 0: the CPML x-strips are full 62-cell
+ * strips instead of just the absorbing columns; bit 1: 8 waves per block
+ * instead of 4).  Results do not depend on it (bitwise).  Synchronises the
+ * device. */
+yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);
 
 /* Modal coefficients (Appendix A) of the forward right-hand sides:
  * dev_alpha complex64 [n_src][n_ports][n_freq]. */

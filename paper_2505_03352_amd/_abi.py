@@ -76,7 +76,7 @@ _SIGS = {
     "yo_finalize": [_P, _I, _S],
     "yo_advance_many": [ct.POINTER(_P), ct.POINTER(_I), _I, _I, _I, _I, _S],
     "yo_steps_done": [_P, ct.POINTER(_I)],
-    "yo_set_tiling": [_P, _I, _I],
+    "yo_set_tiling": [_P, _I, _I, _I],
     "yo_alpha": [_P, _P, _S],
     "yo_gradient": [_P, _P, _P, _S],
     "yo_gradient_kappa": [_P, _P, _P, _S],

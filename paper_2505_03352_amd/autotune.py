@@ -19,8 +19,10 @@ import torch
 
 from ._abi import YO_BOTH
 
-CANDIDATES: Tuple[Tuple[int, int], ...] = ((4, 8), (4, 16), (4, 32), (4, 64), (8, 8), (8, 16),
-                                           (8, 32))
+# (rows per wave, z-planes per wave, flags): flag 1 = full-width CPML x-strips,
+# flag 2 = 8 waves per block
+CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
+    (r, z, f) for r in (4, 8) for z in (8, 16, 32) for f in (0, 1, 2, 3))
 _lock = threading.Lock()
 
 
@@ -71,26 +73,26 @@ def tune(plan, which: int = YO_BOTH, candidates: Optional[Iterable] = None, n_la
         with _lock:
             rec = _load().get(key)
         if rec:
-            plan.set_tiling(rec["rows"], rec["zchunk"])
+            plan.set_tiling(rec["rows"], rec["zchunk"], rec.get("flags", 0))
             return dict(rec, cached=True)
     timings = {}
     nz = plan.grid["nz"]
-    for rows, zc in (candidates or CANDIDATES):
+    for rows, zc, fl in (candidates or CANDIDATES):
         if zc > nz and zc != 8:
             continue
-        plan.set_tiling(rows, zc)
+        plan.set_tiling(rows, zc, fl)
         plan.reset(which, stream)
         t0 = 0.0
         for cls in (0, 1):
             plan.time_kernel(cls, 1, stream)          # warm-up
             ms, _, _ = plan.time_kernel(cls, n_launch, stream)
             t0 += ms
-        timings[f"{rows}x{zc}"] = t0
+        timings[f"{rows}x{zc}x{fl}"] = t0
     best = min(timings, key=timings.get)
-    rows, zc = (int(v) for v in best.split("x"))
-    plan.set_tiling(rows, zc)
+    rows, zc, fl = (int(v) for v in best.split("x"))
+    plan.set_tiling(rows, zc, fl)
     plan.reset(which, stream)
-    rec = dict(rows=rows, zchunk=zc, ms_per_step=timings[best], timings=timings)
+    rec = dict(rows=rows, zchunk=zc, flags=fl, ms_per_step=timings[best], timings=timings)
     if use_cache:
         with _lock:
             d = _load()

@@ -9,7 +9,7 @@
 #define YO_MAX_PORTS 8
 #define YO_MAX_SLOTS 32
 #define YO_TX 62          // owned x-cells per wave (lanes 1..62; lanes 0 and 63 are halo)
-#define YO_WAVES_PER_BLOCK 4
+#define YO_MAX_WPB 8      // waves per block of the step kernel: 4 or 8
 
 // Field arrays carry one ghost layer on every face: component c of cell
 // (x, j, k), x in [-1, nx], j in [-1, ny], k in [-1, nz], sits at
@@ -72,7 +72,7 @@ struct YoStepArgs {
     int n_slots;
     int k_offset;            // launch index inside the chunk; step = counter + k_offset
     int total_waves;
-    int pad_;
+    int wpb;                 // waves per block (4 or 8)
     int prefix[YO_MAX_SLOTS + 1];
     YoSlot slot[YO_MAX_SLOTS];
 };

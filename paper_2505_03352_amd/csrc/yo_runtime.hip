@@ -108,7 +108,7 @@ struct yo_plan {
     std::vector<float> ginv;     // [n_freq][4]
     std::vector<double> omega_dt;
     std::vector<char> src_set, port_set;
-    int ty = 4, kc = 16;
+    int ty = 4, kc = 16, tflags = 0;   // tflags: 1 = merge CPML x-strips, 2 = 8 waves per block
     int n_tile_int = 0, n_tile_pml = 0;
     bool bg_set = false, design_set = false;
     double beta = 0;
@@ -284,9 +284,16 @@ void build_tiles(yo_plan *p)
     std::vector<char> in_ax[3];
     const int width[3] = {YO_TX, p->ty, p->kc};
     for (int a = 0; a < 3; ++a) {
-        const int lo = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
-        const int hi = n[a] - p->phi[a];
-        split_axis(n[a], std::min(lo, hi), hi, width[a], ax[a], in_ax[a]);
+        int lo = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
+        int hi = n[a] - p->phi[a];
+        if (a == 0 && (p->tflags & 1)) {
+            // full-width CPML strips: the shell strips also carry interior columns
+            if (p->plo[0] > 0) lo = std::max(lo, std::min(YO_TX, n[0]));
+            if (p->phi[0] > 0) hi = std::min(hi, n[0] - YO_TX);
+        }
+        hi = std::max(hi, 0);
+        lo = std::min(lo, hi);
+        split_axis(n[a], lo, hi, width[a], ax[a], in_ax[a]);
     }
     // x fastest: the four waves of a block take neighbouring x-strips of the
     // same rows, so together they stream contiguous row segments
@@ -744,13 +751,15 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     return YO_OK;
 }
 
-yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk)
+yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
     if (rows != 4 && rows != 8) return fail(YO_EINVAL, "rows must be 4 or 8");
     if (zchunk < 4) return fail(YO_EINVAL, "zchunk must be >= 4");
+    if (flags & ~3) return fail(YO_EINVAL, "unknown tiling flags");
     p->ty = rows;
     p->kc = zchunk;
+    p->tflags = flags;
     build_tiles(p);
     if (p->tiles_host.size() > p->tiles_cap) return fail(YO_EINVAL, "internal: tile table");
     if (p->ws) {
@@ -917,6 +926,7 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
         YoStepArgs a[2];
         int blocks[2];
+        const int wpb = (plans[base]->tflags & 2) ? 8 : 4;
         for (int cls = 0; cls < 2; ++cls) {
             memset(&a[cls], 0, sizeof(YoStepArgs));
             a[cls].n_slots = cnt;
@@ -932,13 +942,14 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
                 sl.nrhs = std::max(r1 - r0, 1);
                 sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
                 a[cls].prefix[i] = tot;
-                // waves come in groups of YO_WAVES_PER_BLOCK tiles per right-hand side
-                const int groups = (sl.ntile + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
-                tot += sl.nrhs * groups * YO_WAVES_PER_BLOCK;
+                // waves come in groups of wpb tiles per right-hand side
+                const int groups = (sl.ntile + wpb - 1) / wpb;
+                tot += sl.nrhs * groups * wpb;
             }
             a[cls].prefix[cnt] = tot;
             a[cls].total_waves = tot;
-            blocks[cls] = (tot + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
+            a[cls].wpb = wpb;
+            blocks[cls] = (tot + wpb - 1) / wpb;
         }
         YoAuxArgs ad, as;
         aux_args(plans + base, which + base, cnt, true, ad);
@@ -989,7 +1000,8 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         yo_plan *p = plans[i];
         if (!p || !p->ws) return fail(YO_EWORKSPACE, "plan %d has no workspace", i);
         if (which[i] != p->active) return fail(YO_ESTATE, "plan %d: which differs from its reset", i);
-        if (p->ty != plans[0]->ty) return fail(YO_EINVAL, "plans in one call must share the tiling rows");
+        if (p->ty != plans[0]->ty || (p->tflags & 2) != (plans[0]->tflags & 2))
+            return fail(YO_EINVAL, "plans in one call must share the tiling rows and block size");
         for (int j = 0; j < i; ++j)
             if (plans[j] == p) return fail(YO_EINVAL, "plan listed twice");
     }
@@ -1006,7 +1018,8 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         std::string key = "c" + std::to_string(chunk) + "t" + std::to_string(plans[0]->ty);
         for (int i = 0; i < n; ++i)
             key += "#" + std::to_string(plans[i]->id) + ":" + std::to_string(plans[i]->generation) +
-                   "w" + std::to_string(which[i]) + "k" + std::to_string(plans[i]->kc);
+                   "w" + std::to_string(which[i]) + "k" + std::to_string(plans[i]->kc) + "f" +
+                   std::to_string(plans[i]->tflags);
         GraphEntry ge[2];
         while (n_steps - done >= chunk) {
             const int variant = chunk_needs_dft(plans, which, n, chunk) ? 1 : 0;
@@ -1183,9 +1196,10 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     sl.rhs0 = r0;
     sl.nrhs = std::max(r1 - r0, 1);
     sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
-    a.prefix[1] = a.total_waves =
-        sl.nrhs * ((sl.ntile + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK) * YO_WAVES_PER_BLOCK;
-    const int blocks = (a.total_waves + YO_WAVES_PER_BLOCK - 1) / YO_WAVES_PER_BLOCK;
+    const int wpb = (p->tflags & 2) ? 8 : 4;
+    a.wpb = wpb;
+    a.prefix[1] = a.total_waves = sl.nrhs * ((sl.ntile + wpb - 1) / wpb) * wpb;
+    const int blocks = (a.total_waves + wpb - 1) / wpb;
     // owned cells of this class and those inside each axis' absorbing slabs
     const yo_grid &g = p->grid;
     double own = 0.0, in_pml = 0.0;

@@ -311,14 +311,15 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 }
 
 template <int TY, bool PML>
-__global__ __launch_bounds__(256) void k_yee_step(const YoStepArgs a)
+__global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
     const int q = nb >> 3, rem = nb & 7, xcd = b & 7, pos = b >> 3;
     const int lb = (xcd < rem) ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
+    const int wpb = a.wpb;
     // the wave index is the same in every lane: say so, so that everything
     // derived from it (slot, tile, row offsets) lives in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane(lb * YO_WAVES_PER_BLOCK + (int)(threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(lb * wpb + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (wave >= a.total_waves) return;
     int s = 0;
@@ -327,15 +328,15 @@ __global__ __launch_bounds__(256) void k_yee_step(const YoStepArgs a)
     const YoPlanD &P = *sl.plan;
     const int step = *P.step_ctr + a.k_offset;
     if (step >= P.n_steps) return;
-    // A block's four waves take four consecutive tiles (neighbouring x-strips
-    // of the same rows) of one right-hand side, so together they stream
+    // A block's waves take consecutive tiles (neighbouring x-strips of the
+    // same rows) of one right-hand side, so together they stream
     // contiguous row segments; consecutive blocks take the same tiles for the
     // next right-hand sides, which share kappa.
     const int local = wave - a.prefix[s];
-    const int grp = local / (YO_WAVES_PER_BLOCK * sl.nrhs);
-    const int in_grp = local - grp * (YO_WAVES_PER_BLOCK * sl.nrhs);
-    const int r = sl.rhs0 + in_grp / YO_WAVES_PER_BLOCK;
-    const int ti = grp * YO_WAVES_PER_BLOCK + in_grp % YO_WAVES_PER_BLOCK;
+    const int grp = local / (wpb * sl.nrhs);
+    const int in_grp = local - grp * (wpb * sl.nrhs);
+    const int r = sl.rhs0 + in_grp / wpb;
+    const int ti = grp * wpb + in_grp % wpb;
     if (ti >= sl.ntile) return;
     const int4 t = sl.tiles[ti];
     wave_step<TY, PML>(P, P.rhs[r], step, t, lane);
@@ -447,14 +448,16 @@ __global__ void k_ctr(const YoCtrArgs a, int set_value)
 hipError_t yo_launch_step(int ty, int pml, const YoStepArgs &args, int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
+    if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
+    const dim3 blk(64 * args.wpb);
     if (ty == 4 && !pml)
-        hipLaunchKernelGGL((k_yee_step<4, false>), dim3(blocks), dim3(256), 0, s, args);
+        hipLaunchKernelGGL((k_yee_step<4, false>), dim3(blocks), blk, 0, s, args);
     else if (ty == 4 && pml)
-        hipLaunchKernelGGL((k_yee_step<4, true>), dim3(blocks), dim3(256), 0, s, args);
+        hipLaunchKernelGGL((k_yee_step<4, true>), dim3(blocks), blk, 0, s, args);
     else if (ty == 8 && !pml)
-        hipLaunchKernelGGL((k_yee_step<8, false>), dim3(blocks), dim3(256), 0, s, args);
+        hipLaunchKernelGGL((k_yee_step<8, false>), dim3(blocks), blk, 0, s, args);
     else if (ty == 8 && pml)
-        hipLaunchKernelGGL((k_yee_step<8, true>), dim3(blocks), dim3(256), 0, s, args);
+        hipLaunchKernelGGL((k_yee_step<8, true>), dim3(blocks), blk, 0, s, args);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -160,8 +160,9 @@ class Plan:
         self.beta = float(beta)
         self._C = C
 
-    def set_tiling(self, rows: int, zchunk: int):
-        call("yo_set_tiling", self._h, int(rows), int(zchunk))
+    def set_tiling(self, rows: int, zchunk: int, flags: int = 0):
+        call("yo_set_tiling", self._h, int(rows), int(zchunk), int(flags))
+        self.tiling = (int(rows), int(zchunk), int(flags))
 
     # ----------------------------------------------------------- stepping
     def run(self, which=YO_BOTH, chunk=64, use_graph=True, stream=None):

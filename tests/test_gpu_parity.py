@@ -129,20 +129,20 @@ def test_fields_match_oracle_with_cpml_and_source():
     dt = 0.5 * 40e-9 / 299792458.0
     f = FreqSpec(w_dt / dt, 40.0, steps - 60, 60)
     outs = {}
-    for rows, zc in [(4, 16), (8, 8), (4, 4), (8, 64)]:
-        say(f"cpml+source fields tiling=({rows},{zc})")
+    for rows, zc, fl in [(4, 16, 0), (8, 8, 1), (4, 4, 2), (8, 64, 3)]:
+        say(f"cpml+source fields tiling=({rows},{zc},{fl})")
         p = Plan(grid, design, steps, [f], [pl], [], device="cuda")
         p.bind()
         p.set_background(torch.as_tensor(kap, dtype=torch.float32), torch.zeros(p.canvas_shape))
         p.set_source_mode(0, h)
-        p.set_tiling(rows, zc)
+        p.set_tiling(rows, zc, fl)
         p.reset(1)
         p.advance(1, steps)
         E, H = p.get_fields(0)
-        outs[(rows, zc)] = (E.cpu().numpy(), H.cpu().numpy())
+        outs[(rows, zc, fl)] = (E.cpu().numpy(), H.cpu().numpy())
         p.close()
     # every tiling gives bitwise the same fields
-    ref = outs[(4, 16)]
+    ref = outs[(4, 16, 0)]
     for k, v in outs.items():
         assert np.array_equal(v[0], ref[0]) and np.array_equal(v[1], ref[1]), k
     # against the FP64 oracle
