@@ -143,6 +143,34 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     float Ec[3][TY + 2], Enx[3][TY + 2];
     float Hp[2][TY];          // Ht_x, Ht_y of the previous plane, rows j0..j0+TY-1
     float Hc[3][TY + 1];      // Ht of the current plane, rows j0-1..j0+TY-1
+    float Ho_[3][TY + 1], Kv[3][TY];
+
+    // Operands of plane k are in registers when plane k starts: E(k) in Ec,
+    // E(k+1) in Enx, old Ht(k) in Ho_, kappa(k) in Kv.  The loads for plane
+    // k+1 are issued before plane k's stores, because the vector-memory
+    // counter also counts stores and a wait placed after them would wait for
+    // the stores too.
+    auto load_plane = [&](int k, float (&en)[3][TY + 2], float (&ho)[3][TY + 1],
+                          float (&kv)[3][TY]) {
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r) {
+            const int o = ro(j0 - 1 + r, k + 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) en[c][r] = bload(Eo, xo, c * compb + o);
+        }
+#pragma unroll
+        for (int r = 0; r <= TY; ++r) {
+            const int o = ro(j0 - 1 + r, k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ho[c][r] = bload(Ho, xo, c * compb + o);
+        }
+#pragma unroll
+        for (int r = 1; r <= TY; ++r) {
+            const int o = ro(j0 - 1 + r, k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) kv[c][r - 1] = bload(K, xo, c * compb + o);
+        }
+    };
 
 #pragma unroll
     for (int r = 0; r < TY + 2; ++r) {
@@ -152,29 +180,13 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     }
 #pragma unroll
     for (int r = 0; r < TY; ++r) { Hp[0][r] = 0.0f; Hp[1][r] = 0.0f; }
+    load_plane(k0 - 1, Enx, Ho_, Kv);
 
     for (int k = k0 - 1; k < k1; ++k) {
         const bool own_k = (k >= k0);
-        // ---- all loads of this plane first ----
-        float Ho_[3][TY + 1], Kv[3][TY];
-#pragma unroll
-        for (int r = 0; r < TY + 2; ++r) {
-            const int o = ro(j0 - 1 + r, k + 1);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Enx[c][r] = bload(Eo, xo, c * compb + o);
-        }
-#pragma unroll
-        for (int r = 0; r <= TY; ++r) {
-            const int o = ro(j0 - 1 + r, k);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Ho_[c][r] = bload(Ho, xo, c * compb + o);
-        }
-#pragma unroll
-        for (int r = 1; r <= TY; ++r) {
-            const int o = ro(j0 - 1 + r, k);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Kv[c][r - 1] = bload(K, xo, c * compb + o);
-        }
+        float Enx2[3][TY + 2], Ho2[3][TY + 1], Kv2[3][TY];
+        // unconditional (the last plane re-reads itself) so the wait counts stay exact
+        load_plane(k + 1 < k1 ? k + 1 : k, Enx2, Ho2, Kv2);
         int pz = -1;
         if (PML) pz = slab_index(k, nz, P.plo[2], P.phi[2]);
 
@@ -305,7 +317,20 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Ec[c][r] = Enx[c][r];
+            for (int c = 0; c < 3; ++c) {
+                Ec[c][r] = Enx[c][r];
+                Enx[c][r] = Enx2[c][r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r <= TY; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Ho_[c][r] = Ho2[c][r];
+        }
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Kv[c][r] = Kv2[c][r];
         }
     }
 }
