@@ -110,14 +110,17 @@ def main():
     log(f"workload {dev.name}: {dev.nx}x{dev.ny}x{dev.nz}, {len(dev.wavelengths)} wavelengths, "
         f"{dev.n_steps} steps")
     plan = plan_for(dev, device="cuda:0")
-    # a plain copy of known size: the reference the HBM counters are scaled by
-    cal_bytes = 256 << 20
+    # a plain copy of known size, its source pushed out of the 256 MB
+    # last-level cache first: the reference the HBM counters are scaled by
+    cal_bytes = 1 << 30
     cal_src = torch.ones(cal_bytes // 4, dtype=torch.float32, device="cuda:0")
+    evict = torch.zeros((512 << 20) // 4, dtype=torch.float32, device="cuda:0")
     cal_dst = torch.empty_like(cal_src)
+    torch.cuda.synchronize()
     cal_dst.copy_(cal_src)
     torch.cuda.synchronize()
     log(f"calibration copy: {cal_bytes} bytes read, {cal_bytes} bytes written")
-    del cal_src, cal_dst
+    del cal_src, cal_dst, evict
     tuned = None
     if not args.no_autotune:
         tuned = autotune.tune(plan, YO_BOTH, use_cache=False)

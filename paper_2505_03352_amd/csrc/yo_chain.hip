@@ -22,32 +22,33 @@ __global__ void k_fill(float *p, size_t n, float v)
         p[i] = v;
 }
 
-// dense [ncomp][nz][ny][nx] -> ghost layout (interior only; ghosts untouched)
-__global__ void k_to_ghost(const float *src, float *dst, int ncomp, int nz, int ny, int nx, int nxp)
+// dense [ncomp][nz][ny][nx] -> components c0.. of a ghost-layout array of nc
+// components (interior only; ghosts untouched)
+__global__ void k_to_ghost(const float *src, float *dst, int ncomp, int c0, int nc, int nz, int ny,
+                           int nx, int nxp)
 {
     const size_t n = (size_t)ncomp * nz * ny * nx;
-    const size_t gcomp = (size_t)(nz + 2) * (ny + 2) * nxp;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         size_t q = i;
         const int x = (int)(q % nx); q /= nx;
         const int y = (int)(q % ny); q /= ny;
         const int z = (int)(q % nz); q /= nz;
-        dst[q * gcomp + yo_goff(x, y, z, ny, nxp)] = src[i];
+        dst[yo_off(c0 + (int)q, x, y, z, ny, nxp, nc)] = src[i];
     }
 }
 
-__global__ void k_from_ghost(const float *src, float *dst, int ncomp, int nz, int ny, int nx, int nxp)
+__global__ void k_from_ghost(const float *src, float *dst, int ncomp, int c0, int nc, int nz, int ny,
+                             int nx, int nxp)
 {
     const size_t n = (size_t)ncomp * nz * ny * nx;
-    const size_t gcomp = (size_t)(nz + 2) * (ny + 2) * nxp;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         size_t q = i;
         const int x = (int)(q % nx); q /= nx;
         const int y = (int)(q % ny); q /= ny;
         const int z = (int)(q % nz); q /= nz;
-        dst[i] = src[q * gcomp + yo_goff(x, y, z, ny, nxp)];
+        dst[i] = src[yo_off(c0 + (int)q, x, y, z, ny, nxp, nc)];
     }
 }
 
@@ -192,16 +193,15 @@ __global__ void k_smooth(YoChainBufs c, float *kappa, int nx, int ny, int nz, in
     c.aux[4 * gsz + pix] = gxy;
     c.aux[5 * gsz + pix] = gyy;
     const int x = i0 - 2 + m, y = j0 - 2 + n;
-    const size_t comp = (size_t)(nz + 2) * (ny + 2) * nxp;
     for (int k = k_lo; k <= k_hi; ++k) {
-        const size_t o = yo_goff(x, y, k, ny, nxp);
-        kappa[o] = kx;
-        kappa[comp + o] = ky;
+        kappa[yo_off(0, x, y, k, ny, nxp, 3)] = kx;
+        kappa[yo_off(1, x, y, k, ny, nxp, 3)] = ky;
     }
-    for (int k = k_lo; k < k_hi; ++k) kappa[2 * comp + yo_goff(x, y, k, ny, nxp)] = kzi;
-    kappa[2 * comp + yo_goff(x, y, k_lo - 1, ny, nxp)] = kzf;
-    kappa[2 * comp + yo_goff(x, y, k_hi, ny, nxp)] = kzf;
+    for (int k = k_lo; k < k_hi; ++k) kappa[yo_off(2, x, y, k, ny, nxp, 3)] = kzi;
+    kappa[yo_off(2, x, y, k_lo - 1, ny, nxp, 3)] = kzf;
+    kappa[yo_off(2, x, y, k_hi, ny, nxp, 3)] = kzf;
     (void)nx;
+    (void)nz;
 }
 
 // ------------------------------------------------------------- Eq. (1)
@@ -216,7 +216,6 @@ __global__ void k_grad(const YoGradArgs a)
     if (i >= bx * by) return;
     const int bj = i / bx, bi = i - bj * bx;
     const size_t bsz = (size_t)bx * by * bz;
-    const size_t comp = (size_t)(a.nz + 2) * (a.ny + 2) * a.nxp;
     float sx = 0.0f, sy = 0.0f, szi = 0.0f, szf = 0.0f;
     for (int c = 0; c < 3; ++c) {
         for (int bk = 0; bk < bz; ++bk) {
@@ -239,7 +238,7 @@ __global__ void k_grad(const YoGradArgs a)
                 }
             }
             const int x = a.box[0] + bi, y = a.box[1] + bj, z = a.box[2] + bk;
-            const float kap = a.kappa[c * comp + yo_goff(x, y, z, a.ny, a.nxp)];
+            const float kap = a.kappa[yo_off(c, x, y, z, a.ny, a.nxp, 3)];
             const float gk = -ge / (kap * kap);
             if (a.gbox) a.gbox[o] = gk;
             if (c < 2) {
@@ -456,26 +455,27 @@ hipError_t yo_launch_fill(float *p, size_t n, float v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t yo_launch_to_ghost(const float *dense, float *ghost, int ncomp, int nz, int ny, int nx,
-                              int nxp, hipStream_t s)
+hipError_t yo_launch_to_ghost(const float *dense, float *ghost, int ncomp, int c0, int nc, int nz,
+                              int ny, int nx, int nxp, hipStream_t s)
 {
     const size_t n = (size_t)ncomp * nz * ny * nx;
     if (!n) return hipSuccess;
     int blocks = nblk(n);
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_to_ghost, dim3(blocks), dim3(BS), 0, s, dense, ghost, ncomp, nz, ny, nx, nxp);
+    hipLaunchKernelGGL(k_to_ghost, dim3(blocks), dim3(BS), 0, s, dense, ghost, ncomp, c0, nc, nz, ny,
+                       nx, nxp);
     return hipGetLastError();
 }
 
-hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int nz, int ny, int nx,
-                                int nxp, hipStream_t s)
+hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int c0, int nc, int nz,
+                                int ny, int nx, int nxp, hipStream_t s)
 {
     const size_t n = (size_t)ncomp * nz * ny * nx;
     if (!n) return hipSuccess;
     int blocks = nblk(n);
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_from_ghost, dim3(blocks), dim3(BS), 0, s, ghost, dense, ncomp, nz, ny, nx,
-                       nxp);
+    hipLaunchKernelGGL(k_from_ghost, dim3(blocks), dim3(BS), 0, s, ghost, dense, ncomp, c0, nc, nz,
+                       ny, nx, nxp);
     return hipGetLastError();
 }
 

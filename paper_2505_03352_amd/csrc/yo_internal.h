@@ -11,11 +11,15 @@
 #define YO_TX 62          // owned x-cells per wave (lanes 1..62; lanes 0 and 63 are halo)
 #define YO_MAX_WPB 8      // waves per block of the step kernel: 4 or 8
 
-// Field arrays carry one ghost layer on every face: component c of cell
-// (x, j, k), x in [-1, nx], j in [-1, ny], k in [-1, nz], sits at
-//   c * comp + ((k + 1) * (ny + 2) + (j + 1)) * nxp + (x + 1).
-// Ghosts are zero and never written, which realises the perfect-conductor
-// box (values outside the grid read as zero) without branches.
+// Field arrays carry one ghost layer on every face and keep the components
+// of one (j, k) row together: component c of cell (x, j, k), x in [-1, nx],
+// j in [-1, ny], k in [-1, nz], of an array with nc components sits at
+//   (((k + 1) * (ny + 2) + (j + 1)) * nc + c) * nxp + (x + 1).
+// The state of one right-hand side and step parity is one such array with
+// nc = 6 (Ex Ey Ez Ht_x Ht_y Ht_z), kappa one with nc = 3, so a row group
+// of all components is one contiguous block of memory.  Ghosts are zero and
+// never written, which realises the perfect-conductor box (values outside
+// the grid read as zero) without branches.
 
 struct YoPlaneD {
     int axis, index, lo0, lo1, n0, n1;
@@ -24,8 +28,7 @@ struct YoPlaneD {
 // One right-hand side: its own field state, absorbing-layer memories, DFT
 // sums, source plane and per-step phase table.
 struct YoRhsD {
-    float *E[2];             // double-buffered, ghost layout
-    float *H[2];
+    float *F[2];             // double-buffered state, ghost layout, nc = 6 (E then Ht)
     float *psiE[3];          // per axis: [2][slab] (single buffer)
     float *psiH[2][3];       // [buffer][axis]: [2][slab]
     float2 *dft_box;         // [3][bz][by][bx]
@@ -127,11 +130,12 @@ hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);
 hipError_t yo_launch_fill(float *p, size_t n, float v, hipStream_t s);
-// dense [ncomp][nz][ny][nx] <-> ghost layout ([ncomp][nz+2][ny+2][nxp], origin +1)
-hipError_t yo_launch_to_ghost(const float *dense, float *ghost, int ncomp, int nz, int ny, int nx,
-                              int nxp, hipStream_t s);
-hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int nz, int ny, int nx,
-                                int nxp, hipStream_t s);
+// dense [ncomp][nz][ny][nx] <-> components c0 .. c0+ncomp-1 of a ghost-layout
+// array with nc components
+hipError_t yo_launch_to_ghost(const float *dense, float *ghost, int ncomp, int c0, int nc, int nz,
+                              int ny, int nx, int nxp, hipStream_t s);
+hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int c0, int nc, int nz,
+                                int ny, int nx, int nxp, hipStream_t s);
 hipError_t yo_launch_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11,
                               hipStream_t s);
 hipError_t yo_launch_alpha(const float2 *mon_dft, const float2 *weights, int n, float2 *out,
@@ -160,8 +164,8 @@ hipError_t yo_launch_chain_vjp(const YoChainBufs &c, float beta, float *dFdC, hi
 hipError_t yo_launch_zsum(const float *gbox, const int *box, int k_lo, int k_hi, float *gmap, int G0,
                           int G1, hipStream_t s);
 
-// ghost-layout offset of (x, j, k) within one component
-__host__ __device__ inline size_t yo_goff(int x, int j, int k, int ny, int nxp)
+// ghost-layout offset of component c of (x, j, k) in an array of nc components
+__host__ __device__ inline size_t yo_off(int c, int x, int j, int k, int ny, int nxp, int nc)
 {
-    return ((size_t)(k + 1) * (ny + 2) + (size_t)(j + 1)) * nxp + (size_t)(x + 1);
+    return (((size_t)(k + 1) * (ny + 2) + (size_t)(j + 1)) * nc + c) * nxp + (size_t)(x + 1);
 }

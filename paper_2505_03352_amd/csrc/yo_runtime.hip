@@ -453,9 +453,9 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     // ghost layout: one zero layer on every face, rows padded to 128 bytes
     p->nxp = (g.nx + 2 + 31) & ~31;
     p->cells_p = (size_t)(g.nz + 2) * (g.ny + 2) * p->nxp;
-    if (3 * p->cells_p * sizeof(float) >= ((size_t)1 << 31)) {
+    if (6 * p->cells_p * sizeof(float) >= ((size_t)1 << 31)) {
         delete p;
-        return fail(YO_EUNSUPPORTED, "one field array (3 components) must stay below 2 GiB");
+        return fail(YO_EUNSUPPORTED, "one state array (6 components) must stay below 2 GiB");
     }
     // CPML slabs (per right-hand side): per axis, E 2 comps + H 2 buffers x 2 comps
     const size_t W[3] = {(size_t)p->plo[0] + p->phi[0], (size_t)p->plo[1] + p->phi[1],
@@ -622,10 +622,8 @@ static yo_status rebuild_descriptors(yo_plan *p)
     for (int r = 0; r < p->n_rhs; ++r) {
         YoRhsD &R = p->hrhs[r];
         float *f = fields + fields_per_rhs(p) * r;
-        R.E[0] = f;
-        R.E[1] = f + 3 * p->cells_p;
-        R.H[0] = f + 6 * p->cells_p;
-        R.H[1] = f + 9 * p->cells_p;
+        R.F[0] = f;
+        R.F[1] = f + 6 * p->cells_p;
         float *ps = psi + p->psi_per_rhs * r;
         for (int a = 0; a < 3; ++a) {
             float *base = ps + p->psi_axis_off[a];
@@ -777,7 +775,7 @@ yo_status yo_set_background(yo_plan *p, const float *kappa, const float *mask, y
     if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
     hipStream_t s = (hipStream_t)stream;
     const yo_grid &g = p->grid;
-    HIPCHK(yo_launch_to_ghost(kappa, wsp<float>(p, p->L.kappa), 3, g.nz, g.ny, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_to_ghost(kappa, wsp<float>(p, p->L.kappa), 3, 0, 3, g.nz, g.ny, g.nx, p->nxp, s));
     HIPCHK(hipMemcpyAsync(p->chain.mask, mask, sizeof(float) * p->U * p->V, hipMemcpyDeviceToDevice, s));
     p->bg_set = true;
     p->design_set = false;
@@ -1267,8 +1265,8 @@ yo_status yo_set_fields(yo_plan *p, int rhs, const float *E, const float *H, yo_
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(yo_launch_to_ghost(E, R.E[par], 3, g.nz, g.ny, g.nx, p->nxp, s));
-    HIPCHK(yo_launch_to_ghost(H, R.H[par], 3, g.nz, g.ny, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_to_ghost(E, R.F[par], 3, 0, 6, g.nz, g.ny, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_to_ghost(H, R.F[par], 3, 3, 6, g.nz, g.ny, g.nx, p->nxp, s));
     return YO_OK;
 }
 
@@ -1280,8 +1278,8 @@ yo_status yo_get_fields(const yo_plan *p, int rhs, float *E, float *H, yo_stream
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(yo_launch_from_ghost(R.E[par], E, 3, g.nz, g.ny, g.nx, p->nxp, s));
-    HIPCHK(yo_launch_from_ghost(R.H[par], H, 3, g.nz, g.ny, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_from_ghost(R.F[par], E, 3, 0, 6, g.nz, g.ny, g.nx, p->nxp, s));
+    HIPCHK(yo_launch_from_ghost(R.F[par], H, 3, 3, 6, g.nz, g.ny, g.nx, p->nxp, s));
     return YO_OK;
 }
 
@@ -1290,7 +1288,7 @@ yo_status yo_get_kappa(const yo_plan *p, float *kappa, yo_stream stream)
     if (!p || !kappa) return fail(YO_EINVAL, "null argument");
     const yo_grid &g = p->grid;
     HIPCHK(yo_launch_from_ghost(reinterpret_cast<const float *>(p->ws + p->L.kappa.off), kappa, 3,
-                                g.nz, g.ny, g.nx, p->nxp, (hipStream_t)stream));
+                                0, 3, g.nz, g.ny, g.nx, p->nxp, (hipStream_t)stream));
     return YO_OK;
 }
 

@@ -105,14 +105,14 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 {
     const int nx = P.nx, ny = P.ny, nz = P.nz, nxp = P.nxp;
     const int rows = ny + 2;
-    const size_t comp = (size_t)(nz + 2) * rows * nxp;
-    const int compb = (int)(comp * sizeof(float));          // component stride in bytes
+    const size_t groups = (size_t)(nz + 2) * rows;           // row groups (j, k)
+    const int rowb = nxp * (int)sizeof(float);                // one component row, bytes
     const int par = step & 1;
-    const Rsrc Eo = rsrc_of(R.E[par], 3 * comp);
-    const Rsrc En = rsrc_of(R.E[par ^ 1], 3 * comp);
-    const Rsrc Ho = rsrc_of(R.H[par], 3 * comp);
-    const Rsrc Hn = rsrc_of(R.H[par ^ 1], 3 * comp);
-    const Rsrc K = rsrc_of(P.kappa, 3 * comp);
+    // state: 6 component rows per group (E then Ht); kappa: 3
+    const Rsrc Fo = rsrc_of(R.F[par], 6 * groups * nxp);
+    const Rsrc Fn = rsrc_of(R.F[par ^ 1], 6 * groups * nxp);
+    const Rsrc K = rsrc_of(P.kappa, 3 * groups * nxp);
+    const int eb = 0, hb = 3 * rowb;                          // E and Ht within a state group
     const float sx = P.sx, sy = P.sy, sz = P.sz;
 
     const int x0 = t.x & 0xffff, xn = t.x >> 16;
@@ -121,9 +121,12 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     const int x = x0 - 1 + lane;
     const int xo = (clampi(x, -1, nx) + 1) * (int)sizeof(float);   // column byte offset (ghost clamped)
     const bool own_x = (lane >= 1) && (lane <= xn);
-    // wave-uniform byte offset of row (j, k) in the ghost layout
+    // wave-uniform byte offsets of row group (j, k) in the state and kappa arrays
     auto ro = [&](int j, int k) -> int {
-        return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * nxp * (int)sizeof(float);
+        return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 6 * rowb;
+    };
+    auto rk = [&](int j, int k) -> int {
+        return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 3 * rowb;
     };
 
     // ---- CPML data of this lane along x (CPML class only) ----
@@ -156,19 +159,19 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
         for (int r = 0; r < TY + 2; ++r) {
             const int o = ro(j0 - 1 + r, k + 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) en[c][r] = bload(Eo, xo, c * compb + o);
+            for (int c = 0; c < 3; ++c) en[c][r] = bload(Fo, xo, eb + c * rowb + o);
         }
 #pragma unroll
         for (int r = 0; r <= TY; ++r) {
             const int o = ro(j0 - 1 + r, k);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ho[c][r] = bload(Ho, xo, c * compb + o);
+            for (int c = 0; c < 3; ++c) ho[c][r] = bload(Fo, xo, hb + c * rowb + o);
         }
 #pragma unroll
         for (int r = 1; r <= TY; ++r) {
-            const int o = ro(j0 - 1 + r, k);
+            const int o = rk(j0 - 1 + r, k);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) kv[c][r - 1] = bload(K, xo, c * compb + o);
+            for (int c = 0; c < 3; ++c) kv[c][r - 1] = bload(K, xo, c * rowb + o);
         }
     };
 
@@ -176,7 +179,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     for (int r = 0; r < TY + 2; ++r) {
         const int o = ro(j0 - 1 + r, k0 - 1);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Ec[c][r] = bload(Eo, xo, c * compb + o);
+        for (int c = 0; c < 3; ++c) Ec[c][r] = bload(Fo, xo, eb + c * rowb + o);
     }
 #pragma unroll
     for (int r = 0; r < TY; ++r) { Hp[0][r] = 0.0f; Hp[1][r] = 0.0f; }
@@ -244,10 +247,10 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             Hc[1][r] = hy;
             Hc[2][r] = hz;
             if (own) {
-                const int o = ro(j, k);
-                bstore(hx, Hn, xo, o);
-                bstore(hy, Hn, xo, compb + o);
-                bstore(hz, Hn, xo, 2 * compb + o);
+                const int o = ro(j, k) + hb;
+                bstore(hx, Fn, xo, o);
+                bstore(hy, Fn, xo, rowb + o);
+                bstore(hz, Fn, xo, 2 * rowb + o);
             }
         }
         // ---------------- E at plane k, rows j0 .. j0+jn-1 ----------------
@@ -303,10 +306,10 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             ey = (x == 0 || k == 0) ? 0.0f : ey;
             ez = (x == 0 || j == 0) ? 0.0f : ez;
             if (own_x) {
-                const int o = ro(j, k);
-                bstore(ex, En, xo, o);
-                bstore(ey, En, xo, compb + o);
-                bstore(ez, En, xo, 2 * compb + o);
+                const int o = ro(j, k) + eb;
+                bstore(ex, Fn, xo, o);
+                bstore(ey, Fn, xo, rowb + o);
+                bstore(ez, Fn, xo, 2 * rowb + o);
             }
         }
 #pragma unroll
@@ -394,8 +397,7 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
     const int w = step - R.win_start;
     if (w < 0 || w >= R.win_len) return;
     const float4 st = R.steptab[step];
-    const size_t comp = (size_t)(P.nz + 2) * (P.ny + 2) * P.nxp;
-    const float *E = R.E[step & 1];
+    const float *F = R.F[step & 1];
     const int bx = P.box[3], by = P.box[4], bz = P.box[5];
     const int bsz = bx * by * bz;
     float e;
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
         const int c = q / bsz, rem = q - c * bsz;
         const int bk = rem / (bx * by), rem2 = rem - bk * bx * by;
         const int bj = rem2 / bx, bi = rem2 - bj * bx;
-        e = E[c * comp + yo_goff(P.box[0] + bi, P.box[1] + bj, P.box[2] + bk, P.ny, P.nxp)];
+        e = F[yo_off(c, P.box[0] + bi, P.box[1] + bj, P.box[2] + bk, P.ny, P.nxp, 6)];
         acc = R.dft_box + q;
     } else {
         const int qm = q - 3 * bsz;
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
         const int cx = sel3(pl.axis, pl.index, pl.lo0 + ai, pl.lo0 + ai);
         const int cy = sel3(pl.axis, pl.lo0 + ai, pl.index, pl.lo1 + b);
         const int cz = sel3(pl.axis, pl.lo1 + b, pl.lo1 + b, pl.index);
-        e = E[c * comp + yo_goff(cx, cy, cz, P.ny, P.nxp)];
+        e = F[yo_off(c, cx, cy, cz, P.ny, P.nxp, 6)];
         acc = R.dft_mon + qm;
     }
     float2 v = *acc;
@@ -449,12 +451,11 @@ __global__ __launch_bounds__(256) void k_source(const YoAuxArgs a)
     const int cx = sel3(pl.axis, pl.index, pl.lo0 + ai, pl.lo0 + ai);
     const int cy = sel3(pl.axis, pl.lo0 + ai, pl.index, pl.lo1 + b);
     const int cz = sel3(pl.axis, pl.lo1 + b, pl.lo1 + b, pl.index);
-    const size_t comp = (size_t)(P.nz + 2) * (P.ny + 2) * P.nxp;
-    const size_t o = c * comp + yo_goff(cx, cy, cz, P.ny, P.nxp);
+    const size_t o = yo_off(c, cx, cy, cz, P.ny, P.nxp, 6);
     const float2 jv = R.src_j[q];
     const float j = fmaf(jv.x, st.x, jv.y * st.y);
-    float *E = R.E[(step + 1) & 1];
-    E[o] = fmaf(-P.kappa[o], j, E[o]);
+    float *F = R.F[(step + 1) & 1];
+    F[o] = fmaf(-P.kappa[yo_off(c, cx, cy, cz, P.ny, P.nxp, 3)], j, F[o]);
 }
 
 __global__ void k_ctr(const YoCtrArgs a, int set_value)
