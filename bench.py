@@ -93,12 +93,22 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="plain launches instead of HIP-graph replays (for counter collection)")
+    ap.add_argument("--workload", choices=("realistic", "batch", "serving"), default="realistic",
+                    help="realistic: the headline line; batch / serving: the batched and served "
+                         "forms against one-at-a-time solves (their own JSON line)")
+    ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the right-hand sides shard across GPUs without exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     import torch
     from paper_2505_03352_amd import YO_BOTH, autotune
@@ -157,13 +167,18 @@ def main():
     plan.advance(YO_BOTH, 4)
     plan.time_kernel(0, 3)
     k_ms, k_bytes, k_cells = plan.time_kernel(0, 30)
-    p_ms, p_bytes, p_cells = plan.time_kernel(1, 30)
+    p_ms = p_bytes = 0.0
+    for cls in range(1, 8):
+        plan.time_kernel(cls, 2)
+        c_ms, c_bytes, _ = plan.time_kernel(cls, 30)
+        p_ms += c_ms
+        p_bytes += c_bytes
     torch.cuda.synchronize()
     achieved = k_bytes / (k_ms / 1e3) / 1e9
     sha = kernel_sha()
     traffic = read_traffic(sha, k_bytes)
     log(f"interior kernel {k_ms:.3f} ms/launch, {achieved:.0f} GB/s algorithmic; "
-        f"CPML kernel {p_ms:.3f} ms/launch ({p_bytes / (p_ms / 1e3) / 1e9:.0f} GB/s)")
+        f"CPML classes {p_ms:.3f} ms/step ({p_bytes / max(p_ms / 1e3, 1e-12) / 1e9:.0f} GB/s)")
 
     out = {
         "metric": METRIC,
@@ -197,6 +212,97 @@ def main():
         out["cpu_baseline"] = cpu_baseline(dev, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def _line(metric, value, unit, ms, args, cfg, extra):
+    out = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": round(ms, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": cfg}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """8 designs of uneven size (1 wavelength, forward + adjoint each):
+    shared launches with graph replays against one design at a time with
+    plain launches, equal steps and windows."""
+    import torch
+    from paper_2505_03352_amd import batch
+    from paper_2505_03352_amd.plan import plan_for
+    from workloads import configs
+    torch.cuda.set_device(0)
+    devs = configs.batch(8)
+    log("batch: " + ", ".join(f"{d.nx}x{d.ny}x{d.nz}/{d.n_steps}" for d in devs))
+    cells = sum(2 * d.cells * d.n_steps for d in devs)
+    plans = [plan_for(d, device="cuda:0") for d in devs]
+    batch.shared_tiling(plans, 4, 1, zchunk=16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.solve(plans, chunk=args.chunk, use_graph=True)
+    res_b = [(a.cpu().numpy(), g.cpu().numpy()) for a, g in batch.gradients(plans)]
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batched: {t_batch:.2f} s")
+    t0 = time.perf_counter()
+    same = True
+    for p, (a0, g0) in zip(plans, res_b):
+        p.run(3, chunk=args.chunk, use_graph=False)
+        a = p.alpha()
+        g = p.gradient(torch.conj(a))
+        same &= bool((a.cpu().numpy() == a0).all() and (g.cpu().numpy() == g0).all())
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"one at a time: {t_seq:.2f} s, identical results: {same}")
+    for p in plans:
+        p.close()
+    _line("designs/hour (batched, 8 uneven designs)", 3600 * len(devs) / t_batch, "designs/h",
+          t_batch * 1e3, args,
+          {"workload": "batch: 8 designs, axes uniform in 128..320 x 96..240 x 64..96 at 20 nm, "
+                       "1 wavelength, forward + adjoint + gradient each, seeds 100..107"},
+          {"gcell_updates_per_s": round(cells / t_batch / 1e9, 3),
+           "one_at_a_time": {"designs_per_h": round(3600 * len(devs) / t_seq, 1),
+                             "gcell_updates_per_s": round(cells / t_seq / 1e9, 3),
+                             "seconds": round(t_seq, 3)},
+           "speedup": round(t_seq / t_batch, 3), "identical_results": same})
+
+
+def bench_serving(args):
+    """The first N requests of the Poisson trace (4 req/s): continuous
+    batching with `--slots` concurrent requests against one request at a
+    time on the same trace."""
+    import torch
+    from paper_2505_03352_amd.serve import GpuExecutor, Request, Scheduler
+    from workloads import configs
+    torch.cuda.set_device(0)
+    trace = configs.serving_trace()[:args.requests]
+
+    def build(p):
+        i, cls, lams = p
+        return configs.serving_request(i, cls, lams)
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    out = {}
+    for name, slots in (("served", args.slots), ("one_at_a_time", 1)):
+        ex = GpuExecutor(build, device="cuda:0", tiling=(4, 16, 1), chunk=args.chunk)
+        reqs = [Request(i, t, (i, cls, lams)) for i, (t, cls, lams) in enumerate(trace)]
+        st = Scheduler(ex, max_slots=slots, hbm_budget=budget, chunk=args.chunk).run(reqs)
+        torch.cuda.synchronize()
+        out[name] = st
+        log(f"{name}: {st.as_dict()}")
+    s, b = out["served"], out["one_at_a_time"]
+    _line("p50/p99 request latency and designs/hour (continuous batching)", s.throughput_per_h,
+          "designs/h", s.makespan_s * 1e3, args,
+          {"workload": f"serving: first {args.requests} of 200 Poisson arrivals at 4 req/s, "
+                       "sizes 96^3+-8 / 200x160x80 / 320x240x96, 1-3 wavelengths, forward + "
+                       "adjoint + gradient, seed 200", "slots": args.slots,
+           "hbm_budget_bytes": budget},
+          {"p50_s": round(s.p50_s, 3), "p99_s": round(s.p99_s, 3),
+           "gcell_updates_per_s": round(s.cell_updates / s.makespan_s / 1e9, 3),
+           "one_at_a_time": {"designs_per_h": round(b.throughput_per_h, 1),
+                             "p50_s": round(b.p50_s, 3), "p99_s": round(b.p99_s, 3),
+                             "gcell_updates_per_s": round(b.cell_updates / b.makespan_s / 1e9, 3)}})
 
 
 if __name__ == "__main__":

@@ -221,16 +221,18 @@ yo_status yo_get_kappa(const yo_plan *plan, float *dev_kappa, yo_stream stream);
 yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
                          double *cell_updates_per_step);
 
-/* Measurement: time `n_launch` launches of one class of the time-stepping
- * kernel (cls 0: tiles clear of the CPML, cls 1: tiles touching it) over the
+/* Measurement: time `n_launch` launches of one tile class of the
+ * time-stepping kernel (cls 0..7; bit 0/1/2 set: the tiles touch the x/y/z
+ * absorbing slabs, so cls 0 is the interior; an empty class reports zeros
+ * and launches nothing) over the
  * right-hand sides selected by the last yo_reset, at the current step, with
  * HIP events on `stream`; blocks until done.  The launches re-run the same
  * step (they read the current buffers and do not advance the counter), so
  * call it only outside the DFT window or after the results were read.
  * avg_ms: mean duration of one launch; bytes: algorithmic HBM bytes one
  * launch must move (48 per owned cell and right-hand side, plus 12 per
- * owned cell for kappa, plus 32 per CPML axis and right-hand side for class
- * 1 cells inside an absorbing slab); cells: owned cell-updates per launch. */
+ * owned cell for kappa, plus 32 per CPML axis and right-hand side for cells
+ * inside an absorbing slab); cells: owned cell-updates per launch. */
 yo_status yo_time_kernel(yo_plan *plan, int cls, int n_launch, float *avg_ms, double *bytes,
                          double *cells, yo_stream stream);
 

@@ -23,6 +23,7 @@ from ._abi import YO_BOTH
 # flag 2 = 8 waves per block
 CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
     (r, z, f) for r in (4, 8) for z in (8, 16, 32) for f in (0, 1, 2, 3))
+N_CLASSES = 8      # tile classes of the step kernel (interior + 7 CPML classes)
 _lock = threading.Lock()
 
 
@@ -83,7 +84,7 @@ def tune(plan, which: int = YO_BOTH, candidates: Optional[Iterable] = None, n_la
         plan.set_tiling(rows, zc, fl)
         plan.reset(which, stream)
         t0 = 0.0
-        for cls in (0, 1):
+        for cls in range(N_CLASSES):
             plan.time_kernel(cls, 1, stream)          # warm-up
             ms, _, _ = plan.time_kernel(cls, n_launch, stream)
             t0 += ms

@@ -66,7 +66,7 @@ struct YoPlanD {
 // (x0 | xn << 16, j0 | jn << 16, k0 | k1 << 16, 0).
 struct YoSlot {
     const YoPlanD *plan;
-    const int4 *tiles;       // tile list of this launch's class (interior or CPML)
+    const int4 *tiles;       // tile list of this launch's class
     int rhs0, nrhs;
     int ntile, pad_;
 };
@@ -125,7 +125,8 @@ struct YoChainBufs {
 };
 
 // ---- kernel launchers ----
-hipError_t yo_launch_step(int ty, int pml, const YoStepArgs &args, int blocks, hipStream_t s);
+// pm: tile class, bit 0/1/2 = the tiles touch the x/y/z absorbing slabs
+hipError_t yo_launch_step(int ty, int pm, const YoStepArgs &args, int blocks, hipStream_t s);
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);

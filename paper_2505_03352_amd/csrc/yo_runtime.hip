@@ -109,7 +109,7 @@ struct yo_plan {
     std::vector<double> omega_dt;
     std::vector<char> src_set, port_set;
     int ty = 4, kc = 16, tflags = 0;   // tflags: 1 = merge CPML x-strips, 2 = 8 waves per block
-    int n_tile_int = 0, n_tile_pml = 0;
+    int cls_off[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // tile table offsets per class (8 classes)
     bool bg_set = false, design_set = false;
     double beta = 0;
     int steps_done = 0;
@@ -273,10 +273,11 @@ void split_axis(int n, int lo, int hi, int w, std::vector<std::pair<int, int>> &
     }
 }
 
-// Tile table: tiles of the interior class first, then the CPML class.  The
-// interior region along each axis is [lo + 1, n - hi) for a CPML of lo/hi
-// cells: there neither an owned site nor a recomputed halo site (one below)
-// meets a nonzero CPML coefficient.
+// Tile table, grouped by class.  Bit a of a tile's class is set when the
+// tile's sites along axis a (owned, and the recomputed halo one below) can
+// meet a nonzero CPML coefficient of that axis; the region clear of the
+// axis' slabs is [lo + 1, n - hi) for a CPML of lo/hi cells.  Class 0 is the
+// interior.
 void build_tiles(yo_plan *p)
 {
     const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
@@ -295,9 +296,9 @@ void build_tiles(yo_plan *p)
         lo = std::min(lo, hi);
         split_axis(n[a], lo, hi, width[a], ax[a], in_ax[a]);
     }
-    // x fastest: the four waves of a block take neighbouring x-strips of the
+    // x fastest: the waves of a block take neighbouring x-strips of the
     // same rows, so together they stream contiguous row segments
-    std::vector<int4> in, pm;
+    std::vector<int4> byc[8];
     for (size_t iz = 0; iz < ax[2].size(); ++iz)
         for (size_t iy = 0; iy < ax[1].size(); ++iy)
             for (size_t ix = 0; ix < ax[0].size(); ++ix) {
@@ -306,13 +307,15 @@ void build_tiles(yo_plan *p)
                 t.y = ax[1][iy].first | (ax[1][iy].second << 16);
                 t.z = ax[2][iz].first | ((ax[2][iz].first + ax[2][iz].second) << 16);
                 t.w = 0;
-                const bool inner = in_ax[0][ix] && in_ax[1][iy] && in_ax[2][iz];
-                (inner ? in : pm).push_back(t);
+                const int c = (in_ax[0][ix] ? 0 : 1) | (in_ax[1][iy] ? 0 : 2) | (in_ax[2][iz] ? 0 : 4);
+                byc[c].push_back(t);
             }
-    p->n_tile_int = (int)in.size();
-    p->n_tile_pml = (int)pm.size();
-    p->tiles_host = in;
-    p->tiles_host.insert(p->tiles_host.end(), pm.begin(), pm.end());
+    p->tiles_host.clear();
+    for (int c = 0; c < 8; ++c) {
+        p->cls_off[c] = (int)p->tiles_host.size();
+        p->tiles_host.insert(p->tiles_host.end(), byc[c].begin(), byc[c].end());
+    }
+    p->cls_off[8] = (int)p->tiles_host.size();
 }
 
 size_t tiles_capacity(const yo_grid &g, int ty_min, int kc_min)
@@ -913,42 +916,48 @@ static void aux_args(yo_plan *const *plans, const int *which, int cnt, bool dft,
     a.total_blocks = tot;
 }
 
+// Fill the step-kernel arguments of tile class `cls` for a plan list;
+// returns the number of blocks (0: no plan has tiles of that class).
+static int step_args(yo_plan *const *plans, const int *which, int cnt, int cls, int wpb, YoStepArgs &a)
+{
+    memset(&a, 0, sizeof(YoStepArgs));
+    a.n_slots = cnt;
+    int tot = 0;
+    for (int i = 0; i < cnt; ++i) {
+        yo_plan *p = plans[i];
+        int r0, r1;
+        set_rhs_range(p, which[i], r0, r1);
+        YoSlot &sl = a.slot[i];
+        sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
+        sl.tiles = wsp<int4>(p, p->L.tiles) + p->cls_off[cls];
+        sl.rhs0 = r0;
+        sl.nrhs = std::max(r1 - r0, 1);
+        sl.ntile = (r1 > r0) ? p->cls_off[cls + 1] - p->cls_off[cls] : 0;
+        a.prefix[i] = tot;
+        // waves come in groups of wpb tiles per right-hand side
+        const int groups = (sl.ntile + wpb - 1) / wpb;
+        tot += sl.nrhs * groups * wpb;
+    }
+    a.prefix[cnt] = tot;
+    a.total_waves = tot;
+    a.wpb = wpb;
+    return (tot + wpb - 1) / wpb;
+}
+
 // Launch `n_launch` steps (k_offset 0..n_launch-1) of a plan list, then add
 // n_launch to every plan's counter.  Per step: DFT of E^n (when `with_dft`),
-// the interior tiles, the CPML tiles, the source.  Plans must share the
-// tiling rows.
+// one step launch per non-empty tile class, the source.  Plans must share
+// the tiling rows.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
                               bool with_dft, hipStream_t s)
 {
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
-        YoStepArgs a[2];
-        int blocks[2];
+        YoStepArgs a[8];
+        int blocks[8];
         const int wpb = (plans[base]->tflags & 2) ? 8 : 4;
-        for (int cls = 0; cls < 2; ++cls) {
-            memset(&a[cls], 0, sizeof(YoStepArgs));
-            a[cls].n_slots = cnt;
-            int tot = 0;
-            for (int i = 0; i < cnt; ++i) {
-                yo_plan *p = plans[base + i];
-                int r0, r1;
-                set_rhs_range(p, which[base + i], r0, r1);
-                YoSlot &sl = a[cls].slot[i];
-                sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
-                sl.tiles = wsp<int4>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
-                sl.rhs0 = r0;
-                sl.nrhs = std::max(r1 - r0, 1);
-                sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
-                a[cls].prefix[i] = tot;
-                // waves come in groups of wpb tiles per right-hand side
-                const int groups = (sl.ntile + wpb - 1) / wpb;
-                tot += sl.nrhs * groups * wpb;
-            }
-            a[cls].prefix[cnt] = tot;
-            a[cls].total_waves = tot;
-            a[cls].wpb = wpb;
-            blocks[cls] = (tot + wpb - 1) / wpb;
-        }
+        for (int cls = 0; cls < 8; ++cls)
+            blocks[cls] = step_args(plans + base, which + base, cnt, cls, wpb, a[cls]);
         YoAuxArgs ad, as;
         aux_args(plans + base, which + base, cnt, true, ad);
         aux_args(plans + base, which + base, cnt, false, as);
@@ -958,7 +967,8 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
                 ad.k_offset = k;
                 HIPCHK(yo_launch_dft(ad, s));
             }
-            for (int cls = 0; cls < 2; ++cls) {
+            for (int cls = 0; cls < 8; ++cls) {
+                if (!blocks[cls]) continue;
                 a[cls].k_offset = k;
                 HIPCHK(yo_launch_step(ty, cls, a[cls], blocks[cls], s));
             }
@@ -1180,30 +1190,18 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
 {
     if (!p || !avg_ms || !bytes || !cells) return fail(YO_EINVAL, "null argument");
     if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
-    if (cls < 0 || cls > 1 || n_launch < 1) return fail(YO_EINVAL, "bad class or count");
+    if (cls < 0 || cls > 7 || n_launch < 1) return fail(YO_EINVAL, "bad class or count");
     if (!p->active) return fail(YO_ESTATE, "yo_reset first");
     hipStream_t s = (hipStream_t)stream;
     int r0, r1;
     set_rhs_range(p, p->active, r0, r1);
     YoStepArgs a;
-    memset(&a, 0, sizeof a);
-    a.n_slots = 1;
-    YoSlot &sl = a.slot[0];
-    sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
-    sl.tiles = wsp<int4>(p, p->L.tiles) + (cls ? p->n_tile_int : 0);
-    sl.rhs0 = r0;
-    sl.nrhs = std::max(r1 - r0, 1);
-    sl.ntile = (r1 > r0) ? (cls ? p->n_tile_pml : p->n_tile_int) : 0;
     const int wpb = (p->tflags & 2) ? 8 : 4;
-    a.wpb = wpb;
-    a.prefix[1] = a.total_waves = sl.nrhs * ((sl.ntile + wpb - 1) / wpb) * wpb;
-    const int blocks = (a.total_waves + wpb - 1) / wpb;
+    const int blocks = step_args(&p, &p->active, 1, cls, wpb, a);
     // owned cells of this class and those inside each axis' absorbing slabs
     const yo_grid &g = p->grid;
     double own = 0.0, in_pml = 0.0;
-    const int first = cls ? p->n_tile_int : 0;
-    const int last = cls ? p->n_tile_int + p->n_tile_pml : p->n_tile_int;
-    for (int t = first; t < last; ++t) {
+    for (int t = p->cls_off[cls]; t < p->cls_off[cls + 1]; ++t) {
         const int4 tt = p->tiles_host[t];
         const int x0 = tt.x & 0xffff, x1 = x0 + (tt.x >> 16);
         const int y0 = tt.y & 0xffff, y1 = y0 + (tt.y >> 16);
@@ -1222,6 +1220,11 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     const double R = r1 - r0;
     *bytes = own * (48.0 * R + 12.0) + 32.0 * R * in_pml;
     *cells = own * R;
+    if (!blocks || r1 <= r0) {
+        *avg_ms = 0.0f;
+        *bytes = *cells = 0.0;
+        return YO_OK;
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));

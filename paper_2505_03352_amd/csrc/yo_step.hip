@@ -1,6 +1,6 @@
-// Fused Yee time step for gfx950.  One launch advances every tile of every
-// selected right-hand side by one full step (Ht half step, then E step); a
-// second launch of the same kernel does the tiles of the CPML shell.  Two
+// Fused Yee time step for gfx950.  One launch per tile class advances every
+// tile of that class of every selected right-hand side by one full step (Ht
+// half step, then E step).  Two
 // small kernels bracket them: the running DFT of E^n (design box and port
 // planes) before the step, and the soft current source after it.
 //
@@ -27,9 +27,9 @@
 // a zero ghost layer, so every load is unconditional: indices outside the
 // grid are clamped onto the ghost layer and read zero.
 //
-// Tiles of the interior class never touch a CPML coefficient (their owned
-// and halo sites all lie outside the absorbing slabs), so that instantiation
-// has no CPML code at all; the CPML class handles the shell.
+// Tiles are sorted into eight classes by the absorbing slabs (x, y, z)
+// their owned and halo sites touch; each class runs an instantiation that
+// contains the CPML code of exactly those axes (none for the interior).
 //
 // Launch: blocks of 4 waves, dispatched round-robin over the 8 XCDs; the
 // block index is remapped so each XCD receives one contiguous run of tiles
@@ -99,7 +99,8 @@ __device__ __forceinline__ int sel3(int a, int v0, int v1, int v2)
     return a == 0 ? v0 : (a == 1 ? v1 : v2);
 }
 
-template <int TY, bool PML>
+// PM: which axes' absorbing slabs the tile touches (bit 0 x, bit 1 y, bit 2 z)
+template <int TY, int PM>
 __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, const int step,
                                           const int4 t, const int lane)
 {
@@ -135,7 +136,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     const bool xin = (x >= 0) && (x < nx);
     int pxs = -1;
     Cpml cxE = {1.0f, 0.0f, 1.0f}, cxH = {1.0f, 0.0f, 1.0f};
-    if (PML && xin) {
+    if ((PM & 1) && xin) {
         pxs = slab_index(x, nx, P.plo[0], P.phi[0]);
         if (pxs >= 0) {
             cxE = cpml_at(profx, nx, 0, x);
@@ -191,7 +192,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
         // unconditional (the last plane re-reads itself) so the wait counts stay exact
         load_plane(k + 1 < k1 ? k + 1 : k, Enx2, Ho2, Kv2);
         int pz = -1;
-        if (PML) pz = slab_index(k, nz, P.plo[2], P.phi[2]);
+        if (PM & 4) pz = slab_index(k, nz, P.plo[2], P.phi[2]);
 
         // ---------------- Ht at plane k, rows j0-1 .. j0+TY-1 ----------------
 #pragma unroll
@@ -206,13 +207,13 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             float dxEy = ey_i1 - Ec[1][r];
             float dyEx = Ec[0][r + 1] - Ec[0][r];
             const bool own = own_x && own_k && (r >= 1) && (r <= jn);
-            if (PML) {
+            if (PM) {
                 const bool jin = (j >= 0) && (j < ny);
                 if (jin && xin && k >= 0) {
-                    const int py = slab_index(j, ny, P.plo[1], P.phi[1]);
+                    const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
                     float *const *psiO = R.psiH[par];
                     float *const *psiN = R.psiH[par ^ 1];
-                    if (pxs >= 0) {
+                    if ((PM & 1) && pxs >= 0) {
                         const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
                         const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
                         float n0, n1;
@@ -220,7 +221,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
                         dxEy = pml_diff(dxEy, cxH, (psiO[0] + r1)[pxs], n1);   // Hz
                         if (own) { (psiN[0] + r0)[pxs] = n0; (psiN[0] + r1)[pxs] = n1; }
                     }
-                    if (py >= 0) {
+                    if ((PM & 2) && py >= 0) {
                         const Cpml cy = cpml_at(profy, ny, 3, j);
                         const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
                         const size_t r1 = (((size_t)1 * nz + k) * Wy + py) * nxp;
@@ -229,7 +230,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
                         dyEx = pml_diff(dyEx, cy, (psiO[1] + r1)[x], n1);   // Hz
                         if (own) { (psiN[1] + r0)[x] = n0; (psiN[1] + r1)[x] = n1; }
                     }
-                    if (pz >= 0) {
+                    if ((PM & 4) && pz >= 0) {
                         const Cpml cz = cpml_at(profz, nz, 3, k);
                         const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
                         const size_t r1 = (((size_t)1 * Wz + pz) * ny + j) * nxp;
@@ -266,9 +267,9 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             float dxHz = Hc[2][r] - hz_im;
             float dxHy = Hc[1][r] - hy_im;
             float dyHx = Hc[0][r] - Hc[0][r - 1];
-            if (PML && own_x) {
-                const int py = slab_index(j, ny, P.plo[1], P.phi[1]);
-                if (pxs >= 0) {
+            if (PM && own_x) {
+                const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
+                if ((PM & 1) && pxs >= 0) {
                     float *ps = R.psiE[0];
                     const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
                     const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
@@ -277,7 +278,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
                     dxHy = pml_diff(dxHy, cxE, (ps + r1)[pxs], n1);   // Ez
                     (ps + r0)[pxs] = n0; (ps + r1)[pxs] = n1;
                 }
-                if (py >= 0) {
+                if ((PM & 2) && py >= 0) {
                     float *ps = R.psiE[1];
                     const Cpml cy = cpml_at(profy, ny, 0, j);
                     const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
@@ -287,7 +288,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
                     dyHx = pml_diff(dyHx, cy, (ps + r1)[x], n1);   // Ez
                     (ps + r0)[x] = n0; (ps + r1)[x] = n1;
                 }
-                if (pz >= 0) {
+                if ((PM & 4) && pz >= 0) {
                     float *ps = R.psiE[2];
                     const Cpml cz = cpml_at(profz, nz, 0, k);
                     const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
@@ -338,7 +339,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     }
 }
 
-template <int TY, bool PML>
+template <int TY, int PM>
 __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
     const int ti = grp * wpb + in_grp % wpb;
     if (ti >= sl.ntile) return;
     const int4 t = sl.tiles[ti];
-    wave_step<TY, PML>(P, P.rhs[r], step, t, lane);
+    wave_step<TY, PM>(P, P.rhs[r], step, t, lane);
 }
 
 // locate point q of slot s in the aux work list
@@ -471,22 +472,31 @@ __global__ void k_ctr(const YoCtrArgs a, int set_value)
 
 }  // namespace
 
-hipError_t yo_launch_step(int ty, int pml, const YoStepArgs &args, int blocks, hipStream_t s)
+template <int TY>
+static hipError_t launch_ty(int pm, const YoStepArgs &args, int blocks, hipStream_t s)
+{
+    const dim3 blk(64 * args.wpb);
+    switch (pm) {
+    case 0: hipLaunchKernelGGL((k_yee_step<TY, 0>), dim3(blocks), blk, 0, s, args); break;
+    case 1: hipLaunchKernelGGL((k_yee_step<TY, 1>), dim3(blocks), blk, 0, s, args); break;
+    case 2: hipLaunchKernelGGL((k_yee_step<TY, 2>), dim3(blocks), blk, 0, s, args); break;
+    case 3: hipLaunchKernelGGL((k_yee_step<TY, 3>), dim3(blocks), blk, 0, s, args); break;
+    case 4: hipLaunchKernelGGL((k_yee_step<TY, 4>), dim3(blocks), blk, 0, s, args); break;
+    case 5: hipLaunchKernelGGL((k_yee_step<TY, 5>), dim3(blocks), blk, 0, s, args); break;
+    case 6: hipLaunchKernelGGL((k_yee_step<TY, 6>), dim3(blocks), blk, 0, s, args); break;
+    case 7: hipLaunchKernelGGL((k_yee_step<TY, 7>), dim3(blocks), blk, 0, s, args); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_step(int ty, int pm, const YoStepArgs &args, int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
-    const dim3 blk(64 * args.wpb);
-    if (ty == 4 && !pml)
-        hipLaunchKernelGGL((k_yee_step<4, false>), dim3(blocks), blk, 0, s, args);
-    else if (ty == 4 && pml)
-        hipLaunchKernelGGL((k_yee_step<4, true>), dim3(blocks), blk, 0, s, args);
-    else if (ty == 8 && !pml)
-        hipLaunchKernelGGL((k_yee_step<8, false>), dim3(blocks), blk, 0, s, args);
-    else if (ty == 8 && pml)
-        hipLaunchKernelGGL((k_yee_step<8, true>), dim3(blocks), blk, 0, s, args);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (ty == 4) return launch_ty<4>(pm, args, blocks, s);
+    if (ty == 8) return launch_ty<8>(pm, args, blocks, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s)
