@@ -174,8 +174,13 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
 /* Tile shape of the time-stepping kernel: rows per wave (4 or 8), z-planes
  * per wave (>= 4) and flags (bit 0: the CPML x-strips are full 62-cell
  * strips instead of just the absorbing columns; bit 1: 8 waves per block
- * instead of 4).  Results do not depend on it (bitwise).  Synchronises the
- * device. */
+ * instead of 4; bit 2: cooperative blocks, whose waves are stacked in y and
+ * pass the rows they share through LDS instead of each loading them; bit 3:
+ * one launch for the tiles of all CPML classes instead of one per class,
+ * each tile running its own class's code; bit 4: the same single launch
+ * with the code of all three axes).  Other flag bits, or bits 3 and 4
+ * together: YO_EINVAL.  Results do not depend on it (bitwise).
+ * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);
 
 /* Modal coefficients (Appendix A) of the forward right-hand sides:
@@ -223,8 +228,9 @@ yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
 
 /* Measurement: time `n_launch` launches of one tile class of the
  * time-stepping kernel (cls 0..7; bit 0/1/2 set: the tiles touch the x/y/z
- * absorbing slabs, so cls 0 is the interior; an empty class reports zeros
- * and launches nothing) over the
+ * absorbing slabs, so cls 0 is the interior; cls 8: every CPML class, as a
+ * solve launches them; an empty class reports zeros and launches nothing)
+ * over the
  * right-hand sides selected by the last yo_reset, at the current step, with
  * HIP events on `stream`; blocks until done.  The launches re-run the same
  * step (they read the current buffers and do not advance the counter), so

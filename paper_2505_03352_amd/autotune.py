@@ -1,6 +1,6 @@
 """Autotuner for the time-stepping kernel's tile shape.
 
-For a plan it times every candidate (rows per wave, z-planes per wave) on
+For a plan it times every candidate (rows per wave, z-planes per wave, layout flags) on
 the real grid with HIP events, using the kernel-timing entry point (which
 re-runs one step without advancing), and keeps the fastest.  Results are
 cached in a JSON file keyed by the shape class (architecture, padded x
@@ -20,10 +20,15 @@ import torch
 from ._abi import YO_BOTH
 
 # (rows per wave, z-planes per wave, flags): flag 1 = full-width CPML x-strips,
-# flag 2 = 8 waves per block
+# flag 2 = 8 waves per block, flag 4 = cooperative blocks (waves stacked in y),
+# flag 8 / 16 = one launch for all CPML classes (per-class code / code of all
+# axes).  Eight-row tiles run two waves per SIMD; only a few are tried.
 CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
-    (r, z, f) for r in (4, 8) for z in (8, 16, 32) for f in (0, 1, 2, 3))
-N_CLASSES = 8      # tile classes of the step kernel (interior + 7 CPML classes)
+    [(4, z, a | b | c | d) for z in (8, 16, 32) for a in (0, 1) for b in (0, 2) for c in (0, 4)
+     for d in (0, 8, 16)]
+    + [(8, z, f) for z in (8, 16) for f in (1, 9, 17)])
+# what one step launches: the interior class and the CPML classes
+TIMED_CLASSES = (0, 8)
 _lock = threading.Lock()
 
 
@@ -84,7 +89,7 @@ def tune(plan, which: int = YO_BOTH, candidates: Optional[Iterable] = None, n_la
         plan.set_tiling(rows, zc, fl)
         plan.reset(which, stream)
         t0 = 0.0
-        for cls in range(N_CLASSES):
+        for cls in TIMED_CLASSES:
             plan.time_kernel(cls, 1, stream)          # warm-up
             ms, _, _ = plan.time_kernel(cls, n_launch, stream)
             t0 += ms

@@ -61,9 +61,10 @@ struct YoPlanD {
     const YoRhsD *rhs;       // [n_rhs]
 };
 
-// A tile is one wave's work: owned x in [x0, x0+xn) (xn <= 62), rows
-// [j0, j0+jn) (jn <= TY), planes [k0, k1).  Packed as int4
-// (x0 | xn << 16, j0 | jn << 16, k0 | k1 << 16, 0).
+// A tile is one wave's work (or, in the cooperative layout, one block's):
+// owned x in [x0, x0+xn) (xn <= 62), rows [j0, j0+jn) (jn <= TY, or
+// TY * waves per block), planes [k0, k1).  Packed as int4
+// (x0 | xn << 16, j0 | jn << 16, k0 | k1 << 16, tile class).
 struct YoSlot {
     const YoPlanD *plan;
     const int4 *tiles;       // tile list of this launch's class
@@ -125,8 +126,10 @@ struct YoChainBufs {
 };
 
 // ---- kernel launchers ----
-// pm: tile class, bit 0/1/2 = the tiles touch the x/y/z absorbing slabs
-hipError_t yo_launch_step(int ty, int pm, const YoStepArgs &args, int blocks, hipStream_t s);
+// pm: tile class, bit 0/1/2 = the tiles touch the x/y/z absorbing slabs, or
+// 8: tiles of any class, each selecting its code by its class (int4 .w);
+// coop: one tile per block, its waves stacked in y (tiles of ty * wpb rows)
+hipError_t yo_launch_step(int ty, int pm, bool coop, const YoStepArgs &args, int blocks, hipStream_t s);
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);

@@ -108,7 +108,9 @@ struct yo_plan {
     std::vector<float> ginv;     // [n_freq][4]
     std::vector<double> omega_dt;
     std::vector<char> src_set, port_set;
-    int ty = 4, kc = 16, tflags = 0;   // tflags: 1 = merge CPML x-strips, 2 = 8 waves per block
+    int ty = 4, kc = 16, tflags = 0;   // tflags: 1 = merge CPML x-strips, 2 = 8 waves per block,
+                                       // 4 = cooperative blocks (waves stacked in y),
+                                       // 8 / 16 = one launch for all CPML classes
     int cls_off[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // tile table offsets per class (8 classes)
     bool bg_set = false, design_set = false;
     double beta = 0;
@@ -283,7 +285,9 @@ void build_tiles(yo_plan *p)
     const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
     std::vector<std::pair<int, int>> ax[3];
     std::vector<char> in_ax[3];
-    const int width[3] = {YO_TX, p->ty, p->kc};
+    // cooperative layout: one tile per block, its waves stacked in y
+    const int wpb = (p->tflags & 2) ? 8 : 4;
+    const int width[3] = {YO_TX, (p->tflags & 4) ? p->ty * wpb : p->ty, p->kc};
     for (int a = 0; a < 3; ++a) {
         int lo = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
         int hi = n[a] - p->phi[a];
@@ -306,8 +310,8 @@ void build_tiles(yo_plan *p)
                 t.x = ax[0][ix].first | (ax[0][ix].second << 16);
                 t.y = ax[1][iy].first | (ax[1][iy].second << 16);
                 t.z = ax[2][iz].first | ((ax[2][iz].first + ax[2][iz].second) << 16);
-                t.w = 0;
                 const int c = (in_ax[0][ix] ? 0 : 1) | (in_ax[1][iy] ? 0 : 2) | (in_ax[2][iz] ? 0 : 4);
+                t.w = c;
                 byc[c].push_back(t);
             }
     p->tiles_host.clear();
@@ -454,6 +458,7 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     p->port_set.assign(n_ports, 0);
 
     // ghost layout: one zero layer on every face, rows padded to 128 bytes
+    // ghosts at x = -1 and x = nx, rounded up to 32 floats
     p->nxp = (g.nx + 2 + 31) & ~31;
     p->cells_p = (size_t)(g.nz + 2) * (g.ny + 2) * p->nxp;
     if (6 * p->cells_p * sizeof(float) >= ((size_t)1 << 31)) {
@@ -757,7 +762,7 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
     if (!p) return fail(YO_EINVAL, "null argument");
     if (rows != 4 && rows != 8) return fail(YO_EINVAL, "rows must be 4 or 8");
     if (zchunk < 4) return fail(YO_EINVAL, "zchunk must be >= 4");
-    if (flags & ~3) return fail(YO_EINVAL, "unknown tiling flags");
+    if ((flags & ~31) || (flags & 24) == 24) return fail(YO_EINVAL, "unknown tiling flags");
     p->ty = rows;
     p->kc = zchunk;
     p->tflags = flags;
@@ -918,7 +923,8 @@ static void aux_args(yo_plan *const *plans, const int *which, int cnt, bool dft,
 
 // Fill the step-kernel arguments of tile class `cls` for a plan list;
 // returns the number of blocks (0: no plan has tiles of that class).
-static int step_args(yo_plan *const *plans, const int *which, int cnt, int cls, int wpb, YoStepArgs &a)
+static int step_args(yo_plan *const *plans, const int *which, int cnt, int cls_lo, int cls_hi, int wpb,
+                     YoStepArgs &a)
 {
     memset(&a, 0, sizeof(YoStepArgs));
     a.n_slots = cnt;
@@ -929,13 +935,14 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int cls, 
         set_rhs_range(p, which[i], r0, r1);
         YoSlot &sl = a.slot[i];
         sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
-        sl.tiles = wsp<int4>(p, p->L.tiles) + p->cls_off[cls];
+        sl.tiles = wsp<int4>(p, p->L.tiles) + p->cls_off[cls_lo];
         sl.rhs0 = r0;
         sl.nrhs = std::max(r1 - r0, 1);
-        sl.ntile = (r1 > r0) ? p->cls_off[cls + 1] - p->cls_off[cls] : 0;
+        sl.ntile = (r1 > r0) ? p->cls_off[cls_hi] - p->cls_off[cls_lo] : 0;
         a.prefix[i] = tot;
-        // waves come in groups of wpb tiles per right-hand side
-        const int groups = (sl.ntile + wpb - 1) / wpb;
+        // waves come in groups of wpb per right-hand side: wpb tiles, or in
+        // the cooperative layout one tile
+        const int groups = (p->tflags & 4) ? sl.ntile : (sl.ntile + wpb - 1) / wpb;
         tot += sl.nrhs * groups * wpb;
     }
     a.prefix[cnt] = tot;
@@ -944,33 +951,62 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int cls, 
     return (tot + wpb - 1) / wpb;
 }
 
+// The step launches of one step for a plan list: the interior class, then
+// the CPML tiles: each class on its own, or all in one launch that selects
+// each tile's class code (tiling flag 8) or runs the code of all three axes
+// (flag 16).  Returns the number of launches filled in (empty ones skipped).
+struct StepLaunch {
+    int pm, blocks;
+    YoStepArgs a;
+};
+static int step_launches(yo_plan *const *plans, const int *which, int cnt, int cls_sel, StepLaunch *out)
+{
+    const int wpb = (plans[0]->tflags & 2) ? 8 : 4;
+    const bool merged = (plans[0]->tflags & 8) != 0;
+    int n = 0;
+    auto add = [&](int lo, int hi, int pm) {
+        out[n].pm = pm;
+        out[n].blocks = step_args(plans, which, cnt, lo, hi, wpb, out[n].a);
+        if (out[n].blocks) ++n;
+    };
+    if (cls_sel >= 0 && cls_sel < 8) {
+        add(cls_sel, cls_sel + 1, cls_sel);
+        return n;
+    }
+    if (cls_sel < 0) add(0, 1, 0);
+    if (plans[0]->tflags & 16)
+        add(1, 8, 7);          // one launch, the code of all three axes
+    else if (merged)
+        add(1, 8, 8);          // one launch, each tile's own class code
+    else
+        for (int c = 1; c < 8; ++c) add(c, c + 1, c);
+    return n;
+}
+
 // Launch `n_launch` steps (k_offset 0..n_launch-1) of a plan list, then add
 // n_launch to every plan's counter.  Per step: DFT of E^n (when `with_dft`),
-// one step launch per non-empty tile class, the source.  Plans must share
-// the tiling rows.
+// the step launches (interior, CPML), the source.  Plans must share the
+// tiling rows and flags 2, 4 and 8.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
                               bool with_dft, hipStream_t s)
 {
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
-        YoStepArgs a[8];
-        int blocks[8];
-        const int wpb = (plans[base]->tflags & 2) ? 8 : 4;
-        for (int cls = 0; cls < 8; ++cls)
-            blocks[cls] = step_args(plans + base, which + base, cnt, cls, wpb, a[cls]);
+        static thread_local StepLaunch L[8];
+        const int nl = step_launches(plans + base, which + base, cnt, -1, L);
         YoAuxArgs ad, as;
         aux_args(plans + base, which + base, cnt, true, ad);
         aux_args(plans + base, which + base, cnt, false, as);
         const int ty = plans[base]->ty;
+        const bool coop = (plans[base]->tflags & 4) != 0;
         for (int k = 0; k < n_launch; ++k) {
             if (with_dft) {
                 ad.k_offset = k;
                 HIPCHK(yo_launch_dft(ad, s));
             }
-            for (int cls = 0; cls < 8; ++cls) {
-                if (!blocks[cls]) continue;
-                a[cls].k_offset = k;
-                HIPCHK(yo_launch_step(ty, cls, a[cls], blocks[cls], s));
+            for (int i = 0; i < nl; ++i) {
+                L[i].a.k_offset = k;
+                HIPCHK(yo_launch_step(ty, L[i].pm, coop, L[i].a, L[i].blocks, s));
             }
             as.k_offset = k;
             HIPCHK(yo_launch_source(as, s));
@@ -1008,8 +1044,8 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         yo_plan *p = plans[i];
         if (!p || !p->ws) return fail(YO_EWORKSPACE, "plan %d has no workspace", i);
         if (which[i] != p->active) return fail(YO_ESTATE, "plan %d: which differs from its reset", i);
-        if (p->ty != plans[0]->ty || (p->tflags & 2) != (plans[0]->tflags & 2))
-            return fail(YO_EINVAL, "plans in one call must share the tiling rows and block size");
+        if (p->ty != plans[0]->ty || (p->tflags & 30) != (plans[0]->tflags & 30))
+            return fail(YO_EINVAL, "plans in one call must share the tiling rows, block size and layout");
         for (int j = 0; j < i; ++j)
             if (plans[j] == p) return fail(YO_EINVAL, "plan listed twice");
     }
@@ -1190,24 +1226,24 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
 {
     if (!p || !avg_ms || !bytes || !cells) return fail(YO_EINVAL, "null argument");
     if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
-    if (cls < 0 || cls > 7 || n_launch < 1) return fail(YO_EINVAL, "bad class or count");
+    if (cls < 0 || cls > 8 || n_launch < 1) return fail(YO_EINVAL, "bad class or count");
     if (!p->active) return fail(YO_ESTATE, "yo_reset first");
     hipStream_t s = (hipStream_t)stream;
     int r0, r1;
     set_rhs_range(p, p->active, r0, r1);
-    YoStepArgs a;
-    const int wpb = (p->tflags & 2) ? 8 : 4;
-    const int blocks = step_args(&p, &p->active, 1, cls, wpb, a);
-    // owned cells of this class and those inside each axis' absorbing slabs
+    static thread_local StepLaunch L[8];
+    const int nl = step_launches(&p, &p->active, 1, cls, L);
+    // owned cells of the timed classes and those inside each axis' absorbing slabs
     const yo_grid &g = p->grid;
     double own = 0.0, in_pml = 0.0;
-    for (int t = p->cls_off[cls]; t < p->cls_off[cls + 1]; ++t) {
+    const int c_lo = cls < 8 ? cls : 1, c_hi = cls < 8 ? cls + 1 : 8;
+    for (int t = p->cls_off[c_lo]; t < p->cls_off[c_hi]; ++t) {
         const int4 tt = p->tiles_host[t];
         const int x0 = tt.x & 0xffff, x1 = x0 + (tt.x >> 16);
         const int y0 = tt.y & 0xffff, y1 = y0 + (tt.y >> 16);
         const int z0 = tt.z & 0xffff, z1 = tt.z >> 16;
         own += (double)(x1 - x0) * (y1 - y0) * (z1 - z0);
-        if (cls) {
+        if (tt.w) {
             for (int z = z0; z < z1; ++z)
                 for (int y = y0; y < y1; ++y)
                     for (int x = x0; x < x1; ++x) {
@@ -1220,7 +1256,7 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     const double R = r1 - r0;
     *bytes = own * (48.0 * R + 12.0) + 32.0 * R * in_pml;
     *cells = own * R;
-    if (!blocks || r1 <= r0) {
+    if (!nl || r1 <= r0) {
         *avg_ms = 0.0f;
         *bytes = *cells = 0.0;
         return YO_OK;
@@ -1229,7 +1265,9 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    for (int k = 0; k < n_launch; ++k) HIPCHK(yo_launch_step(p->ty, cls, a, blocks, s));
+    for (int k = 0; k < n_launch; ++k)
+        for (int i = 0; i < nl; ++i)
+            HIPCHK(yo_launch_step(p->ty, L[i].pm, (p->tflags & 4) != 0, L[i].a, L[i].blocks, s));
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.0f;

@@ -38,13 +38,16 @@
 
 namespace {
 
-__device__ __forceinline__ float shfl_next(float v)   // value of lane+1
+// Neighbour exchange along x with DPP whole-wave shifts (one VALU move, no
+// LDS round trip).  The lane with no neighbour gets 0; those are halo lanes,
+// whose results are never used.
+__device__ __forceinline__ float shfl_next(float v)   // value of lane+1 (wave_shl:1)
 {
-    return __shfl_down(v, 1, 64);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
-__device__ __forceinline__ float shfl_prev(float v)   // value of lane-1
+__device__ __forceinline__ float shfl_prev(float v)   // value of lane-1 (wave_shr:1)
 {
-    return __shfl_up(v, 1, 64);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -99,10 +102,118 @@ __device__ __forceinline__ int sel3(int a, int v0, int v1, int v2)
     return a == 0 ? v0 : (a == 1 ? v1 : v2);
 }
 
+// CPML corrections of the six differences of one Ht site row (x = this
+// lane, row j, plane k): each difference inside an absorbing slab of its
+// axis becomes d/kp + psi with psi <- b psi + c d.  Ht's memories are
+// double-buffered by step parity (halo rows recompute Ht, reading psi of
+// the old step); only the owner writes the new value.
+template <int PM>
+__device__ __forceinline__ void h_cpml(const YoPlanD &P, const YoRhsD &R, int par, int x, int j, int k,
+                                       int pxs, int pz, const Cpml &cxH, bool own, float &dxEz,
+                                       float &dxEy, float &dyEz, float &dyEx, float &dzEy, float &dzEx)
+{
+    const int nx = P.nx, ny = P.ny, nz = P.nz, nxp = P.nxp;
+    const bool xin = (x >= 0) && (x < nx);
+    const bool jin = (j >= 0) && (j < ny);
+    if (!(jin && xin && k >= 0)) return;
+    const int Wx = P.plo[0] + P.phi[0], Wy = P.plo[1] + P.phi[1], Wz = P.plo[2] + P.phi[2];
+    const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
+    float *const *psiO = R.psiH[par];
+    float *const *psiN = R.psiH[par ^ 1];
+    if ((PM & 1) && pxs >= 0) {
+        const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
+        const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
+        float n0, n1;
+        dxEz = pml_diff(dxEz, cxH, (psiO[0] + r0)[pxs], n0);   // Hy
+        dxEy = pml_diff(dxEy, cxH, (psiO[0] + r1)[pxs], n1);   // Hz
+        if (own) { (psiN[0] + r0)[pxs] = n0; (psiN[0] + r1)[pxs] = n1; }
+    }
+    if ((PM & 2) && py >= 0) {
+        const Cpml cy = cpml_at(P.prof[1], ny, 3, j);
+        const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
+        const size_t r1 = (((size_t)1 * nz + k) * Wy + py) * nxp;
+        float n0, n1;
+        dyEz = pml_diff(dyEz, cy, (psiO[1] + r0)[x], n0);   // Hx
+        dyEx = pml_diff(dyEx, cy, (psiO[1] + r1)[x], n1);   // Hz
+        if (own) { (psiN[1] + r0)[x] = n0; (psiN[1] + r1)[x] = n1; }
+    }
+    if ((PM & 4) && pz >= 0) {
+        const Cpml cz = cpml_at(P.prof[2], nz, 3, k);
+        const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
+        const size_t r1 = (((size_t)1 * Wz + pz) * ny + j) * nxp;
+        float n0, n1;
+        dzEy = pml_diff(dzEy, cz, (psiO[2] + r0)[x], n0);   // Hx
+        dzEx = pml_diff(dzEx, cz, (psiO[2] + r1)[x], n1);   // Hy
+        if (own) { (psiN[2] + r0)[x] = n0; (psiN[2] + r1)[x] = n1; }
+    }
+}
+
+// CPML corrections of the six differences of one E site (single buffered:
+// each E memory is read and written by its owner only).
+template <int PM>
+__device__ __forceinline__ void e_cpml(const YoPlanD &P, const YoRhsD &R, int x, int j, int k, int pxs,
+                                       int pz, const Cpml &cxE, bool own, float &dxHz, float &dxHy,
+                                       float &dyHz, float &dyHx, float &dzHy, float &dzHx)
+{
+    const int nx = P.nx, ny = P.ny, nz = P.nz, nxp = P.nxp;
+    if (!(x >= 0 && x < nx && j >= 0 && j < ny && k >= 0 && k < nz)) return;
+    const int Wx = P.plo[0] + P.phi[0], Wy = P.plo[1] + P.phi[1], Wz = P.plo[2] + P.phi[2];
+    const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
+    if ((PM & 1) && pxs >= 0) {
+        float *ps = R.psiE[0];
+        const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
+        const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
+        float n0, n1;
+        dxHz = pml_diff(dxHz, cxE, (ps + r0)[pxs], n0);   // Ey
+        dxHy = pml_diff(dxHy, cxE, (ps + r1)[pxs], n1);   // Ez
+        if (own) { (ps + r0)[pxs] = n0; (ps + r1)[pxs] = n1; }
+    }
+    if ((PM & 2) && py >= 0) {
+        float *ps = R.psiE[1];
+        const Cpml cy = cpml_at(P.prof[1], ny, 0, j);
+        const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
+        const size_t r1 = (((size_t)1 * nz + k) * Wy + py) * nxp;
+        float n0, n1;
+        dyHz = pml_diff(dyHz, cy, (ps + r0)[x], n0);   // Ex
+        dyHx = pml_diff(dyHx, cy, (ps + r1)[x], n1);   // Ez
+        if (own) { (ps + r0)[x] = n0; (ps + r1)[x] = n1; }
+    }
+    if ((PM & 4) && pz >= 0) {
+        float *ps = R.psiE[2];
+        const Cpml cz = cpml_at(P.prof[2], nz, 0, k);
+        const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
+        const size_t r1 = (((size_t)1 * Wz + pz) * ny + j) * nxp;
+        float n0, n1;
+        dzHy = pml_diff(dzHy, cz, (ps + r0)[x], n0);   // Ex
+        dzHx = pml_diff(dzHx, cz, (ps + r1)[x], n1);   // Ey
+        if (own) { (ps + r0)[x] = n0; (ps + r1)[x] = n1; }
+    }
+}
+
 // PM: which axes' absorbing slabs the tile touches (bit 0 x, bit 1 y, bit 2 z)
-template <int TY, int PM>
+// Exchange slots of a cooperative block, per plane parity and wave: Ex and
+// Ez of the wave's first row (next plane), Ht_x and Ht_z of its last row.
+#define YO_XS_FLOATS (2 * YO_MAX_WPB * 4 * 64)
+
+__device__ __forceinline__ void block_sync_lds()
+{
+    // LDS-only ordering: outstanding global loads and stores stay in flight
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One wave's share of a tile.  COOP = false: the tile is the wave's own
+// (rows j0 .. j0+jn-1); the wave loads the E rows above and below and
+// recomputes the Ht row below.  COOP = true: the tile is the block's, its
+// waves are stacked in y (wave w owns rows J0 + w TY ...), and neighbouring
+// waves hand each other the one row they share through LDS: Ex, Ez of the
+// row above and Ht_x, Ht_z of the row below.  Only the block's bottom wave
+// recomputes the Ht row below the block and only its top wave loads the E
+// row above it; one barrier per plane.
+template <int TY, int PM, bool COOP>
 __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, const int step,
-                                          const int4 t, const int lane)
+                                          const int4 t, const int w, const int lane, float *xs)
 {
     const int nx = P.nx, ny = P.ny, nz = P.nz, nxp = P.nxp;
     const int rows = ny + 2;
@@ -117,11 +228,30 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     const float sx = P.sx, sy = P.sy, sz = P.sz;
 
     const int x0 = t.x & 0xffff, xn = t.x >> 16;
-    const int j0 = t.y & 0xffff, jn = t.y >> 16;
+    const int J0 = t.y & 0xffff, JN = t.y >> 16;
     const int k0 = t.z & 0xffff, k1 = t.z >> 16;
+    const int j0 = COOP ? J0 + w * TY : J0;
+    const int jn = COOP ? clampi(JN - w * TY, 0, TY) : JN;
+    const bool bottom = !COOP || w == 0;
+    const bool top = !COOP || JN - w * TY <= TY;        // no rows of the tile above this wave
+    if (COOP && jn == 0) {
+        // past the tile's last row: nothing to compute, but keep the barriers
+        for (int k = k0 - 1; k < k1; ++k) block_sync_lds();
+        return;
+    }
+    // this wave's slots; a neighbour's are 4 * 64 floats below or above
+    float *const xme = COOP ? xs + w * 4 * 64 + lane : nullptr;
+    auto xslot = [&](int pp, int dw, int c) -> float & {
+        return xme[(pp * YO_MAX_WPB + dw) * 4 * 64 + c * 64];
+    };
     const int x = x0 - 1 + lane;
     const int xo = (clampi(x, -1, nx) + 1) * (int)sizeof(float);   // column byte offset (ghost clamped)
     const bool own_x = (lane >= 1) && (lane <= xn);
+    // Stores are unconditional (no branch around them, so the compiler can
+    // count outstanding memory operations exactly); a lane with nothing to
+    // store gives an offset past the end of the buffer, and the hardware's
+    // range check drops the write.
+    const int jo = (int)0x80000000;
     // wave-uniform byte offsets of row group (j, k) in the state and kappa arrays
     auto ro = [&](int j, int k) -> int {
         return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 6 * rowb;
@@ -131,8 +261,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     };
 
     // ---- CPML data of this lane along x (CPML class only) ----
-    const float *profx = P.prof[0], *profy = P.prof[1], *profz = P.prof[2];
-    const int Wx = P.plo[0] + P.phi[0], Wy = P.plo[1] + P.phi[1], Wz = P.plo[2] + P.phi[2];
+    const float *profx = P.prof[0];
     const bool xin = (x >= 0) && (x < nx);
     int pxs = -1;
     Cpml cxE = {1.0f, 0.0f, 1.0f}, cxH = {1.0f, 0.0f, 1.0f};
@@ -154,16 +283,18 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     // k+1 are issued before plane k's stores, because the vector-memory
     // counter also counts stores and a wait placed after them would wait for
     // the stores too.
+    // rows a wave never loads (the row below unless bottom, the row above
+    // unless top) are filled from neighbours or never read
     auto load_plane = [&](int k, float (&en)[3][TY + 2], float (&ho)[3][TY + 1],
                           float (&kv)[3][TY]) {
 #pragma unroll
-        for (int r = 0; r < TY + 2; ++r) {
+        for (int r = 1; r <= TY; ++r) {
             const int o = ro(j0 - 1 + r, k + 1);
 #pragma unroll
             for (int c = 0; c < 3; ++c) en[c][r] = bload(Fo, xo, eb + c * rowb + o);
         }
 #pragma unroll
-        for (int r = 0; r <= TY; ++r) {
+        for (int r = 1; r <= TY; ++r) {
             const int o = ro(j0 - 1 + r, k);
 #pragma unroll
             for (int c = 0; c < 3; ++c) ho[c][r] = bload(Fo, xo, hb + c * rowb + o);
@@ -174,10 +305,31 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 #pragma unroll
             for (int c = 0; c < 3; ++c) kv[c][r - 1] = bload(K, xo, c * rowb + o);
         }
+        // last, so that the branches do not blur the wait counts of the rest
+        if (bottom) {
+            const int oe = ro(j0 - 1, k + 1), oh = ro(j0 - 1, k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                en[c][0] = bload(Fo, xo, eb + c * rowb + oe);
+                ho[c][0] = bload(Fo, xo, hb + c * rowb + oh);
+            }
+        }
+        if (top) {
+            // only Ex and Ez of the row above enter (as y-differences)
+            const int o = ro(j0 + TY, k + 1);
+            en[0][TY + 1] = bload(Fo, xo, eb + o);
+            en[2][TY + 1] = bload(Fo, xo, eb + 2 * rowb + o);
+        }
     };
 
 #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Ec[c][0] = Enx[c][0] = Ho_[c][0] = Hc[c][0] = 0.0f;
+        Ec[c][TY + 1] = Enx[c][TY + 1] = 0.0f;
+    }
+#pragma unroll
     for (int r = 0; r < TY + 2; ++r) {
+        if (r == 0 && !bottom) continue;
         const int o = ro(j0 - 1 + r, k0 - 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) Ec[c][r] = bload(Fo, xo, eb + c * rowb + o);
@@ -193,10 +345,17 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
         load_plane(k + 1 < k1 ? k + 1 : k, Enx2, Ho2, Kv2);
         int pz = -1;
         if (PM & 4) pz = slab_index(k, nz, P.plo[2], P.phi[2]);
+        const int pp = k & 1;
+        if (COOP) {
+            // E of plane k+1, first row: the wave below's row above
+            xslot(pp, 0, 0) = Enx[0][1];
+            xslot(pp, 0, 1) = Enx[2][1];
+        }
 
         // ---------------- Ht at plane k, rows j0-1 .. j0+TY-1 ----------------
 #pragma unroll
         for (int r = 0; r <= TY; ++r) {
+            if (r == 0 && !bottom) continue;
             const int j = j0 - 1 + r;
             const float ez_i1 = shfl_next(Ec[2][r]);
             const float ey_i1 = shfl_next(Ec[1][r]);
@@ -207,51 +366,33 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             float dxEy = ey_i1 - Ec[1][r];
             float dyEx = Ec[0][r + 1] - Ec[0][r];
             const bool own = own_x && own_k && (r >= 1) && (r <= jn);
-            if (PM) {
-                const bool jin = (j >= 0) && (j < ny);
-                if (jin && xin && k >= 0) {
-                    const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
-                    float *const *psiO = R.psiH[par];
-                    float *const *psiN = R.psiH[par ^ 1];
-                    if ((PM & 1) && pxs >= 0) {
-                        const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
-                        const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
-                        float n0, n1;
-                        dxEz = pml_diff(dxEz, cxH, (psiO[0] + r0)[pxs], n0);   // Hy
-                        dxEy = pml_diff(dxEy, cxH, (psiO[0] + r1)[pxs], n1);   // Hz
-                        if (own) { (psiN[0] + r0)[pxs] = n0; (psiN[0] + r1)[pxs] = n1; }
-                    }
-                    if ((PM & 2) && py >= 0) {
-                        const Cpml cy = cpml_at(profy, ny, 3, j);
-                        const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
-                        const size_t r1 = (((size_t)1 * nz + k) * Wy + py) * nxp;
-                        float n0, n1;
-                        dyEz = pml_diff(dyEz, cy, (psiO[1] + r0)[x], n0);   // Hx
-                        dyEx = pml_diff(dyEx, cy, (psiO[1] + r1)[x], n1);   // Hz
-                        if (own) { (psiN[1] + r0)[x] = n0; (psiN[1] + r1)[x] = n1; }
-                    }
-                    if ((PM & 4) && pz >= 0) {
-                        const Cpml cz = cpml_at(profz, nz, 3, k);
-                        const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
-                        const size_t r1 = (((size_t)1 * Wz + pz) * ny + j) * nxp;
-                        float n0, n1;
-                        dzEy = pml_diff(dzEy, cz, (psiO[2] + r0)[x], n0);   // Hx
-                        dzEx = pml_diff(dzEx, cz, (psiO[2] + r1)[x], n1);   // Hy
-                        if (own) { (psiN[2] + r0)[x] = n0; (psiN[2] + r1)[x] = n1; }
-                    }
-                }
-            }
+            if (PM)
+                h_cpml<PM>(P, R, par, x, j, k, pxs, pz, cxH, own, dxEz, dxEy, dyEz, dyEx, dzEy, dzEx);
             const float hx = Ho_[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
             const float hy = Ho_[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
             const float hz = Ho_[2][r] - fmaf(sx, dxEy, -(sy * dyEx));
             Hc[0][r] = hx;
             Hc[1][r] = hy;
             Hc[2][r] = hz;
-            if (own) {
+            if (r >= 1) {
                 const int o = ro(j, k) + hb;
-                bstore(hx, Fn, xo, o);
-                bstore(hy, Fn, xo, rowb + o);
-                bstore(hz, Fn, xo, 2 * rowb + o);
+                const int so = own ? xo : jo;
+                bstore(hx, Fn, so, o);
+                bstore(hy, Fn, so, rowb + o);
+                bstore(hz, Fn, so, 2 * rowb + o);
+            }
+        }
+        if (COOP) {
+            xslot(pp, 0, 2) = Hc[0][TY];
+            xslot(pp, 0, 3) = Hc[2][TY];
+            block_sync_lds();
+            if (!bottom) {
+                Hc[0][0] = xslot(pp, -1, 2);
+                Hc[2][0] = xslot(pp, -1, 3);
+            }
+            if (!top) {
+                Enx[0][TY + 1] = xslot(pp, 1, 0);
+                Enx[2][TY + 1] = xslot(pp, 1, 1);
             }
         }
         // ---------------- E at plane k, rows j0 .. j0+jn-1 ----------------
@@ -260,45 +401,15 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             const int j = j0 - 1 + r;
             const float hz_im = shfl_prev(Hc[2][r]);
             const float hy_im = shfl_prev(Hc[1][r]);
-            if (!own_k || r > jn) continue;
+            const bool own = own_x && own_k && (r <= jn);
             float dyHz = Hc[2][r] - Hc[2][r - 1];
             float dzHy = Hc[1][r] - Hp[1][r - 1];
             float dzHx = Hc[0][r] - Hp[0][r - 1];
             float dxHz = Hc[2][r] - hz_im;
             float dxHy = Hc[1][r] - hy_im;
             float dyHx = Hc[0][r] - Hc[0][r - 1];
-            if (PM && own_x) {
-                const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
-                if ((PM & 1) && pxs >= 0) {
-                    float *ps = R.psiE[0];
-                    const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
-                    const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
-                    float n0, n1;
-                    dxHz = pml_diff(dxHz, cxE, (ps + r0)[pxs], n0);   // Ey
-                    dxHy = pml_diff(dxHy, cxE, (ps + r1)[pxs], n1);   // Ez
-                    (ps + r0)[pxs] = n0; (ps + r1)[pxs] = n1;
-                }
-                if ((PM & 2) && py >= 0) {
-                    float *ps = R.psiE[1];
-                    const Cpml cy = cpml_at(profy, ny, 0, j);
-                    const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
-                    const size_t r1 = (((size_t)1 * nz + k) * Wy + py) * nxp;
-                    float n0, n1;
-                    dyHz = pml_diff(dyHz, cy, (ps + r0)[x], n0);   // Ex
-                    dyHx = pml_diff(dyHx, cy, (ps + r1)[x], n1);   // Ez
-                    (ps + r0)[x] = n0; (ps + r1)[x] = n1;
-                }
-                if ((PM & 4) && pz >= 0) {
-                    float *ps = R.psiE[2];
-                    const Cpml cz = cpml_at(profz, nz, 0, k);
-                    const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
-                    const size_t r1 = (((size_t)1 * Wz + pz) * ny + j) * nxp;
-                    float n0, n1;
-                    dzHy = pml_diff(dzHy, cz, (ps + r0)[x], n0);   // Ex
-                    dzHx = pml_diff(dzHx, cz, (ps + r1)[x], n1);   // Ey
-                    (ps + r0)[x] = n0; (ps + r1)[x] = n1;
-                }
-            }
+            if (PM)
+                e_cpml<PM>(P, R, x, j, k, pxs, pz, cxE, own, dxHz, dxHy, dyHz, dyHx, dzHy, dzHx);
             float ex = fmaf(Kv[0][r - 1], fmaf(sy, dyHz, -(sz * dzHy)), Ec[0][r]);
             float ey = fmaf(Kv[1][r - 1], fmaf(sz, dzHx, -(sx * dxHz)), Ec[1][r]);
             float ez = fmaf(Kv[2][r - 1], fmaf(sx, dxHy, -(sy * dyHx)), Ec[2][r]);
@@ -306,11 +417,12 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             ex = (j == 0 || k == 0) ? 0.0f : ex;
             ey = (x == 0 || k == 0) ? 0.0f : ey;
             ez = (x == 0 || j == 0) ? 0.0f : ez;
-            if (own_x) {
+            {
                 const int o = ro(j, k) + eb;
-                bstore(ex, Fn, xo, o);
-                bstore(ey, Fn, xo, rowb + o);
-                bstore(ez, Fn, xo, 2 * rowb + o);
+                const int so = own ? xo : jo;
+                bstore(ex, Fn, so, o);
+                bstore(ey, Fn, so, rowb + o);
+                bstore(ez, Fn, so, 2 * rowb + o);
             }
         }
 #pragma unroll
@@ -339,7 +451,30 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     }
 }
 
-template <int TY, int PM>
+// PM = YO_PM_ANY: tiles of every CPML class in one launch; each tile's class
+// (int4 .w) selects its code.
+#define YO_PM_ANY 8
+template <int TY, int PM, bool COOP>
+__device__ __forceinline__ void tile_step(const YoPlanD &P, const YoRhsD &R, int step, const int4 t,
+                                          int w, int lane, float *xs)
+{
+    if constexpr (PM == YO_PM_ANY) {
+        switch (t.w) {
+        case 1: wave_step<TY, 1, COOP>(P, R, step, t, w, lane, xs); break;
+        case 2: wave_step<TY, 2, COOP>(P, R, step, t, w, lane, xs); break;
+        case 3: wave_step<TY, 3, COOP>(P, R, step, t, w, lane, xs); break;
+        case 4: wave_step<TY, 4, COOP>(P, R, step, t, w, lane, xs); break;
+        case 5: wave_step<TY, 5, COOP>(P, R, step, t, w, lane, xs); break;
+        case 6: wave_step<TY, 6, COOP>(P, R, step, t, w, lane, xs); break;
+        case 7: wave_step<TY, 7, COOP>(P, R, step, t, w, lane, xs); break;
+        default: wave_step<TY, 0, COOP>(P, R, step, t, w, lane, xs); break;
+        }
+    } else {
+        wave_step<TY, PM, COOP>(P, R, step, t, w, lane, xs);
+    }
+}
+
+template <int TY, int PM, bool COOP>
 __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -350,6 +485,8 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
     // derived from it (slot, tile, row offsets) lives in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(lb * wpb + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
+    // every early exit below is uniform over the block (slot prefixes are
+    // whole blocks), as the cooperative variant's barriers require
     if (wave >= a.total_waves) return;
     int s = 0;
     while (s + 1 < a.n_slots && wave >= a.prefix[s + 1]) ++s;
@@ -357,19 +494,31 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
     const YoPlanD &P = *sl.plan;
     const int step = *P.step_ctr + a.k_offset;
     if (step >= P.n_steps) return;
-    // A block's waves take consecutive tiles (neighbouring x-strips of the
-    // same rows) of one right-hand side, so together they stream
-    // contiguous row segments; consecutive blocks take the same tiles for the
-    // next right-hand sides, which share kappa.
     const int local = wave - a.prefix[s];
-    const int grp = local / (wpb * sl.nrhs);
-    const int in_grp = local - grp * (wpb * sl.nrhs);
-    const int r = sl.rhs0 + in_grp / wpb;
-    const int ti = grp * wpb + in_grp % wpb;
-    if (ti >= sl.ntile) return;
-    const int4 t = sl.tiles[ti];
-    wave_step<TY, PM>(P, P.rhs[r], step, t, lane);
+    if (COOP) {
+        // one tile per block; consecutive blocks take the same tile for the
+        // next right-hand sides, which share kappa
+        __shared__ float xs[YO_XS_FLOATS];
+        const int blk = local / wpb;
+        const int w = local - blk * wpb;
+        const int r = sl.rhs0 + blk % sl.nrhs;
+        const int ti = blk / sl.nrhs;
+        if (ti >= sl.ntile) return;
+        tile_step<TY, PM, true>(P, P.rhs[r], step, sl.tiles[ti], w, lane, xs);
+    } else {
+        // A block's waves take consecutive tiles (neighbouring x-strips of
+        // the same rows) of one right-hand side, so together they stream
+        // contiguous row segments; consecutive blocks take the same tiles
+        // for the next right-hand sides.
+        const int grp = local / (wpb * sl.nrhs);
+        const int in_grp = local - grp * (wpb * sl.nrhs);
+        const int r = sl.rhs0 + in_grp / wpb;
+        const int ti = grp * wpb + in_grp % wpb;
+        if (ti >= sl.ntile) return;
+        tile_step<TY, PM, false>(P, P.rhs[r], step, sl.tiles[ti], 0, lane, nullptr);
+    }
 }
+
 
 // locate point q of slot s in the aux work list
 __device__ __forceinline__ bool aux_point(const YoAuxArgs &a, int &s, int &r, int &q)
@@ -472,31 +621,40 @@ __global__ void k_ctr(const YoCtrArgs a, int set_value)
 
 }  // namespace
 
-template <int TY>
-static hipError_t launch_ty(int pm, const YoStepArgs &args, int blocks, hipStream_t s)
+template <int PM, bool COOP>
+static void launch_one(int ty, const YoStepArgs &args, int blocks, hipStream_t s)
 {
     const dim3 blk(64 * args.wpb);
+    if (ty == 4)
+        hipLaunchKernelGGL((k_yee_step<4, PM, COOP>), dim3(blocks), blk, 0, s, args);
+    else
+        hipLaunchKernelGGL((k_yee_step<8, PM, COOP>), dim3(blocks), blk, 0, s, args);
+}
+
+template <bool COOP>
+static hipError_t launch_pm(int ty, int pm, const YoStepArgs &args, int blocks, hipStream_t s)
+{
     switch (pm) {
-    case 0: hipLaunchKernelGGL((k_yee_step<TY, 0>), dim3(blocks), blk, 0, s, args); break;
-    case 1: hipLaunchKernelGGL((k_yee_step<TY, 1>), dim3(blocks), blk, 0, s, args); break;
-    case 2: hipLaunchKernelGGL((k_yee_step<TY, 2>), dim3(blocks), blk, 0, s, args); break;
-    case 3: hipLaunchKernelGGL((k_yee_step<TY, 3>), dim3(blocks), blk, 0, s, args); break;
-    case 4: hipLaunchKernelGGL((k_yee_step<TY, 4>), dim3(blocks), blk, 0, s, args); break;
-    case 5: hipLaunchKernelGGL((k_yee_step<TY, 5>), dim3(blocks), blk, 0, s, args); break;
-    case 6: hipLaunchKernelGGL((k_yee_step<TY, 6>), dim3(blocks), blk, 0, s, args); break;
-    case 7: hipLaunchKernelGGL((k_yee_step<TY, 7>), dim3(blocks), blk, 0, s, args); break;
+    case 0: launch_one<0, COOP>(ty, args, blocks, s); break;
+    case 1: launch_one<1, COOP>(ty, args, blocks, s); break;
+    case 2: launch_one<2, COOP>(ty, args, blocks, s); break;
+    case 3: launch_one<3, COOP>(ty, args, blocks, s); break;
+    case 4: launch_one<4, COOP>(ty, args, blocks, s); break;
+    case 5: launch_one<5, COOP>(ty, args, blocks, s); break;
+    case 6: launch_one<6, COOP>(ty, args, blocks, s); break;
+    case 7: launch_one<7, COOP>(ty, args, blocks, s); break;
+    case YO_PM_ANY: launch_one<YO_PM_ANY, COOP>(ty, args, blocks, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t yo_launch_step(int ty, int pm, const YoStepArgs &args, int blocks, hipStream_t s)
+hipError_t yo_launch_step(int ty, int pm, bool coop, const YoStepArgs &args, int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
-    if (ty == 4) return launch_ty<4>(pm, args, blocks, s);
-    if (ty == 8) return launch_ty<8>(pm, args, blocks, s);
-    return hipErrorInvalidValue;
+    if (ty != 4 && ty != 8) return hipErrorInvalidValue;
+    return coop ? launch_pm<true>(ty, pm, args, blocks, s) : launch_pm<false>(ty, pm, args, blocks, s);
 }
 
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s)

@@ -242,8 +242,9 @@ class Plan:
     def time_kernel(self, cls: int = 0, n_launch: int = 20, stream=None):
         """(avg ms per launch, algorithmic bytes per launch, cell-updates per
         launch) of one tile class (0..7, bit a: touches the absorbing slabs
-        of axis a; 0 = interior) of the time-stepping kernel, by HIP events.
-        An empty class gives zeros."""
+        of axis a; 0 = interior; 8 = all CPML classes as a solve launches
+        them) of the time-stepping kernel, by HIP events.  An empty class
+        gives zeros."""
         ms, b, c = ct.c_float(), ct.c_double(), ct.c_double()
         call("yo_time_kernel", self._h, int(cls), int(n_launch), ct.byref(ms), ct.byref(b),
              ct.byref(c), _stream(stream))

@@ -28,10 +28,9 @@ from __future__ import annotations
 
 import collections
 import concurrent.futures as cf
-import threading
 import time
 from dataclasses import dataclass, field
-from typing import Any, Callable, Dict, List, Optional, Sequence
+from typing import Any, Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -116,7 +115,6 @@ class Scheduler:
         self.clock = clock or RealClock()
         self.prep_workers = prep_workers
         self.events: List[tuple] = []      # (time, kind, rid) for inspection
-        self._lock = threading.Lock()
 
     def _log(self, kind, rid):
         self.events.append((self.clock.now(), kind, rid))

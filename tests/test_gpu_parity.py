@@ -45,18 +45,19 @@ def closed_box_plan(nx, ny, nz, kappa, n_steps, courant=0.5):
     return p
 
 
-@pytest.mark.parametrize("rows,zchunk", [(4, 16), (8, 8)])
+# tilings: (rows per wave, z-planes, flags); flag 4 = cooperative blocks
+@pytest.mark.parametrize("rows,zchunk,flags", [(4, 16, 0), (8, 8, 0), (4, 16, 4), (8, 8, 6)])
 @pytest.mark.parametrize("mnp,eps", [((2, 3, 0), 2.085), ((1, 2, 1), 12.11), ((0, 2, 1), 1.0)])
-def test_cavity_eigenmode(mnp, eps, rows, zchunk):
+def test_cavity_eigenmode(mnp, eps, rows, zchunk, flags):
     nx, ny, nz = 70, 44, 36
     m, n, p_ = mnp
     steps = 2000
-    say(f"cavity {mnp} eps={eps} tiling=({rows},{zchunk})")
+    say(f"cavity {mnp} eps={eps} tiling=({rows},{zchunk},{flags})")
     kap = np.full((3, nz, ny, nx), 1.0 / eps)
     E0, H0 = cavity.pec_standing_wave(nx, ny, nz, m, n, p_,
                                       cavity.divergence_free_amplitudes(nx, ny, nz, m, n, p_))
     plan = closed_box_plan(nx, ny, nz, kap, steps)
-    plan.set_tiling(rows, zchunk)
+    plan.set_tiling(rows, zchunk, flags)
     plan.reset(1)
     plan.set_fields(0, torch.as_tensor(E0, dtype=torch.float32), torch.as_tensor(H0, dtype=torch.float32))
     plan.advance(1, steps)
@@ -129,7 +130,10 @@ def test_fields_match_oracle_with_cpml_and_source():
     dt = 0.5 * 40e-9 / 299792458.0
     f = FreqSpec(w_dt / dt, 40.0, steps - 60, 60)
     outs = {}
-    for rows, zc, fl in [(4, 16, 0), (8, 8, 1), (4, 4, 2), (8, 64, 3)]:
+    # flag 4: cooperative blocks (its y-slab tiles of 7 rows leave idle
+    # waves); flags 8 and 16: all CPML classes in one launch
+    for rows, zc, fl in [(4, 16, 0), (8, 8, 1), (4, 4, 2), (8, 64, 3), (4, 16, 4), (4, 16, 5),
+                         (8, 8, 6), (4, 4, 7), (4, 16, 13), (8, 8, 10), (4, 16, 17), (4, 8, 21)]:
         say(f"cpml+source fields tiling=({rows},{zc},{fl})")
         p = Plan(grid, design, steps, [f], [pl], [], device="cuda")
         p.bind()
