@@ -171,15 +171,21 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n_plans, 
 /* Host-side step count of the last reset/advance of `plan`. */
 yo_status yo_steps_done(const yo_plan *plan, int *steps);
 
-/* Tile shape of the time-stepping kernel: rows per wave (4 or 8), z-planes
- * per wave (>= 4) and flags (bit 0: the CPML x-strips are full 62-cell
- * strips instead of just the absorbing columns; bit 1: 8 waves per block
- * instead of 4; bit 2: cooperative blocks, whose waves are stacked in y and
- * pass the rows they share through LDS instead of each loading them; bit 3:
- * one launch for the tiles of all CPML classes instead of one per class,
- * each tile running its own class's code; bit 4: the same single launch
- * with the code of all three axes).  Other flag bits, or bits 3 and 4
- * together: YO_EINVAL.  Results do not depend on it (bitwise).
+/* Work split of the time-stepping kernel.  Each step runs two launches: the
+ * interior tiles (clear of every absorbing slab, no CPML code) and the CPML
+ * shell.  rows: rows per wave, must be 4; zchunk: z-planes per tile (>= 4);
+ * flags, a sum of:
+ *    1  the CPML x-shell is cut into full 62-cell strips instead of just
+ *       the absorbing columns
+ *    2  8 waves per block instead of 4
+ *    4  shell: cooperative blocks (the block's waves are stacked in y and
+ *       pass the rows they share through LDS instead of each loading them)
+ *    8  shell: each tile runs the code of its own CPML axes (else the code
+ *       of all three axes)
+ *   16  interior: cooperative blocks
+ *   32  interior: no prefetch of the next plane's operands
+ *   64  shell: no prefetch
+ * Other bits: YO_EINVAL.  Results do not depend on the split (bitwise).
  * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);
 
@@ -226,11 +232,9 @@ yo_status yo_get_kappa(const yo_plan *plan, float *dev_kappa, yo_stream stream);
 yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
                          double *cell_updates_per_step);
 
-/* Measurement: time `n_launch` launches of one tile class of the
- * time-stepping kernel (cls 0..7; bit 0/1/2 set: the tiles touch the x/y/z
- * absorbing slabs, so cls 0 is the interior; cls 8: every CPML class, as a
- * solve launches them; an empty class reports zeros and launches nothing)
- * over the
+/* Measurement: time `n_launch` launches of one part of the time-stepping
+ * kernel (cls 0: interior tiles, 1: CPML shell; other values YO_EINVAL; an
+ * empty part reports zeros and launches nothing) over the
  * right-hand sides selected by the last yo_reset, at the current step, with
  * HIP events on `stream`; blocks until done.  The launches re-run the same
  * step (they read the current buffers and do not advance the counter), so

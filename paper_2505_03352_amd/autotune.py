@@ -1,12 +1,17 @@
-"""Autotuner for the time-stepping kernel's tile shape.
+"""Autotuner for the time-stepping kernel's work split.
 
-For a plan it times every candidate (rows per wave, z-planes per wave, layout flags) on
-the real grid with HIP events, using the kernel-timing entry point (which
-re-runs one step without advancing), and keeps the fastest.  Results are
+Each step runs two launches, the interior tiles and the CPML shell; their
+layout choices are independent except for what the two share (z-planes per
+tile, waves per block, whether the x-shell is cut into full strips).  For
+each shared setting the tuner times every interior choice (cooperative
+blocks or not, prefetch or not) with the interior launch alone and every
+shell choice (cooperative, per-class code, prefetch) with the shell launch
+alone, on the real grid with HIP events (the kernel-timing entry point
+re-runs one step without advancing), and keeps the fastest sum.  Results are
 cached in a JSON file keyed by the shape class (architecture, padded x
 extent, ny, nz, number of right-hand sides, CPML width), so plans of the
-same class reuse the choice.  Any tile shape gives bitwise the same fields,
-so tuning only changes speed.
+same class reuse the choice.  Every split gives bitwise the same fields, so
+tuning only changes speed.
 """
 from __future__ import annotations
 
@@ -19,16 +24,12 @@ import torch
 
 from ._abi import YO_BOTH
 
-# (rows per wave, z-planes per wave, flags): flag 1 = full-width CPML x-strips,
-# flag 2 = 8 waves per block, flag 4 = cooperative blocks (waves stacked in y),
-# flag 8 / 16 = one launch for all CPML classes (per-class code / code of all
-# axes).  Eight-row tiles run two waves per SIMD; only a few are tried.
-CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
-    [(4, z, a | b | c | d) for z in (8, 16, 32) for a in (0, 1) for b in (0, 2) for c in (0, 4)
-     for d in (0, 8, 16)]
-    + [(8, z, f) for z in (8, 16) for f in (1, 9, 17)])
-# what one step launches: the interior class and the CPML classes
-TIMED_CLASSES = (0, 8)
+ROWS = 4
+# shared settings: (z-planes per tile, flags from {1: x-strips, 2: 8 waves per block})
+SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b) for z in (8, 16, 32) for a in (0, 1)
+                                            for b in (0, 2))
+INTERIOR_FLAGS = (0, 16, 32, 16 | 32)          # cooperative, no prefetch
+SHELL_FLAGS = tuple(a | b | c for a in (0, 4) for b in (0, 8) for c in (0, 64))
 _lock = threading.Lock()
 
 
@@ -69,9 +70,17 @@ def _store(d: dict):
         pass
 
 
-def tune(plan, which: int = YO_BOTH, candidates: Optional[Iterable] = None, n_launch: int = 5,
+def _time(plan, zc, flags, part, which, n_launch, stream) -> float:
+    plan.set_tiling(ROWS, zc, flags)
+    plan.reset(which, stream)
+    plan.time_kernel(part, 1, stream)                 # warm-up
+    ms, _, _ = plan.time_kernel(part, n_launch, stream)
+    return ms
+
+
+def tune(plan, which: int = YO_BOTH, shared: Optional[Iterable] = None, n_launch: int = 5,
          use_cache: bool = True, stream=None) -> dict:
-    """Pick and apply the fastest tiling for `plan`; returns the record.
+    """Pick and apply the fastest split for `plan`; returns the record.
 
     Leaves the plan reset (fields zero) for `which`."""
     key = shape_key(plan, which)
@@ -80,25 +89,29 @@ def tune(plan, which: int = YO_BOTH, candidates: Optional[Iterable] = None, n_la
             rec = _load().get(key)
         if rec:
             plan.set_tiling(rec["rows"], rec["zchunk"], rec.get("flags", 0))
+            plan.reset(which, stream)
             return dict(rec, cached=True)
-    timings = {}
     nz = plan.grid["nz"]
-    for rows, zc, fl in (candidates or CANDIDATES):
+    timings = {}
+    best = None
+    for zc, base in (shared or SHARED):
         if zc > nz and zc != 8:
             continue
-        plan.set_tiling(rows, zc, fl)
-        plan.reset(which, stream)
-        t0 = 0.0
-        for cls in TIMED_CLASSES:
-            plan.time_kernel(cls, 1, stream)          # warm-up
-            ms, _, _ = plan.time_kernel(cls, n_launch, stream)
-            t0 += ms
-        timings[f"{rows}x{zc}x{fl}"] = t0
-    best = min(timings, key=timings.get)
-    rows, zc, fl = (int(v) for v in best.split("x"))
-    plan.set_tiling(rows, zc, fl)
+        ti = {f: _time(plan, zc, base | f, 0, which, n_launch, stream) for f in INTERIOR_FLAGS}
+        ts = {f: _time(plan, zc, base | f, 1, which, n_launch, stream) for f in SHELL_FLAGS}
+        fi = min(ti, key=ti.get)
+        fs = min(ts, key=ts.get)
+        total = ti[fi] + ts[fs]
+        flags = base | fi | fs
+        timings[f"z{zc}f{base}"] = dict(interior={str(k): round(v, 4) for k, v in ti.items()},
+                                        shell={str(k): round(v, 4) for k, v in ts.items()},
+                                        best=flags, ms=round(total, 4))
+        if best is None or total < best[0]:
+            best = (total, zc, flags)
+    total, zc, flags = best
+    plan.set_tiling(ROWS, zc, flags)
     plan.reset(which, stream)
-    rec = dict(rows=rows, zchunk=zc, flags=fl, ms_per_step=timings[best], timings=timings)
+    rec = dict(rows=ROWS, zchunk=zc, flags=flags, ms_per_step=total, timings=timings)
     if use_cache:
         with _lock:
             d = _load()

@@ -9,6 +9,7 @@
 #define YO_MAX_PORTS 8
 #define YO_MAX_SLOTS 32
 #define YO_TX 62          // owned x-cells per wave (lanes 1..62; lanes 0 and 63 are halo)
+#define YO_TY 4           // rows per wave
 #define YO_MAX_WPB 8      // waves per block of the step kernel: 4 or 8
 
 // Field arrays carry one ghost layer on every face and keep the components
@@ -62,8 +63,8 @@ struct YoPlanD {
 };
 
 // A tile is one wave's work (or, in the cooperative layout, one block's):
-// owned x in [x0, x0+xn) (xn <= 62), rows [j0, j0+jn) (jn <= TY, or
-// TY * waves per block), planes [k0, k1).  Packed as int4
+// owned x in [x0, x0+xn) (xn <= 62), rows [j0, j0+jn) (jn <= YO_TY, or
+// YO_TY * waves per block), planes [k0, k1).  Packed as int4
 // (x0 | xn << 16, j0 | jn << 16, k0 | k1 << 16, tile class).
 struct YoSlot {
     const YoPlanD *plan;
@@ -126,10 +127,12 @@ struct YoChainBufs {
 };
 
 // ---- kernel launchers ----
-// pm: tile class, bit 0/1/2 = the tiles touch the x/y/z absorbing slabs, or
-// 8: tiles of any class, each selecting its code by its class (int4 .w);
-// coop: one tile per block, its waves stacked in y (tiles of ty * wpb rows)
-hipError_t yo_launch_step(int ty, int pm, bool coop, const YoStepArgs &args, int blocks, hipStream_t s);
+// pm: 0 = interior tiles (no CPML code), 7 = CPML tiles with the code of all
+// three axes, 8 = CPML tiles each running its own class's code (int4 .w);
+// coop: one tile per block, its waves stacked in y (tiles of YO_TY * wpb
+// rows); prefetch: operands of the next plane loaded during this one
+hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &args, int blocks,
+                          hipStream_t s);
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);

@@ -70,6 +70,18 @@ int g_next_plan_id = 1;
 
 }  // namespace
 
+// Tiling flags (yo_set_tiling)
+enum {
+    YO_TILE_XSTRIPS = 1,      // CPML x-shell as full 62-cell strips
+    YO_TILE_WPB8 = 2,         // 8 waves per block (else 4)
+    YO_TILE_COOP_SHELL = 4,   // CPML shell: cooperative blocks
+    YO_TILE_CLASS_CODE = 8,   // CPML shell: each tile runs its own class's code
+    YO_TILE_COOP_INT = 16,    // interior: cooperative blocks
+    YO_TILE_NOPF_INT = 32,    // interior: no prefetch of the next plane
+    YO_TILE_NOPF_SHELL = 64,  // CPML shell: no prefetch of the next plane
+    YO_TILE_ALL = 127
+};
+
 struct yo_plan {
     int id = 0;
     int generation = 0;
@@ -108,10 +120,8 @@ struct yo_plan {
     std::vector<float> ginv;     // [n_freq][4]
     std::vector<double> omega_dt;
     std::vector<char> src_set, port_set;
-    int ty = 4, kc = 16, tflags = 0;   // tflags: 1 = merge CPML x-strips, 2 = 8 waves per block,
-                                       // 4 = cooperative blocks (waves stacked in y),
-                                       // 8 / 16 = one launch for all CPML classes
-    int cls_off[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // tile table offsets per class (8 classes)
+    int kc = 16, tflags = 0;     // z-planes per tile; tiling flags (YO_TILE_* below)
+    int n_int = 0, n_tiles = 0;  // tile table: interior tiles [0, n_int), CPML shell [n_int, n_tiles)
     bool bg_set = false, design_set = false;
     double beta = 0;
     int steps_done = 0;
@@ -275,51 +285,54 @@ void split_axis(int n, int lo, int hi, int w, std::vector<std::pair<int, int>> &
     }
 }
 
-// Tile table, grouped by class.  Bit a of a tile's class is set when the
-// tile's sites along axis a (owned, and the recomputed halo one below) can
-// meet a nonzero CPML coefficient of that axis; the region clear of the
-// axis' slabs is [lo + 1, n - hi) for a CPML of lo/hi cells.  Class 0 is the
-// interior.
+// Tile table: the interior tiles, then the CPML shell, each in space order
+// (z, y, x fastest).  Along each axis the region clear of the absorbing
+// slabs is [lo + 1, n - hi) for a CPML of lo/hi cells (no owned site and no
+// recomputed halo site one below meets a CPML coefficient); a tile is
+// interior when it lies in that region along all three axes.  A shell tile's
+// class (int4 .w) has bit a set when it is not clear along axis a.  The two
+// parts may use different row counts (cooperative blocks take YO_TY rows per
+// wave of the block).
 void build_tiles(yo_plan *p)
 {
     const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
-    std::vector<std::pair<int, int>> ax[3];
-    std::vector<char> in_ax[3];
-    // cooperative layout: one tile per block, its waves stacked in y
-    const int wpb = (p->tflags & 2) ? 8 : 4;
-    const int width[3] = {YO_TX, (p->tflags & 4) ? p->ty * wpb : p->ty, p->kc};
+    const int wpb = (p->tflags & YO_TILE_WPB8) ? 8 : 4;
+    int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-        int lo = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
-        int hi = n[a] - p->phi[a];
-        if (a == 0 && (p->tflags & 1)) {
+        lo[a] = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
+        hi[a] = n[a] - p->phi[a];
+        if (a == 0 && (p->tflags & YO_TILE_XSTRIPS)) {
             // full-width CPML strips: the shell strips also carry interior columns
-            if (p->plo[0] > 0) lo = std::max(lo, std::min(YO_TX, n[0]));
-            if (p->phi[0] > 0) hi = std::min(hi, n[0] - YO_TX);
+            if (p->plo[0] > 0) lo[0] = std::max(lo[0], std::min(YO_TX, n[0]));
+            if (p->phi[0] > 0) hi[0] = std::min(hi[0], n[0] - YO_TX);
         }
-        hi = std::max(hi, 0);
-        lo = std::min(lo, hi);
-        split_axis(n[a], lo, hi, width[a], ax[a], in_ax[a]);
+        hi[a] = std::max(hi[a], 0);
+        lo[a] = std::min(lo[a], hi[a]);
     }
-    // x fastest: the waves of a block take neighbouring x-strips of the
-    // same rows, so together they stream contiguous row segments
-    std::vector<int4> byc[8];
-    for (size_t iz = 0; iz < ax[2].size(); ++iz)
-        for (size_t iy = 0; iy < ax[1].size(); ++iy)
-            for (size_t ix = 0; ix < ax[0].size(); ++ix) {
-                int4 t;
-                t.x = ax[0][ix].first | (ax[0][ix].second << 16);
-                t.y = ax[1][iy].first | (ax[1][iy].second << 16);
-                t.z = ax[2][iz].first | ((ax[2][iz].first + ax[2][iz].second) << 16);
-                const int c = (in_ax[0][ix] ? 0 : 1) | (in_ax[1][iy] ? 0 : 2) | (in_ax[2][iz] ? 0 : 4);
-                t.w = c;
-                byc[c].push_back(t);
-            }
+    std::vector<std::pair<int, int>> ax, ay, az;
+    std::vector<char> ix, iy, iz;
+    split_axis(n[0], lo[0], hi[0], YO_TX, ax, ix);
+    split_axis(n[2], lo[2], hi[2], p->kc, az, iz);
+    auto emit = [&](bool shell, int rows, std::vector<int4> &out) {
+        split_axis(n[1], lo[1], hi[1], rows, ay, iy);
+        for (size_t k = 0; k < az.size(); ++k)
+            for (size_t j = 0; j < ay.size(); ++j)
+                for (size_t i = 0; i < ax.size(); ++i) {
+                    const int c = (ix[i] ? 0 : 1) | (iy[j] ? 0 : 2) | (iz[k] ? 0 : 4);
+                    if ((c != 0) != shell) continue;
+                    int4 t;
+                    t.x = ax[i].first | (ax[i].second << 16);
+                    t.y = ay[j].first | (ay[j].second << 16);
+                    t.z = az[k].first | ((az[k].first + az[k].second) << 16);
+                    t.w = c;
+                    out.push_back(t);
+                }
+    };
     p->tiles_host.clear();
-    for (int c = 0; c < 8; ++c) {
-        p->cls_off[c] = (int)p->tiles_host.size();
-        p->tiles_host.insert(p->tiles_host.end(), byc[c].begin(), byc[c].end());
-    }
-    p->cls_off[8] = (int)p->tiles_host.size();
+    emit(false, (p->tflags & YO_TILE_COOP_INT) ? YO_TY * wpb : YO_TY, p->tiles_host);
+    p->n_int = (int)p->tiles_host.size();
+    emit(true, (p->tflags & YO_TILE_COOP_SHELL) ? YO_TY * wpb : YO_TY, p->tiles_host);
+    p->n_tiles = (int)p->tiles_host.size();
 }
 
 size_t tiles_capacity(const yo_grid &g, int ty_min, int kc_min)
@@ -760,10 +773,9 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
 yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
-    if (rows != 4 && rows != 8) return fail(YO_EINVAL, "rows must be 4 or 8");
+    if (rows != YO_TY) return fail(YO_EINVAL, "rows per wave must be %d", YO_TY);
     if (zchunk < 4) return fail(YO_EINVAL, "zchunk must be >= 4");
-    if ((flags & ~31) || (flags & 24) == 24) return fail(YO_EINVAL, "unknown tiling flags");
-    p->ty = rows;
+    if (flags & ~YO_TILE_ALL) return fail(YO_EINVAL, "unknown tiling flags");
     p->kc = zchunk;
     p->tflags = flags;
     build_tiles(p);
@@ -923,26 +935,30 @@ static void aux_args(yo_plan *const *plans, const int *which, int cnt, bool dft,
 
 // Fill the step-kernel arguments of tile class `cls` for a plan list;
 // returns the number of blocks (0: no plan has tiles of that class).
-static int step_args(yo_plan *const *plans, const int *which, int cnt, int cls_lo, int cls_hi, int wpb,
-                     YoStepArgs &a)
+// Step-kernel arguments of one part (0 interior, 1 CPML shell) for a plan
+// list; returns the number of blocks (0: no plan has tiles there).
+static int step_args(yo_plan *const *plans, const int *which, int cnt, int part, YoStepArgs &a)
 {
     memset(&a, 0, sizeof(YoStepArgs));
     a.n_slots = cnt;
+    const int wpb = (plans[0]->tflags & YO_TILE_WPB8) ? 8 : 4;
+    const bool coop = (plans[0]->tflags & (part ? YO_TILE_COOP_SHELL : YO_TILE_COOP_INT)) != 0;
     int tot = 0;
     for (int i = 0; i < cnt; ++i) {
         yo_plan *p = plans[i];
         int r0, r1;
         set_rhs_range(p, which[i], r0, r1);
         YoSlot &sl = a.slot[i];
+        const int t0 = part ? p->n_int : 0, t1 = part ? p->n_tiles : p->n_int;
         sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
-        sl.tiles = wsp<int4>(p, p->L.tiles) + p->cls_off[cls_lo];
+        sl.tiles = wsp<int4>(p, p->L.tiles) + t0;
         sl.rhs0 = r0;
         sl.nrhs = std::max(r1 - r0, 1);
-        sl.ntile = (r1 > r0) ? p->cls_off[cls_hi] - p->cls_off[cls_lo] : 0;
+        sl.ntile = (r1 > r0) ? t1 - t0 : 0;
         a.prefix[i] = tot;
         // waves come in groups of wpb per right-hand side: wpb tiles, or in
         // the cooperative layout one tile
-        const int groups = (p->tflags & 4) ? sl.ntile : (sl.ntile + wpb - 1) / wpb;
+        const int groups = coop ? sl.ntile : (sl.ntile + wpb - 1) / wpb;
         tot += sl.nrhs * groups * wpb;
     }
     a.prefix[cnt] = tot;
@@ -951,62 +967,40 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int cls_l
     return (tot + wpb - 1) / wpb;
 }
 
-// The step launches of one step for a plan list: the interior class, then
-// the CPML tiles: each class on its own, or all in one launch that selects
-// each tile's class code (tiling flag 8) or runs the code of all three axes
-// (flag 16).  Returns the number of launches filled in (empty ones skipped).
-struct StepLaunch {
-    int pm, blocks;
-    YoStepArgs a;
-};
-static int step_launches(yo_plan *const *plans, const int *which, int cnt, int cls_sel, StepLaunch *out)
+// Launch one part's step kernel (the variant its tiling flags choose).
+static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, int blocks, hipStream_t s)
 {
-    const int wpb = (plans[0]->tflags & 2) ? 8 : 4;
-    const bool merged = (plans[0]->tflags & 8) != 0;
-    int n = 0;
-    auto add = [&](int lo, int hi, int pm) {
-        out[n].pm = pm;
-        out[n].blocks = step_args(plans, which, cnt, lo, hi, wpb, out[n].a);
-        if (out[n].blocks) ++n;
-    };
-    if (cls_sel >= 0 && cls_sel < 8) {
-        add(cls_sel, cls_sel + 1, cls_sel);
-        return n;
-    }
-    if (cls_sel < 0) add(0, 1, 0);
-    if (plans[0]->tflags & 16)
-        add(1, 8, 7);          // one launch, the code of all three axes
-    else if (merged)
-        add(1, 8, 8);          // one launch, each tile's own class code
-    else
-        for (int c = 1; c < 8; ++c) add(c, c + 1, c);
-    return n;
+    const int f = p0->tflags;
+    if (part == 0)
+        return yo_launch_step(0, (f & YO_TILE_COOP_INT) != 0, !(f & YO_TILE_NOPF_INT), a, blocks, s);
+    return yo_launch_step((f & YO_TILE_CLASS_CODE) ? 8 : 7, (f & YO_TILE_COOP_SHELL) != 0,
+                          !(f & YO_TILE_NOPF_SHELL), a, blocks, s);
 }
 
 // Launch `n_launch` steps (k_offset 0..n_launch-1) of a plan list, then add
 // n_launch to every plan's counter.  Per step: DFT of E^n (when `with_dft`),
-// the step launches (interior, CPML), the source.  Plans must share the
-// tiling rows and flags 2, 4 and 8.
+// the step launches (interior, CPML shell), the source.  Plans must share
+// every tiling flag but the x-strip one.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
                               bool with_dft, hipStream_t s)
 {
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
-        static thread_local StepLaunch L[8];
-        const int nl = step_launches(plans + base, which + base, cnt, -1, L);
+        static thread_local YoStepArgs A[2];
+        int blocks[2];
+        for (int part = 0; part < 2; ++part)
+            blocks[part] = step_args(plans + base, which + base, cnt, part, A[part]);
         YoAuxArgs ad, as;
         aux_args(plans + base, which + base, cnt, true, ad);
         aux_args(plans + base, which + base, cnt, false, as);
-        const int ty = plans[base]->ty;
-        const bool coop = (plans[base]->tflags & 4) != 0;
         for (int k = 0; k < n_launch; ++k) {
             if (with_dft) {
                 ad.k_offset = k;
                 HIPCHK(yo_launch_dft(ad, s));
             }
-            for (int i = 0; i < nl; ++i) {
-                L[i].a.k_offset = k;
-                HIPCHK(yo_launch_step(ty, L[i].pm, coop, L[i].a, L[i].blocks, s));
+            for (int part = 0; part < 2; ++part) {
+                A[part].k_offset = k;
+                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
             }
             as.k_offset = k;
             HIPCHK(yo_launch_source(as, s));
@@ -1044,8 +1038,8 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         yo_plan *p = plans[i];
         if (!p || !p->ws) return fail(YO_EWORKSPACE, "plan %d has no workspace", i);
         if (which[i] != p->active) return fail(YO_ESTATE, "plan %d: which differs from its reset", i);
-        if (p->ty != plans[0]->ty || (p->tflags & 30) != (plans[0]->tflags & 30))
-            return fail(YO_EINVAL, "plans in one call must share the tiling rows, block size and layout");
+        if ((p->tflags & ~YO_TILE_XSTRIPS) != (plans[0]->tflags & ~YO_TILE_XSTRIPS))
+            return fail(YO_EINVAL, "plans in one call must share the tiling flags (but the x-strip one)");
         for (int j = 0; j < i; ++j)
             if (plans[j] == p) return fail(YO_EINVAL, "plan listed twice");
     }
@@ -1059,7 +1053,7 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
     };
     int done = 0;
     if (use_graph && n_steps >= chunk) {
-        std::string key = "c" + std::to_string(chunk) + "t" + std::to_string(plans[0]->ty);
+        std::string key = "c" + std::to_string(chunk);
         for (int i = 0; i < n; ++i)
             key += "#" + std::to_string(plans[i]->id) + ":" + std::to_string(plans[i]->generation) +
                    "w" + std::to_string(which[i]) + "k" + std::to_string(plans[i]->kc) + "f" +
@@ -1226,18 +1220,17 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
 {
     if (!p || !avg_ms || !bytes || !cells) return fail(YO_EINVAL, "null argument");
     if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
-    if (cls < 0 || cls > 8 || n_launch < 1) return fail(YO_EINVAL, "bad class or count");
+    if (cls < 0 || cls > 1 || n_launch < 1) return fail(YO_EINVAL, "bad part or count");
     if (!p->active) return fail(YO_ESTATE, "yo_reset first");
     hipStream_t s = (hipStream_t)stream;
     int r0, r1;
     set_rhs_range(p, p->active, r0, r1);
-    static thread_local StepLaunch L[8];
-    const int nl = step_launches(&p, &p->active, 1, cls, L);
-    // owned cells of the timed classes and those inside each axis' absorbing slabs
+    static thread_local YoStepArgs A;
+    const int blocks = step_args(&p, &p->active, 1, cls, A);
+    // owned cells of the part and (cell, axis) pairs inside an absorbing slab
     const yo_grid &g = p->grid;
     double own = 0.0, in_pml = 0.0;
-    const int c_lo = cls < 8 ? cls : 1, c_hi = cls < 8 ? cls + 1 : 8;
-    for (int t = p->cls_off[c_lo]; t < p->cls_off[c_hi]; ++t) {
+    for (int t = cls ? p->n_int : 0; t < (cls ? p->n_tiles : p->n_int); ++t) {
         const int4 tt = p->tiles_host[t];
         const int x0 = tt.x & 0xffff, x1 = x0 + (tt.x >> 16);
         const int y0 = tt.y & 0xffff, y1 = y0 + (tt.y >> 16);
@@ -1256,7 +1249,7 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     const double R = r1 - r0;
     *bytes = own * (48.0 * R + 12.0) + 32.0 * R * in_pml;
     *cells = own * R;
-    if (!nl || r1 <= r0) {
+    if (!blocks || r1 <= r0) {
         *avg_ms = 0.0f;
         *bytes = *cells = 0.0;
         return YO_OK;
@@ -1265,9 +1258,7 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    for (int k = 0; k < n_launch; ++k)
-        for (int i = 0; i < nl; ++i)
-            HIPCHK(yo_launch_step(p->ty, L[i].pm, (p->tflags & 4) != 0, L[i].a, L[i].blocks, s));
+    for (int k = 0; k < n_launch; ++k) HIPCHK(launch_part(p, cls, A, blocks, s));
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.0f;

@@ -148,15 +148,14 @@ __device__ __forceinline__ void h_cpml(const YoPlanD &P, const YoRhsD &R, int pa
     }
 }
 
-// CPML corrections of the six differences of one E site (single buffered:
-// each E memory is read and written by its owner only).
+// CPML corrections of the six differences of one owned E site (single
+// buffered: each E memory is read and written by its owner only).
 template <int PM>
 __device__ __forceinline__ void e_cpml(const YoPlanD &P, const YoRhsD &R, int x, int j, int k, int pxs,
-                                       int pz, const Cpml &cxE, bool own, float &dxHz, float &dxHy,
-                                       float &dyHz, float &dyHx, float &dzHy, float &dzHx)
+                                       int pz, const Cpml &cxE, float &dxHz, float &dxHy, float &dyHz,
+                                       float &dyHx, float &dzHy, float &dzHx)
 {
-    const int nx = P.nx, ny = P.ny, nz = P.nz, nxp = P.nxp;
-    if (!(x >= 0 && x < nx && j >= 0 && j < ny && k >= 0 && k < nz)) return;
+    const int ny = P.ny, nz = P.nz, nxp = P.nxp;
     const int Wx = P.plo[0] + P.phi[0], Wy = P.plo[1] + P.phi[1], Wz = P.plo[2] + P.phi[2];
     const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
     if ((PM & 1) && pxs >= 0) {
@@ -166,7 +165,7 @@ __device__ __forceinline__ void e_cpml(const YoPlanD &P, const YoRhsD &R, int x,
         float n0, n1;
         dxHz = pml_diff(dxHz, cxE, (ps + r0)[pxs], n0);   // Ey
         dxHy = pml_diff(dxHy, cxE, (ps + r1)[pxs], n1);   // Ez
-        if (own) { (ps + r0)[pxs] = n0; (ps + r1)[pxs] = n1; }
+        (ps + r0)[pxs] = n0; (ps + r1)[pxs] = n1;
     }
     if ((PM & 2) && py >= 0) {
         float *ps = R.psiE[1];
@@ -176,7 +175,7 @@ __device__ __forceinline__ void e_cpml(const YoPlanD &P, const YoRhsD &R, int x,
         float n0, n1;
         dyHz = pml_diff(dyHz, cy, (ps + r0)[x], n0);   // Ex
         dyHx = pml_diff(dyHx, cy, (ps + r1)[x], n1);   // Ez
-        if (own) { (ps + r0)[x] = n0; (ps + r1)[x] = n1; }
+        (ps + r0)[x] = n0; (ps + r1)[x] = n1;
     }
     if ((PM & 4) && pz >= 0) {
         float *ps = R.psiE[2];
@@ -186,7 +185,7 @@ __device__ __forceinline__ void e_cpml(const YoPlanD &P, const YoRhsD &R, int x,
         float n0, n1;
         dzHy = pml_diff(dzHy, cz, (ps + r0)[x], n0);   // Ex
         dzHx = pml_diff(dzHx, cz, (ps + r1)[x], n1);   // Ey
-        if (own) { (ps + r0)[x] = n0; (ps + r1)[x] = n1; }
+        (ps + r0)[x] = n0; (ps + r1)[x] = n1;
     }
 }
 
@@ -211,7 +210,7 @@ __device__ __forceinline__ void block_sync_lds()
 // row above and Ht_x, Ht_z of the row below.  Only the block's bottom wave
 // recomputes the Ht row below the block and only its top wave loads the E
 // row above it; one barrier per plane.
-template <int TY, int PM, bool COOP>
+template <int TY, int PM, bool COOP, bool PF>
 __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, const int step,
                                           const int4 t, const int w, const int lane, float *xs)
 {
@@ -247,11 +246,6 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     const int x = x0 - 1 + lane;
     const int xo = (clampi(x, -1, nx) + 1) * (int)sizeof(float);   // column byte offset (ghost clamped)
     const bool own_x = (lane >= 1) && (lane <= xn);
-    // Stores are unconditional (no branch around them, so the compiler can
-    // count outstanding memory operations exactly); a lane with nothing to
-    // store gives an offset past the end of the buffer, and the hardware's
-    // range check drops the write.
-    const int jo = (int)0x80000000;
     // wave-uniform byte offsets of row group (j, k) in the state and kappa arrays
     auto ro = [&](int j, int k) -> int {
         return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 6 * rowb;
@@ -278,11 +272,12 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     float Hc[3][TY + 1];      // Ht of the current plane, rows j0-1..j0+TY-1
     float Ho_[3][TY + 1], Kv[3][TY];
 
-    // Operands of plane k are in registers when plane k starts: E(k) in Ec,
-    // E(k+1) in Enx, old Ht(k) in Ho_, kappa(k) in Kv.  The loads for plane
-    // k+1 are issued before plane k's stores, because the vector-memory
-    // counter also counts stores and a wait placed after them would wait for
-    // the stores too.
+    // Plane k works on E(k) in Ec, E(k+1) in Enx, old Ht(k) in Ho_ and
+    // kappa(k) in Kv.  PF (prefetch): those are in registers when plane k
+    // starts, and the loads for plane k+1 are issued before plane k's stores,
+    // because the vector-memory counter also counts stores and a wait placed
+    // after them would wait for the stores too.  Without PF a plane loads its
+    // own operands (fewer registers, more waves to hide the latency).
     // rows a wave never loads (the row below unless bottom, the row above
     // unless top) are filled from neighbours or never read
     auto load_plane = [&](int k, float (&en)[3][TY + 2], float (&ho)[3][TY + 1],
@@ -336,13 +331,17 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     }
 #pragma unroll
     for (int r = 0; r < TY; ++r) { Hp[0][r] = 0.0f; Hp[1][r] = 0.0f; }
-    load_plane(k0 - 1, Enx, Ho_, Kv);
+    if (PF) load_plane(k0 - 1, Enx, Ho_, Kv);
 
     for (int k = k0 - 1; k < k1; ++k) {
         const bool own_k = (k >= k0);
         float Enx2[3][TY + 2], Ho2[3][TY + 1], Kv2[3][TY];
-        // unconditional (the last plane re-reads itself) so the wait counts stay exact
-        load_plane(k + 1 < k1 ? k + 1 : k, Enx2, Ho2, Kv2);
+        if (PF) {
+            // unconditional (the last plane re-reads itself) so the wait counts stay exact
+            load_plane(k + 1 < k1 ? k + 1 : k, Enx2, Ho2, Kv2);
+        } else {
+            load_plane(k, Enx, Ho_, Kv);
+        }
         int pz = -1;
         if (PM & 4) pz = slab_index(k, nz, P.plo[2], P.phi[2]);
         const int pp = k & 1;
@@ -374,12 +373,11 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             Hc[0][r] = hx;
             Hc[1][r] = hy;
             Hc[2][r] = hz;
-            if (r >= 1) {
+            if (own) {
                 const int o = ro(j, k) + hb;
-                const int so = own ? xo : jo;
-                bstore(hx, Fn, so, o);
-                bstore(hy, Fn, so, rowb + o);
-                bstore(hz, Fn, so, 2 * rowb + o);
+                bstore(hx, Fn, xo, o);
+                bstore(hy, Fn, xo, rowb + o);
+                bstore(hz, Fn, xo, 2 * rowb + o);
             }
         }
         if (COOP) {
@@ -401,15 +399,15 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             const int j = j0 - 1 + r;
             const float hz_im = shfl_prev(Hc[2][r]);
             const float hy_im = shfl_prev(Hc[1][r]);
-            const bool own = own_x && own_k && (r <= jn);
+            if (!own_k || r > jn) continue;
             float dyHz = Hc[2][r] - Hc[2][r - 1];
             float dzHy = Hc[1][r] - Hp[1][r - 1];
             float dzHx = Hc[0][r] - Hp[0][r - 1];
             float dxHz = Hc[2][r] - hz_im;
             float dxHy = Hc[1][r] - hy_im;
             float dyHx = Hc[0][r] - Hc[0][r - 1];
-            if (PM)
-                e_cpml<PM>(P, R, x, j, k, pxs, pz, cxE, own, dxHz, dxHy, dyHz, dyHx, dzHy, dzHx);
+            if (PM && own_x)
+                e_cpml<PM>(P, R, x, j, k, pxs, pz, cxE, dxHz, dxHy, dyHz, dyHx, dzHy, dzHx);
             float ex = fmaf(Kv[0][r - 1], fmaf(sy, dyHz, -(sz * dzHy)), Ec[0][r]);
             float ey = fmaf(Kv[1][r - 1], fmaf(sz, dzHx, -(sx * dxHz)), Ec[1][r]);
             float ez = fmaf(Kv[2][r - 1], fmaf(sx, dxHy, -(sy * dyHx)), Ec[2][r]);
@@ -417,12 +415,11 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             ex = (j == 0 || k == 0) ? 0.0f : ex;
             ey = (x == 0 || k == 0) ? 0.0f : ey;
             ez = (x == 0 || j == 0) ? 0.0f : ez;
-            {
+            if (own_x) {
                 const int o = ro(j, k) + eb;
-                const int so = own ? xo : jo;
-                bstore(ex, Fn, so, o);
-                bstore(ey, Fn, so, rowb + o);
-                bstore(ez, Fn, so, 2 * rowb + o);
+                bstore(ex, Fn, xo, o);
+                bstore(ey, Fn, xo, rowb + o);
+                bstore(ez, Fn, xo, 2 * rowb + o);
             }
         }
 #pragma unroll
@@ -435,46 +432,48 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 Ec[c][r] = Enx[c][r];
-                Enx[c][r] = Enx2[c][r];
+                if (PF) Enx[c][r] = Enx2[c][r];
             }
         }
+        if (PF) {
 #pragma unroll
-        for (int r = 0; r <= TY; ++r) {
+            for (int r = 0; r <= TY; ++r) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Ho_[c][r] = Ho2[c][r];
-        }
+                for (int c = 0; c < 3; ++c) Ho_[c][r] = Ho2[c][r];
+            }
 #pragma unroll
-        for (int r = 0; r < TY; ++r) {
+            for (int r = 0; r < TY; ++r) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Kv[c][r] = Kv2[c][r];
+                for (int c = 0; c < 3; ++c) Kv[c][r] = Kv2[c][r];
+            }
         }
     }
 }
 
-// PM = YO_PM_ANY: tiles of every CPML class in one launch; each tile's class
-// (int4 .w) selects its code.
+// PM = YO_PM_ANY: tiles of every CPML class in one launch, each tile's class
+// (int4 .w) selecting its code.
 #define YO_PM_ANY 8
-template <int TY, int PM, bool COOP>
+template <int PM, bool COOP, bool PF>
 __device__ __forceinline__ void tile_step(const YoPlanD &P, const YoRhsD &R, int step, const int4 t,
                                           int w, int lane, float *xs)
 {
     if constexpr (PM == YO_PM_ANY) {
         switch (t.w) {
-        case 1: wave_step<TY, 1, COOP>(P, R, step, t, w, lane, xs); break;
-        case 2: wave_step<TY, 2, COOP>(P, R, step, t, w, lane, xs); break;
-        case 3: wave_step<TY, 3, COOP>(P, R, step, t, w, lane, xs); break;
-        case 4: wave_step<TY, 4, COOP>(P, R, step, t, w, lane, xs); break;
-        case 5: wave_step<TY, 5, COOP>(P, R, step, t, w, lane, xs); break;
-        case 6: wave_step<TY, 6, COOP>(P, R, step, t, w, lane, xs); break;
-        case 7: wave_step<TY, 7, COOP>(P, R, step, t, w, lane, xs); break;
-        default: wave_step<TY, 0, COOP>(P, R, step, t, w, lane, xs); break;
+        case 1: wave_step<YO_TY, 1, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 2: wave_step<YO_TY, 2, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 3: wave_step<YO_TY, 3, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 4: wave_step<YO_TY, 4, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 5: wave_step<YO_TY, 5, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 6: wave_step<YO_TY, 6, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 7: wave_step<YO_TY, 7, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        default: wave_step<YO_TY, 0, COOP, PF>(P, R, step, t, w, lane, xs); break;
         }
     } else {
-        wave_step<TY, PM, COOP>(P, R, step, t, w, lane, xs);
+        wave_step<YO_TY, PM, COOP, PF>(P, R, step, t, w, lane, xs);
     }
 }
 
-template <int TY, int PM, bool COOP>
+template <int PM, bool COOP, bool PF>
 __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -504,7 +503,7 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
         const int r = sl.rhs0 + blk % sl.nrhs;
         const int ti = blk / sl.nrhs;
         if (ti >= sl.ntile) return;
-        tile_step<TY, PM, true>(P, P.rhs[r], step, sl.tiles[ti], w, lane, xs);
+        tile_step<PM, true, PF>(P, P.rhs[r], step, sl.tiles[ti], w, lane, xs);
     } else {
         // A block's waves take consecutive tiles (neighbouring x-strips of
         // the same rows) of one right-hand side, so together they stream
@@ -515,10 +514,9 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
         const int r = sl.rhs0 + in_grp / wpb;
         const int ti = grp * wpb + in_grp % wpb;
         if (ti >= sl.ntile) return;
-        tile_step<TY, PM, false>(P, P.rhs[r], step, sl.tiles[ti], 0, lane, nullptr);
+        tile_step<PM, false, PF>(P, P.rhs[r], step, sl.tiles[ti], 0, lane, nullptr);
     }
 }
-
 
 // locate point q of slot s in the aux work list
 __device__ __forceinline__ bool aux_point(const YoAuxArgs &a, int &s, int &r, int &q)
@@ -621,40 +619,36 @@ __global__ void k_ctr(const YoCtrArgs a, int set_value)
 
 }  // namespace
 
-template <int PM, bool COOP>
-static void launch_one(int ty, const YoStepArgs &args, int blocks, hipStream_t s)
+template <int PM, bool COOP, bool PF>
+static void launch_one(const YoStepArgs &args, int blocks, hipStream_t s)
 {
-    const dim3 blk(64 * args.wpb);
-    if (ty == 4)
-        hipLaunchKernelGGL((k_yee_step<4, PM, COOP>), dim3(blocks), blk, 0, s, args);
-    else
-        hipLaunchKernelGGL((k_yee_step<8, PM, COOP>), dim3(blocks), blk, 0, s, args);
+    hipLaunchKernelGGL((k_yee_step<PM, COOP, PF>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
 }
 
-template <bool COOP>
-static hipError_t launch_pm(int ty, int pm, const YoStepArgs &args, int blocks, hipStream_t s)
+template <int PM>
+static void launch_pm(bool coop, bool pf, const YoStepArgs &args, int blocks, hipStream_t s)
 {
-    switch (pm) {
-    case 0: launch_one<0, COOP>(ty, args, blocks, s); break;
-    case 1: launch_one<1, COOP>(ty, args, blocks, s); break;
-    case 2: launch_one<2, COOP>(ty, args, blocks, s); break;
-    case 3: launch_one<3, COOP>(ty, args, blocks, s); break;
-    case 4: launch_one<4, COOP>(ty, args, blocks, s); break;
-    case 5: launch_one<5, COOP>(ty, args, blocks, s); break;
-    case 6: launch_one<6, COOP>(ty, args, blocks, s); break;
-    case 7: launch_one<7, COOP>(ty, args, blocks, s); break;
-    case YO_PM_ANY: launch_one<YO_PM_ANY, COOP>(ty, args, blocks, s); break;
-    default: return hipErrorInvalidValue;
+    if (coop) {
+        if (pf) launch_one<PM, true, true>(args, blocks, s);
+        else launch_one<PM, true, false>(args, blocks, s);
+    } else {
+        if (pf) launch_one<PM, false, true>(args, blocks, s);
+        else launch_one<PM, false, false>(args, blocks, s);
     }
-    return hipGetLastError();
 }
 
-hipError_t yo_launch_step(int ty, int pm, bool coop, const YoStepArgs &args, int blocks, hipStream_t s)
+hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &args, int blocks,
+                          hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
-    if (ty != 4 && ty != 8) return hipErrorInvalidValue;
-    return coop ? launch_pm<true>(ty, pm, args, blocks, s) : launch_pm<false>(ty, pm, args, blocks, s);
+    switch (pm) {
+    case 0: launch_pm<0>(coop, prefetch, args, blocks, s); break;
+    case 7: launch_pm<7>(coop, prefetch, args, blocks, s); break;
+    case YO_PM_ANY: launch_pm<YO_PM_ANY>(coop, prefetch, args, blocks, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s)

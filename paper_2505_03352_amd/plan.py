@@ -161,6 +161,7 @@ class Plan:
         self._C = C
 
     def set_tiling(self, rows: int, zchunk: int, flags: int = 0):
+        """Work split of the time-stepping kernel (see yo_set_tiling)."""
         call("yo_set_tiling", self._h, int(rows), int(zchunk), int(flags))
         self.tiling = (int(rows), int(zchunk), int(flags))
 
@@ -241,10 +242,9 @@ class Plan:
 
     def time_kernel(self, cls: int = 0, n_launch: int = 20, stream=None):
         """(avg ms per launch, algorithmic bytes per launch, cell-updates per
-        launch) of one tile class (0..7, bit a: touches the absorbing slabs
-        of axis a; 0 = interior; 8 = all CPML classes as a solve launches
-        them) of the time-stepping kernel, by HIP events.  An empty class
-        gives zeros."""
+        launch) of one part of the time-stepping kernel (0: interior tiles,
+        1: CPML shell), by HIP events on the stream.  An empty part gives
+        zeros."""
         ms, b, c = ct.c_float(), ct.c_double(), ct.c_double()
         call("yo_time_kernel", self._h, int(cls), int(n_launch), ct.byref(ms), ct.byref(b),
              ct.byref(c), _stream(stream))

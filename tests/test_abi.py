@@ -109,12 +109,11 @@ def test_calls_before_bind_fail_cleanly():
     L = _abi.lib()
     assert L.yo_reset(p.handle, _abi.YO_BOTH, None) == _abi.YO_EWORKSPACE
     assert L.yo_finalize(p.handle, _abi.YO_BOTH, None) == _abi.YO_EWORKSPACE
-    assert L.yo_set_tiling(p.handle, 5, 16, 0) == _abi.YO_EINVAL
-    assert L.yo_set_tiling(p.handle, 4, 16, 32) == _abi.YO_EINVAL
-    assert L.yo_set_tiling(p.handle, 4, 16, 24) == _abi.YO_EINVAL
-    assert L.yo_set_tiling(p.handle, 8, 8, 3) == _abi.YO_OK
-    assert L.yo_set_tiling(p.handle, 4, 16, 15) == _abi.YO_OK
-    assert L.yo_set_tiling(p.handle, 4, 16, 23) == _abi.YO_OK
+    assert L.yo_set_tiling(p.handle, 8, 16, 0) == _abi.YO_EINVAL
+    assert L.yo_set_tiling(p.handle, 4, 3, 0) == _abi.YO_EINVAL
+    assert L.yo_set_tiling(p.handle, 4, 16, 128) == _abi.YO_EINVAL
+    assert L.yo_set_tiling(p.handle, 4, 8, 3) == _abi.YO_OK
+    assert L.yo_set_tiling(p.handle, 4, 16, 127) == _abi.YO_OK
     p.close()
 
 

@@ -45,8 +45,9 @@ def closed_box_plan(nx, ny, nz, kappa, n_steps, courant=0.5):
     return p
 
 
-# tilings: (rows per wave, z-planes, flags); flag 4 = cooperative blocks
-@pytest.mark.parametrize("rows,zchunk,flags", [(4, 16, 0), (8, 8, 0), (4, 16, 4), (8, 8, 6)])
+# work splits (rows per wave, z-planes, flags); a closed box has no CPML
+# shell, so only the interior choices matter: 16 cooperative, 32 no prefetch
+@pytest.mark.parametrize("rows,zchunk,flags", [(4, 16, 0), (4, 8, 32), (4, 16, 16), (4, 8, 50)])
 @pytest.mark.parametrize("mnp,eps", [((2, 3, 0), 2.085), ((1, 2, 1), 12.11), ((0, 2, 1), 1.0)])
 def test_cavity_eigenmode(mnp, eps, rows, zchunk, flags):
     nx, ny, nz = 70, 44, 36
@@ -130,10 +131,11 @@ def test_fields_match_oracle_with_cpml_and_source():
     dt = 0.5 * 40e-9 / 299792458.0
     f = FreqSpec(w_dt / dt, 40.0, steps - 60, 60)
     outs = {}
-    # flag 4: cooperative blocks (its y-slab tiles of 7 rows leave idle
-    # waves); flags 8 and 16: all CPML classes in one launch
-    for rows, zc, fl in [(4, 16, 0), (8, 8, 1), (4, 4, 2), (8, 64, 3), (4, 16, 4), (4, 16, 5),
-                         (8, 8, 6), (4, 4, 7), (4, 16, 13), (8, 8, 10), (4, 16, 17), (4, 8, 21)]:
+    # every interior and shell choice (see yo_set_tiling); cooperative shell
+    # blocks on the y-slabs of 7 rows leave idle waves
+    for rows, zc, fl in [(4, 16, 0), (4, 8, 1), (4, 4, 2), (4, 64, 3), (4, 16, 4), (4, 16, 13),
+                         (4, 8, 70), (4, 4, 23), (4, 16, 45), (4, 8, 122), (4, 16, 77),
+                         (4, 8, 53)]:
         say(f"cpml+source fields tiling=({rows},{zc},{fl})")
         p = Plan(grid, design, steps, [f], [pl], [], device="cuda")
         p.bind()
