@@ -246,6 +246,18 @@ yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
 yo_status yo_time_kernel(yo_plan *plan, int cls, int n_launch, float *avg_ms, double *bytes,
                          double *cells, yo_stream stream);
 
+/* Launch timing inside a solve: with n_last > 0, every later yo_advance,
+ * yo_run or yo_advance_many (with this plan first in its list) runs its
+ * last n_last steps with plain launches and records a pair of HIP events on
+ * its stream around each launch of `part` (0 interior tiles, 1 CPML shell);
+ * n_last = 0 turns it off.  n_last <= 4096; events are created here and
+ * owned by the plan.  Host only.  YO_EINVAL on a bad part or count. */
+yo_status yo_set_timing(yo_plan *plan, int part, int n_last);
+
+/* Mean duration of the launches timed by the last advance (waits for the
+ * last of them); count = how many (0: none, avg_ms = 0). */
+yo_status yo_get_timing(yo_plan *plan, float *avg_ms, int *count);
+
 const char *yo_last_error(void);
 const char *yo_version(void);
 

@@ -77,6 +77,8 @@ _SIGS = {
     "yo_advance_many": [ct.POINTER(_P), ct.POINTER(_I), _I, _I, _I, _I, _S],
     "yo_steps_done": [_P, ct.POINTER(_I)],
     "yo_set_tiling": [_P, _I, _I, _I],
+    "yo_set_timing": [_P, _I, _I],
+    "yo_get_timing": [_P, ct.POINTER(ct.c_float), ct.POINTER(ct.c_int)],
     "yo_alpha": [_P, _P, _S],
     "yo_gradient": [_P, _P, _P, _S],
     "yo_gradient_kappa": [_P, _P, _P, _S],

@@ -128,6 +128,10 @@ struct yo_plan {
     int active = 0;              // which right-hand sides the last reset selected
     bool finalized = false;
     hipStream_t cap_stream = nullptr;
+    // launch timing: the last tm_n steps of each advance run eagerly, with
+    // HIP events around part tm_part's launch (pairs in tm_ev)
+    int tm_part = 0, tm_n = 0, tm_done = 0;
+    std::vector<hipEvent_t> tm_ev;
 };
 
 namespace {
@@ -582,6 +586,7 @@ void yo_plan_destroy(yo_plan *p)
         }
     }
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (hipEvent_t e : p->tm_ev) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -982,7 +987,7 @@ static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, 
 // the step launches (interior, CPML shell), the source.  Plans must share
 // every tiling flag but the x-strip one.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
-                              bool with_dft, hipStream_t s)
+                              bool with_dft, hipStream_t s, yo_plan *timed = nullptr)
 {
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
@@ -1000,7 +1005,11 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
             }
             for (int part = 0; part < 2; ++part) {
                 A[part].k_offset = k;
+                const bool tm = timed && base == 0 && part == timed->tm_part && blocks[part] &&
+                                timed->tm_done < timed->tm_n;
+                if (tm) HIPCHK(hipEventRecord(timed->tm_ev[2 * timed->tm_done], s));
                 HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
+                if (tm) HIPCHK(hipEventRecord(timed->tm_ev[2 * timed->tm_done++ + 1], s));
             }
             as.k_offset = k;
             HIPCHK(yo_launch_source(as, s));
@@ -1045,6 +1054,11 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
     }
     hipStream_t s = (hipStream_t)stream;
     if (chunk < 1) chunk = 1;
+    // launch timing (yo_set_timing on the first plan): the last tm_n steps
+    // of this call run eagerly with events around the timed part
+    yo_plan *timed = plans[0]->tm_n > 0 ? plans[0] : nullptr;
+    const int tail = timed ? std::min(timed->tm_n, n_steps) : 0;
+    if (timed) timed->tm_done = 0;
     // steps_done is advanced per chunk so chunk_needs_dft sees the current steps
     std::vector<int> start(n);
     for (int i = 0; i < n; ++i) start[i] = plans[i]->steps_done;
@@ -1052,14 +1066,14 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         for (int i = 0; i < n; ++i) plans[i]->steps_done += k;
     };
     int done = 0;
-    if (use_graph && n_steps >= chunk) {
+    if (use_graph && n_steps - tail >= chunk) {
         std::string key = "c" + std::to_string(chunk);
         for (int i = 0; i < n; ++i)
             key += "#" + std::to_string(plans[i]->id) + ":" + std::to_string(plans[i]->generation) +
                    "w" + std::to_string(which[i]) + "k" + std::to_string(plans[i]->kc) + "f" +
                    std::to_string(plans[i]->tflags);
         GraphEntry ge[2];
-        while (n_steps - done >= chunk) {
+        while (n_steps - tail - done >= chunk) {
             const int variant = chunk_needs_dft(plans, which, n, chunk) ? 1 : 0;
             const std::string kv = key + (variant ? "|dft" : "|nodft");
             if (!ge[variant].exec) {
@@ -1092,8 +1106,11 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         }
     }
     while (done < n_steps) {
-        const int k = std::min(chunk, n_steps - done);
-        yo_status st = launch_steps(plans, which, n, k, chunk_needs_dft(plans, which, n, k), s);
+        const bool in_tail = done >= n_steps - tail;
+        const int lim = in_tail ? n_steps - done : n_steps - tail - done;
+        const int k = std::min(chunk, lim);
+        yo_status st = launch_steps(plans, which, n, k, chunk_needs_dft(plans, which, n, k), s,
+                                    in_tail ? timed : nullptr);
         if (st) return st;
         done += k;
         bump(k);
@@ -1212,6 +1229,39 @@ yo_status yo_chain_vjp(yo_plan *p, const float *gk, float *dFdC, yo_stream strea
     HIPCHK(yo_launch_fill(p->chain.gmap, 4 * (size_t)p->G0 * p->G1, 0.0f, s));
     HIPCHK(yo_launch_zsum(gk, p->box, p->des.k_lo, p->des.k_hi, p->chain.gmap, p->G0, p->G1, s));
     HIPCHK(yo_launch_chain_vjp(p->chain, (float)p->beta, dFdC, s));
+    return YO_OK;
+}
+
+yo_status yo_set_timing(yo_plan *p, int part, int n_last)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (part < 0 || part > 1 || n_last < 0 || n_last > 4096) return fail(YO_EINVAL, "bad part or count");
+    const size_t need = 2 * (size_t)n_last;
+    while (p->tm_ev.size() < need) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        p->tm_ev.push_back(e);
+    }
+    p->tm_part = part;
+    p->tm_n = n_last;
+    p->tm_done = 0;
+    return YO_OK;
+}
+
+yo_status yo_get_timing(yo_plan *p, float *avg_ms, int *count)
+{
+    if (!p || !avg_ms || !count) return fail(YO_EINVAL, "null argument");
+    *avg_ms = 0.0f;
+    *count = p->tm_done;
+    if (!p->tm_done) return YO_OK;
+    HIPCHK(hipEventSynchronize(p->tm_ev[2 * p->tm_done - 1]));
+    double tot = 0.0;
+    for (int i = 0; i < p->tm_done; ++i) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, p->tm_ev[2 * i], p->tm_ev[2 * i + 1]));
+        tot += ms;
+    }
+    *avg_ms = (float)(tot / p->tm_done);
     return YO_OK;
 }
 

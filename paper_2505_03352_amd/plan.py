@@ -250,6 +250,17 @@ class Plan:
              ct.byref(c), _stream(stream))
         return float(ms.value), float(b.value), float(c.value)
 
+    def set_timing(self, part: int = 0, n_last: int = 100):
+        """Time the launches of one part (0 interior, 1 CPML shell) over the
+        last `n_last` steps of every later advance (0: off)."""
+        call("yo_set_timing", self._h, int(part), int(n_last))
+
+    def timing(self):
+        """(mean ms per timed launch, launches timed) of the last advance."""
+        ms, n = ct.c_float(), ct.c_int()
+        call("yo_get_timing", self._h, ct.byref(ms), ct.byref(n))
+        return float(ms.value), int(n.value)
+
     def model_bytes(self, which=YO_BOTH):
         b, c = ct.c_double(), ct.c_double()
         call("yo_model_bytes", self._h, which, ct.byref(b), ct.byref(c))

@@ -391,3 +391,24 @@ def test_conjugate_views_are_resolved():
     g2 = p.gradient(torch.conj(a).resolve_conj()).cpu().numpy()  # materialised
     assert np.array_equal(g1, g2)
     p.close()
+
+
+def test_launch_timing_keeps_results_and_counts_launches():
+    """Timing the last steps' launches (plain launches with events) leaves
+    the fields bitwise unchanged."""
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro(n_steps=500)
+    res = []
+    for timed in (False, True):
+        say(f"launch timing {timed}")
+        p = plan_for(dev)
+        if timed:
+            p.set_timing(0, 64)
+        p.run(3, chunk=50, use_graph=True)
+        res.append((p.get_dft(0, 0).cpu().numpy(), p.alpha().cpu().numpy()))
+        if timed:
+            ms, n = p.timing()
+            assert n == 64 and ms > 0
+        p.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
