@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: arrival rate, requests/s")
+    ap.add_argument("--max-cells", type=float, default=4.5e7,
+                    help="serving: cap on cell-updates per step of the admitted requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -239,7 +241,7 @@ def bench_batch(args):
     log("batch: " + ", ".join(f"{d.nx}x{d.ny}x{d.nz}/{d.n_steps}" for d in devs))
     cells = sum(2 * d.cells * d.n_steps for d in devs)
     plans = [plan_for(d, device="cuda:0") for d in devs]
-    batch.shared_tiling(plans, 4, 1, zchunk=16)
+    batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS, zchunk=16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.solve(plans, chunk=args.chunk, use_graph=True)
@@ -289,9 +291,11 @@ def bench_serving(args):
     budget = int(0.8 * free)
     out = {}
     for name, slots in (("served", args.slots), ("one_at_a_time", 1)):
-        ex = GpuExecutor(build, device="cuda:0", tiling=(4, 16, 1), chunk=args.chunk)
+        ex = GpuExecutor(build, device="cuda:0", chunk=args.chunk)
         reqs = [Request(i, t, (i, cls, lams)) for i, (t, cls, lams) in enumerate(trace)]
-        st = Scheduler(ex, max_slots=slots, hbm_budget=budget, chunk=args.chunk).run(reqs)
+        cap = args.max_cells if slots > 1 else None
+        st = Scheduler(ex, max_slots=slots, hbm_budget=budget, chunk=args.chunk,
+                       max_active_cells=cap).run(reqs)
         torch.cuda.synchronize()
         out[name] = st
         log(f"{name}: {st.as_dict()}")
@@ -301,6 +305,7 @@ def bench_serving(args):
           {"workload": f"serving: first {args.requests} of 200 Poisson arrivals at {args.rate:g} req/s, "
                        "sizes 96^3+-8 / 200x160x80 / 320x240x96, 1-3 wavelengths, forward + "
                        "adjoint + gradient, seed 200", "slots": args.slots,
+           "max_active_cell_updates_per_step": args.max_cells,
            "hbm_budget_bytes": budget},
           {"p50_s": round(s.p50_s, 3), "p99_s": round(s.p99_s, 3),
            "gcell_updates_per_s": round(s.cell_updates / s.makespan_s / 1e9, 3),

@@ -19,9 +19,15 @@ from ._abi import YO_BOTH
 from .plan import Plan, advance_many
 
 
-def shared_tiling(plans: Sequence[Plan], rows: int, flags: int, zchunk: Optional[int] = None):
-    """Give every plan the same rows/block size (required to share launches);
-    z-chunk and the CPML x-strip choice stay per plan unless given."""
+# x-strips, cooperative CPML shell with per-class code and no prefetch: the
+# split the autotuner picks on the realistic device
+DEFAULT_FLAGS = 77
+
+
+def shared_tiling(plans: Sequence[Plan], rows: int = 4, flags: int = DEFAULT_FLAGS,
+                  zchunk: Optional[int] = None):
+    """Give every plan the same split flags (required to share launches);
+    the z-chunk stays per plan unless given."""
     for p in plans:
         zc = zchunk if zchunk is not None else getattr(p, "tiling", (rows, 16, flags))[1]
         p.set_tiling(rows, zc, flags)

@@ -6,9 +6,12 @@ wavelengths, alpha and the gradient dF/dC.  Requests arrive over time
 
   * prepares each arrived request on the host (geometry, plan descriptors)
     in a worker thread, in arrival order;
-  * admits the request at the head of the queue when a slot is free and its
-    device footprint fits in the free part of the HBM budget (FIFO: a
-    request that does not fit yet holds back the ones behind it);
+  * admits the request at the head of the queue when a slot is free, its
+    device footprint fits in the free part of the HBM budget and, if a work
+    cap is set, the cell-updates per step of everything admitted stay under
+    it (more resident work than saturates the GPU's bandwidth only stretches
+    every latency; FIFO: a request that does not fit yet holds back the ones
+    behind it);
   * advances every admitted request together, in shared launches, one chunk
     of steps at a time; new requests join and finished ones leave at chunk
     boundaries, so requests that arrive while others run overlap with them
@@ -105,7 +108,7 @@ class Scheduler:
     """FIFO admission by slot and HBM footprint; chunked shared stepping."""
 
     def __init__(self, executor, max_slots: int = 8, hbm_budget: int = 64 << 30, chunk: int = 100,
-                 clock=None, prep_workers: int = 2):
+                 clock=None, prep_workers: int = 2, max_active_cells: Optional[float] = None):
         if max_slots < 1 or chunk < 1:
             raise ValueError("max_slots and chunk must be >= 1")
         self.ex = executor
@@ -114,6 +117,7 @@ class Scheduler:
         self.chunk = int(chunk)
         self.clock = clock or RealClock()
         self.prep_workers = prep_workers
+        self.max_active_cells = max_active_cells
         self.events: List[tuple] = []      # (time, kind, rid) for inspection
 
     def _log(self, kind, rid):
@@ -178,6 +182,10 @@ class Scheduler:
                         continue
                     if used + job.footprint > self.budget:
                         break
+                    if self.max_active_cells is not None and active:
+                        work = sum(self.ex.cells_per_step(j) for j in active)
+                        if work + self.ex.cells_per_step(job) > self.max_active_cells:
+                            break
                     queue.popleft()
                     used += job.footprint
                     peak = max(peak, used)
@@ -247,7 +255,7 @@ class GpuExecutor:
     are in flight, which keeps admission decisions close to the GPU's
     progress."""
 
-    def __init__(self, build: Callable, device="cuda:0", tiling=(4, 16, 1), use_graph=False,
+    def __init__(self, build: Callable, device="cuda:0", tiling=(4, 16, 77), use_graph=False,
                  chunk: int = 100):
         import torch
         from . import _abi  # noqa: F401  (fails loudly without the library)

@@ -161,3 +161,13 @@ def test_percentiles_and_stats():
 def test_bad_parameters():
     with pytest.raises(ValueError):
         Scheduler(FakeExecutor(FakeClock()), max_slots=0)
+
+
+def test_work_cap_limits_concurrency_but_not_progress():
+    # each request steps 300k cells; a cap of 700k cells admits two at a time,
+    # and a single request above the cap still runs (alone)
+    reqs = make([(0.0, (300_000, 100, 1)) for _ in range(5)] + [(0.0, (900_000, 50, 1))])
+    st, sch, ex = run(reqs, max_slots=8, chunk=20, max_active_cells=700_000)
+    assert st.n_done == 6
+    assert max(len(c) for c in ex.calls) == 2
+    assert any(c == (5,) for c in ex.calls)               # the big one ran alone
