@@ -173,7 +173,7 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
 
 /* Work split of the time-stepping kernel.  Each step runs two launches: the
  * interior tiles (clear of every absorbing slab, no CPML code) and the CPML
- * shell.  rows: rows per wave, must be 4; zchunk: z-planes per tile (>= 4);
+ * shell.  rows: rows per wave, must be 4; zchunk: z-planes per tile, 4..63;
  * flags, a sum of:
  *    1  the CPML x-shell is cut into full 62-cell strips instead of just
  *       the absorbing columns

@@ -30,8 +30,11 @@ struct YoPlaneD {
 // sums, source plane and per-step phase table.
 struct YoRhsD {
     float *F[2];             // double-buffered state, ghost layout, nc = 6 (E then Ht)
-    float *psiE[3];          // per axis: [2][slab] (single buffer)
-    float *psiH[2][3];       // [buffer][axis]: [2][slab]
+    // CPML memories: per axis a, at float offset psi_off[a] of the plan, six
+    // arrays of psi_n[a] floats: E (2 components), Ht step parity 0 (2),
+    // Ht parity 1 (2); each [2 comps] of the axis' slab layout
+    // (x [nz][ny][Wx], y [nz][Wy][nxp], z [Wz][ny][nxp])
+    float *psi;
     float2 *dft_box;         // [3][bz][by][bx]
     float2 *dft_mon;         // concatenated port planes [2][n1][n0]
     const float4 *steptab;   // [n_steps]: (ramp cos, ramp sin) at (n+1/2)dt, (cos, sin) at n dt
@@ -50,6 +53,8 @@ struct YoPlanD {
     int plo[3], phi[3];      // PML cells low/high per axis
     const float *kappa;      // ghost layout (ghost values unused)
     const float *prof[3];    // per axis [6][n_a]: bE cE kiE bH cH kiH
+    int psi_off[3], psi_n[3];
+    int psi_total;           // floats of CPML memory per right-hand side
     int box[6];              // x0 y0 z0 bx by bz
     int n_ports;
     int n_steps;

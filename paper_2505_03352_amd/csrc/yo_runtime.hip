@@ -494,6 +494,10 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
         off += 6 * slab[a];
     }
     p->psi_per_rhs = off;
+    if (off * sizeof(float) >= ((size_t)1 << 31)) {
+        delete p;
+        return fail(YO_EUNSUPPORTED, "the CPML memories of one right-hand side must stay below 2 GiB");
+    }
     p->box[0] = d.i0 - 1;
     p->box[1] = d.j0 - 1;
     p->box[2] = d.k_lo - 1;
@@ -625,6 +629,11 @@ static yo_status rebuild_descriptors(yo_plan *p)
     P.prof[1] = prof + 6 * (size_t)g.nx;
     P.prof[2] = prof + 6 * (size_t)(g.nx + g.ny);
     for (int i = 0; i < 6; ++i) P.box[i] = p->box[i];
+    for (int a = 0; a < 3; ++a) {
+        P.psi_off[a] = (int)p->psi_axis_off[a];
+        P.psi_n[a] = (int)p->psi_axis_n[a];
+    }
+    P.psi_total = (int)p->psi_per_rhs;
     P.n_ports = p->n_ports;
     P.n_steps = p->n_steps;
     P.mon_total = (int)p->mon_total;
@@ -650,14 +659,7 @@ static yo_status rebuild_descriptors(yo_plan *p)
         float *f = fields + fields_per_rhs(p) * r;
         R.F[0] = f;
         R.F[1] = f + 6 * p->cells_p;
-        float *ps = psi + p->psi_per_rhs * r;
-        for (int a = 0; a < 3; ++a) {
-            float *base = ps + p->psi_axis_off[a];
-            const size_t n = p->psi_axis_n[a];
-            R.psiE[a] = n ? base : nullptr;
-            R.psiH[0][a] = n ? base + 2 * n : nullptr;
-            R.psiH[1][a] = n ? base + 4 * n : nullptr;
-        }
+        R.psi = psi + p->psi_per_rhs * r;
         R.dft_box = dbox + 3 * p->bsz * r;
         R.dft_mon = dmon + std::max<size_t>(p->mon_total, 1) * r;
         int f_idx, srcp;
@@ -779,7 +781,8 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
     if (rows != YO_TY) return fail(YO_EINVAL, "rows per wave must be %d", YO_TY);
-    if (zchunk < 4) return fail(YO_EINVAL, "zchunk must be >= 4");
+    // a tile's planes and the halo plane below are at most one per lane
+    if (zchunk < 4 || zchunk > 63) return fail(YO_EINVAL, "zchunk must be in [4, 63]");
     if (flags & ~YO_TILE_ALL) return fail(YO_EINVAL, "unknown tiling flags");
     p->kc = zchunk;
     p->tflags = flags;

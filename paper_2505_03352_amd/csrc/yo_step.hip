@@ -102,94 +102,183 @@ __device__ __forceinline__ int sel3(int a, int v0, int v1, int v2)
     return a == 0 ? v0 : (a == 1 ? v1 : v2);
 }
 
+// What the CPML code needs of the plan and the right-hand side, read once
+// per tile before any store (a store to global memory would otherwise make
+// the compiler reload the descriptors with vector loads and wait for them),
+// plus the y and z profile coefficients of the tile's rows and planes, one
+// row (plane) per lane, taken out with readlane when used.
+struct CpmlCtx {
+    int nx, ny, nz, nxp;
+    int plo[3], phi[3], W[3];
+    int off[3], n[3];        // CPML memory layout (floats), see YoRhsD
+    Rsrc ps;                 // this right-hand side's CPML memories
+    Cpml cyE, cyH;           // lane l: row j0 - 1 + l
+    Cpml czE, czH;           // lane l: plane k0 - 1 + l
+    int j0m, k0m;            // j0 - 1, k0 - 1
+};
+
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ Cpml lane_cpml(const Cpml &c, int l)
+{
+    Cpml o;
+    o.b = lane_value(c.b, l);
+    o.c = lane_value(c.c, l);
+    o.ki = lane_value(c.ki, l);
+    return o;
+}
+
+// Byte offsets of CPML memory q (0, 1: E components; 2 + 2 par + c: Ht) of
+// axis A at site (x, j, k): the lane part (voff) and the wave-uniform part
+// (soff); false when the site is outside the axis' slabs.
+template <int A>
+__device__ __forceinline__ bool psi_at(const CpmlCtx &C, int q, int x, int j, int k, int pxs,
+                                       int &voff, int &soff)
+{
+    if (A == 0) {
+        voff = pxs * (int)sizeof(float);
+        soff = (C.off[0] + q * C.n[0] + (k * C.ny + j) * C.W[0]) * (int)sizeof(float);
+        return pxs >= 0;
+    }
+    if (A == 1) {
+        const int py = slab_index(j, C.ny, C.plo[1], C.phi[1]);
+        voff = x * (int)sizeof(float);
+        soff = (C.off[1] + q * C.n[1] + (k * C.W[1] + py) * C.nxp) * (int)sizeof(float);
+        return py >= 0;
+    }
+    const int pz = slab_index(k, C.nz, C.plo[2], C.phi[2]);
+    voff = x * (int)sizeof(float);
+    soff = (C.off[2] + q * C.n[2] + (pz * C.ny + j) * C.nxp) * (int)sizeof(float);
+    return pz >= 0;
+}
+
 // CPML corrections of the six differences of one Ht site row (x = this
 // lane, row j, plane k): each difference inside an absorbing slab of its
 // axis becomes d/kp + psi with psi <- b psi + c d.  Ht's memories are
 // double-buffered by step parity (halo rows recompute Ht, reading psi of
-// the old step); only the owner writes the new value.
-template <int PM>
-__device__ __forceinline__ void h_cpml(const YoPlanD &P, const YoRhsD &R, int par, int x, int j, int k,
-                                       int pxs, int pz, const Cpml &cxH, bool own, float &dxEz,
-                                       float &dxEy, float &dyEz, float &dyEx, float &dzEy, float &dzEx)
+// the old step); only the owner writes the new value.  PRE: the old values
+// were loaded with the plane's fields (q[axis][component]); else they are
+// loaded here.
+template <int PM, bool PRE>
+__device__ __forceinline__ void h_cpml(const CpmlCtx &C, int par, int x, int j, int k, int pxs,
+                                       const Cpml &cxH, bool own, const float (&q)[3][2],
+                                       float &dxEz, float &dxEy, float &dyEz, float &dyEx,
+                                       float &dzEy, float &dzEx)
 {
-    const int nx = P.nx, ny = P.ny, nz = P.nz, nxp = P.nxp;
-    const bool xin = (x >= 0) && (x < nx);
-    const bool jin = (j >= 0) && (j < ny);
+    const bool xin = (x >= 0) && (x < C.nx);
+    const bool jin = (j >= 0) && (j < C.ny);
     if (!(jin && xin && k >= 0)) return;
-    const int Wx = P.plo[0] + P.phi[0], Wy = P.plo[1] + P.phi[1], Wz = P.plo[2] + P.phi[2];
-    const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
-    float *const *psiO = R.psiH[par];
-    float *const *psiN = R.psiH[par ^ 1];
-    if ((PM & 1) && pxs >= 0) {
-        const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
-        const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
+    const int qo = 2 + 2 * par, qn = 2 + 2 * (par ^ 1);
+    int v, s0, s1, t0, t1;
+    if ((PM & 1) && psi_at<0>(C, qo, x, j, k, pxs, v, s0)) {
+        psi_at<0>(C, qo + 1, x, j, k, pxs, v, s1);
         float n0, n1;
-        dxEz = pml_diff(dxEz, cxH, (psiO[0] + r0)[pxs], n0);   // Hy
-        dxEy = pml_diff(dxEy, cxH, (psiO[0] + r1)[pxs], n1);   // Hz
-        if (own) { (psiN[0] + r0)[pxs] = n0; (psiN[0] + r1)[pxs] = n1; }
+        dxEz = pml_diff(dxEz, cxH, PRE ? q[0][0] : bload(C.ps, v, s0), n0);   // Hy
+        dxEy = pml_diff(dxEy, cxH, PRE ? q[0][1] : bload(C.ps, v, s1), n1);   // Hz
+        if (own) {
+            psi_at<0>(C, qn, x, j, k, pxs, v, t0);
+            psi_at<0>(C, qn + 1, x, j, k, pxs, v, t1);
+            bstore(n0, C.ps, v, t0);
+            bstore(n1, C.ps, v, t1);
+        }
     }
-    if ((PM & 2) && py >= 0) {
-        const Cpml cy = cpml_at(P.prof[1], ny, 3, j);
-        const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
-        const size_t r1 = (((size_t)1 * nz + k) * Wy + py) * nxp;
+    if ((PM & 2) && psi_at<1>(C, qo, x, j, k, pxs, v, s0)) {
+        psi_at<1>(C, qo + 1, x, j, k, pxs, v, s1);
+        const Cpml cy = lane_cpml(C.cyH, j - C.j0m);
         float n0, n1;
-        dyEz = pml_diff(dyEz, cy, (psiO[1] + r0)[x], n0);   // Hx
-        dyEx = pml_diff(dyEx, cy, (psiO[1] + r1)[x], n1);   // Hz
-        if (own) { (psiN[1] + r0)[x] = n0; (psiN[1] + r1)[x] = n1; }
+        dyEz = pml_diff(dyEz, cy, PRE ? q[1][0] : bload(C.ps, v, s0), n0);   // Hx
+        dyEx = pml_diff(dyEx, cy, PRE ? q[1][1] : bload(C.ps, v, s1), n1);   // Hz
+        if (own) {
+            psi_at<1>(C, qn, x, j, k, pxs, v, t0);
+            psi_at<1>(C, qn + 1, x, j, k, pxs, v, t1);
+            bstore(n0, C.ps, v, t0);
+            bstore(n1, C.ps, v, t1);
+        }
     }
-    if ((PM & 4) && pz >= 0) {
-        const Cpml cz = cpml_at(P.prof[2], nz, 3, k);
-        const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
-        const size_t r1 = (((size_t)1 * Wz + pz) * ny + j) * nxp;
+    if ((PM & 4) && psi_at<2>(C, qo, x, j, k, pxs, v, s0)) {
+        psi_at<2>(C, qo + 1, x, j, k, pxs, v, s1);
+        const Cpml cz = lane_cpml(C.czH, k - C.k0m);
         float n0, n1;
-        dzEy = pml_diff(dzEy, cz, (psiO[2] + r0)[x], n0);   // Hx
-        dzEx = pml_diff(dzEx, cz, (psiO[2] + r1)[x], n1);   // Hy
-        if (own) { (psiN[2] + r0)[x] = n0; (psiN[2] + r1)[x] = n1; }
+        dzEy = pml_diff(dzEy, cz, PRE ? q[2][0] : bload(C.ps, v, s0), n0);   // Hx
+        dzEx = pml_diff(dzEx, cz, PRE ? q[2][1] : bload(C.ps, v, s1), n1);   // Hy
+        if (own) {
+            psi_at<2>(C, qn, x, j, k, pxs, v, t0);
+            psi_at<2>(C, qn + 1, x, j, k, pxs, v, t1);
+            bstore(n0, C.ps, v, t0);
+            bstore(n1, C.ps, v, t1);
+        }
     }
 }
 
 // CPML corrections of the six differences of one owned E site (single
-// buffered: each E memory is read and written by its owner only).
-template <int PM>
-__device__ __forceinline__ void e_cpml(const YoPlanD &P, const YoRhsD &R, int x, int j, int k, int pxs,
-                                       int pz, const Cpml &cxE, float &dxHz, float &dxHy, float &dyHz,
+// buffered: each E memory is read and written by its owner only).  PRE as
+// for h_cpml.
+template <int PM, bool PRE>
+__device__ __forceinline__ void e_cpml(const CpmlCtx &C, int x, int j, int k, int pxs, const Cpml &cxE,
+                                       const float (&q)[3][2], float &dxHz, float &dxHy, float &dyHz,
                                        float &dyHx, float &dzHy, float &dzHx)
 {
-    const int ny = P.ny, nz = P.nz, nxp = P.nxp;
-    const int Wx = P.plo[0] + P.phi[0], Wy = P.plo[1] + P.phi[1], Wz = P.plo[2] + P.phi[2];
-    const int py = (PM & 2) ? slab_index(j, ny, P.plo[1], P.phi[1]) : -1;
-    if ((PM & 1) && pxs >= 0) {
-        float *ps = R.psiE[0];
-        const size_t r0 = ((size_t)0 * nz + k) * ny * Wx + (size_t)j * Wx;
-        const size_t r1 = ((size_t)1 * nz + k) * ny * Wx + (size_t)j * Wx;
+    int v, s0, s1;
+    if ((PM & 1) && psi_at<0>(C, 0, x, j, k, pxs, v, s0)) {
+        psi_at<0>(C, 1, x, j, k, pxs, v, s1);
         float n0, n1;
-        dxHz = pml_diff(dxHz, cxE, (ps + r0)[pxs], n0);   // Ey
-        dxHy = pml_diff(dxHy, cxE, (ps + r1)[pxs], n1);   // Ez
-        (ps + r0)[pxs] = n0; (ps + r1)[pxs] = n1;
+        dxHz = pml_diff(dxHz, cxE, PRE ? q[0][0] : bload(C.ps, v, s0), n0);   // Ey
+        dxHy = pml_diff(dxHy, cxE, PRE ? q[0][1] : bload(C.ps, v, s1), n1);   // Ez
+        bstore(n0, C.ps, v, s0);
+        bstore(n1, C.ps, v, s1);
     }
-    if ((PM & 2) && py >= 0) {
-        float *ps = R.psiE[1];
-        const Cpml cy = cpml_at(P.prof[1], ny, 0, j);
-        const size_t r0 = (((size_t)0 * nz + k) * Wy + py) * nxp;
-        const size_t r1 = (((size_t)1 * nz + k) * Wy + py) * nxp;
+    if ((PM & 2) && psi_at<1>(C, 0, x, j, k, pxs, v, s0)) {
+        psi_at<1>(C, 1, x, j, k, pxs, v, s1);
+        const Cpml cy = lane_cpml(C.cyE, j - C.j0m);
         float n0, n1;
-        dyHz = pml_diff(dyHz, cy, (ps + r0)[x], n0);   // Ex
-        dyHx = pml_diff(dyHx, cy, (ps + r1)[x], n1);   // Ez
-        (ps + r0)[x] = n0; (ps + r1)[x] = n1;
+        dyHz = pml_diff(dyHz, cy, PRE ? q[1][0] : bload(C.ps, v, s0), n0);   // Ex
+        dyHx = pml_diff(dyHx, cy, PRE ? q[1][1] : bload(C.ps, v, s1), n1);   // Ez
+        bstore(n0, C.ps, v, s0);
+        bstore(n1, C.ps, v, s1);
     }
-    if ((PM & 4) && pz >= 0) {
-        float *ps = R.psiE[2];
-        const Cpml cz = cpml_at(P.prof[2], nz, 0, k);
-        const size_t r0 = (((size_t)0 * Wz + pz) * ny + j) * nxp;
-        const size_t r1 = (((size_t)1 * Wz + pz) * ny + j) * nxp;
+    if ((PM & 4) && psi_at<2>(C, 0, x, j, k, pxs, v, s0)) {
+        psi_at<2>(C, 1, x, j, k, pxs, v, s1);
+        const Cpml cz = lane_cpml(C.czE, k - C.k0m);
         float n0, n1;
-        dzHy = pml_diff(dzHy, cz, (ps + r0)[x], n0);   // Ex
-        dzHx = pml_diff(dzHx, cz, (ps + r1)[x], n1);   // Ey
-        (ps + r0)[x] = n0; (ps + r1)[x] = n1;
+        dzHy = pml_diff(dzHy, cz, PRE ? q[2][0] : bload(C.ps, v, s0), n0);   // Ex
+        dzHx = pml_diff(dzHx, cz, PRE ? q[2][1] : bload(C.ps, v, s1), n1);   // Ey
+        bstore(n0, C.ps, v, s0);
+        bstore(n1, C.ps, v, s1);
     }
 }
 
-// PM: which axes' absorbing slabs the tile touches (bit 0 x, bit 1 y, bit 2 z)
+// Old CPML memories q (0, 1: E; 2 + 2 par + c: Ht) of every axis in PM at one
+// site, or 0 where `use` is false or the site is outside the slab (such a
+// lane's offset is past the buffer, so the load moves no data and the
+// loads need no branch).
+template <int PM>
+__device__ __forceinline__ void psi_preload(const CpmlCtx &C, int q, int x, int j, int k, int pxs,
+                                            bool use, float (&out)[3][2])
+{
+    const int far = (int)0x80000000;
+    int v, s0, s1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!(PM & (1 << a))) continue;
+        bool in = false;
+        if (a == 0) {
+            in = psi_at<0>(C, q, x, j, k, pxs, v, s0);
+            psi_at<0>(C, q + 1, x, j, k, pxs, v, s1);
+        } else if (a == 1) {
+            in = psi_at<1>(C, q, x, j, k, pxs, v, s0);
+            psi_at<1>(C, q + 1, x, j, k, pxs, v, s1);
+        } else {
+            in = psi_at<2>(C, q, x, j, k, pxs, v, s0);
+            psi_at<2>(C, q + 1, x, j, k, pxs, v, s1);
+        }
+        in = in && use;
+        out[a][0] = bload(C.ps, in ? v : far, in ? s0 : 0);
+        out[a][1] = bload(C.ps, in ? v : far, in ? s1 : 0);
+    }
+}
+
 // Exchange slots of a cooperative block, per plane parity and wave: Ex and
 // Ez of the wave's first row (next plane), Ht_x and Ht_z of its last row.
 #define YO_XS_FLOATS (2 * YO_MAX_WPB * 4 * 64)
@@ -254,16 +343,46 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
         return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 3 * rowb;
     };
 
-    // ---- CPML data of this lane along x (CPML class only) ----
-    const float *profx = P.prof[0];
+    // ---- CPML data (CPML classes only), read before any store ----
     const bool xin = (x >= 0) && (x < nx);
     int pxs = -1;
     Cpml cxE = {1.0f, 0.0f, 1.0f}, cxH = {1.0f, 0.0f, 1.0f};
-    if ((PM & 1) && xin) {
-        pxs = slab_index(x, nx, P.plo[0], P.phi[0]);
-        if (pxs >= 0) {
-            cxE = cpml_at(profx, nx, 0, x);
-            cxH = cpml_at(profx, nx, 3, x);
+    CpmlCtx C;
+    if (PM) {
+        C.nx = nx; C.ny = ny; C.nz = nz; C.nxp = nxp;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C.plo[a] = P.plo[a];
+            C.phi[a] = P.phi[a];
+            C.W[a] = P.plo[a] + P.phi[a];
+            C.off[a] = P.psi_off[a];
+            C.n[a] = P.psi_n[a];
+        }
+        C.ps = rsrc_of(R.psi, (size_t)P.psi_total);
+        C.j0m = j0 - 1;
+        C.k0m = k0 - 1;
+        const Cpml one = {1.0f, 0.0f, 1.0f};
+        C.cyE = C.cyH = C.czE = C.czH = one;
+        if ((PM & 2) && lane <= TY) {
+            const int jj = j0 - 1 + lane;
+            if (jj >= 0 && jj < ny && slab_index(jj, ny, P.plo[1], P.phi[1]) >= 0) {
+                C.cyE = cpml_at(P.prof[1], ny, 0, jj);
+                C.cyH = cpml_at(P.prof[1], ny, 3, jj);
+            }
+        }
+        if (PM & 4) {
+            const int kk = k0 - 1 + lane;
+            if (kk >= 0 && kk < k1 && slab_index(kk, nz, P.plo[2], P.phi[2]) >= 0) {
+                C.czE = cpml_at(P.prof[2], nz, 0, kk);
+                C.czH = cpml_at(P.prof[2], nz, 3, kk);
+            }
+        }
+        if ((PM & 1) && xin) {
+            pxs = slab_index(x, nx, P.plo[0], P.phi[0]);
+            if (pxs >= 0) {
+                cxE = cpml_at(P.prof[0], nx, 0, x);
+                cxH = cpml_at(P.prof[0], nx, 3, x);
+            }
         }
     }
 
@@ -342,8 +461,24 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
         } else {
             load_plane(k, Enx, Ho_, Kv);
         }
-        int pz = -1;
-        if (PM & 4) pz = slab_index(k, nz, P.plo[2], P.phi[2]);
+        // CPML tiles without prefetch: the plane's old CPML memories are
+        // loaded here with its fields, so one wait covers both
+        constexpr bool PRE = PM != 0 && !PF;
+        float qH[TY + 1][3][2], qE[TY][3][2];
+        if constexpr (PRE) {
+            const bool kin = k >= 0 && k < nz;
+#pragma unroll
+            for (int r = 0; r <= TY; ++r) {
+                const int j = j0 - 1 + r;
+                const bool use = (r > 0 || bottom) && xin && kin && j >= 0 && j < ny;
+                psi_preload<PM>(C, 2 + 2 * par, x, j, k, pxs, use, qH[r]);
+            }
+#pragma unroll
+            for (int r = 1; r <= TY; ++r) {
+                const bool use = own_x && k >= k0 && r <= jn;
+                psi_preload<PM>(C, 0, x, j0 - 1 + r, k, pxs, use, qE[r - 1]);
+            }
+        }
         const int pp = k & 1;
         if (COOP) {
             // E of plane k+1, first row: the wave below's row above
@@ -366,7 +501,8 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             float dyEx = Ec[0][r + 1] - Ec[0][r];
             const bool own = own_x && own_k && (r >= 1) && (r <= jn);
             if (PM)
-                h_cpml<PM>(P, R, par, x, j, k, pxs, pz, cxH, own, dxEz, dxEy, dyEz, dyEx, dzEy, dzEx);
+                h_cpml<PM, PRE>(C, par, x, j, k, pxs, cxH, own, qH[r], dxEz, dxEy, dyEz, dyEx, dzEy,
+                                dzEx);
             const float hx = Ho_[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
             const float hy = Ho_[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
             const float hz = Ho_[2][r] - fmaf(sx, dxEy, -(sy * dyEx));
@@ -407,7 +543,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             float dxHy = Hc[1][r] - hy_im;
             float dyHx = Hc[0][r] - Hc[0][r - 1];
             if (PM && own_x)
-                e_cpml<PM>(P, R, x, j, k, pxs, pz, cxE, dxHz, dxHy, dyHz, dyHx, dzHy, dzHx);
+                e_cpml<PM, PRE>(C, x, j, k, pxs, cxE, qE[r - 1], dxHz, dxHy, dyHz, dyHx, dzHy, dzHx);
             float ex = fmaf(Kv[0][r - 1], fmaf(sy, dyHz, -(sz * dzHy)), Ec[0][r]);
             float ey = fmaf(Kv[1][r - 1], fmaf(sz, dzHx, -(sx * dxHz)), Ec[1][r]);
             float ez = fmaf(Kv[2][r - 1], fmaf(sx, dxHy, -(sy * dyHx)), Ec[2][r]);
