@@ -19,9 +19,9 @@ from ._abi import YO_BOTH
 from .plan import Plan, advance_many
 
 
-# x-strips, cooperative CPML shell with per-class code and no prefetch: the
+# x-strips, CPML shell with per-class code and no prefetch: the
 # split the autotuner picks on the realistic device
-DEFAULT_FLAGS = 77
+DEFAULT_FLAGS = 73
 
 
 def shared_tiling(plans: Sequence[Plan], rows: int = 4, flags: int = DEFAULT_FLAGS,
