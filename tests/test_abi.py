@@ -126,3 +126,15 @@ def test_model_bytes_matches_traffic_model():
     per = b / c
     assert 48 + 2 <= per <= 70
     p.close()
+
+
+def test_size_limits_rejected():
+    dev = configs.tiny()
+    # a state array of one right-hand side beyond 2 GiB
+    with pytest.raises(_abi.YeeOptError) as e:
+        _create(dev, grid={"nx": 700, "ny": 700, "nz": 300})
+    assert e.value.status == _abi.YO_EUNSUPPORTED
+    # a grid too small for its CPML and tiles
+    with pytest.raises(_abi.YeeOptError) as e:
+        _create(dev, grid={"nx": 3})
+    assert e.value.status == _abi.YO_EINVAL

@@ -328,6 +328,7 @@ def test_realistic_full_size_short_run_fields_match_oracle():
     dev = configs.realistic(n_steps=150, wavelengths=[1.55e-6])
     say("realistic full-size fields: GPU")
     p = plan_for(dev)
+    p.set_tiling(4, 16, 73)
     p.reset(1)
     p.advance(1, 150)
     E, H = p.get_fields(0)
@@ -344,6 +345,64 @@ def test_realistic_full_size_short_run_fields_match_oracle():
     eH = np.abs(H - r.H).max() / np.abs(r.H).max()
     say(f"  max rel err E {eE:.2e} H {eH:.2e}")
     assert eE < 1e-4 and eH < 1e-4
+
+
+def test_multiport_full_size_short_run_fields_match_oracle():
+    """The 600x400x120 multi-port grid (1 wavelength: 1 forward + 4 adjoint
+    right-hand sides), 100 steps from rest with the input source on, in the
+    bench's work split: every field value of the forward right-hand side
+    against the oracle."""
+    from paper_2505_03352_amd.plan import plan_for
+    from oracle import ports
+    dev = configs.multiport(n_steps=100, wavelengths=[1.55e-6])
+    say("multi-port full-size fields: GPU")
+    p = plan_for(dev)
+    p.set_tiling(4, 16, 73)
+    p.reset(3)
+    p.advance(3, 100)
+    E, H = p.get_fields(0)
+    E, H = E.cpu().numpy(), H.cpu().numpy()
+    kap = p.get_kappa().cpu().numpy().astype(np.float64)
+    p.close()
+    say("multi-port full-size fields: oracle")
+    prm = adjoint.sim_params(dev, dev.wavelengths[0])
+    r = fdtd.run(prm, kap, src_plane=dev.sources[0].plane,
+                 src_j=ports.source_current(dev.sources[0].h))
+    eE = np.abs(E - r.E).max() / np.abs(r.E).max()
+    eH = np.abs(H - r.H).max() / np.abs(r.H).max()
+    say(f"  max rel err E {eE:.2e} H {eH:.2e}")
+    assert eE < 1e-4 and eH < 1e-4
+
+
+@pytest.mark.parametrize("c_value,beta", [(0.0, 8.0), (1.0, 8.0), (0.5, 1000.0)])
+def test_degenerate_designs_match_oracle(c_value, beta):
+    """Uniform controls (all cladding, all core, and exactly grey under a
+    near-step projection): kappa equals the oracle's, alpha and the gradient
+    stay finite and match it."""
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.tiny()
+    dev.C = np.full_like(dev.C, c_value)
+    dev.beta = beta
+    say(f"degenerate design C={c_value} beta={beta}")
+    p = plan_for(dev)
+    p.run(3, chunk=100, use_graph=True)
+    a = p.alpha()
+    g = p.gradient(torch.conj(a)).cpu().numpy()
+    kap = p.get_kappa().cpu().numpy()
+    a = a.cpu().numpy()
+    p.close()
+    say("  oracle")
+    res = adjoint.forward_adjoint(dev)
+    assert np.abs(kap - res.kappa).max() < 1e-5 * np.abs(res.kappa).max()
+    ao = res.alpha[0, 0, 0]
+    go = adjoint.grad_C(dev, res, np.conj(res.alpha))
+    assert np.isfinite(g).all() and np.isfinite(a).all()
+    assert abs(a[0, 0, 0] - ao) < 1e-4 * abs(ao)
+    scale = np.abs(go).max()
+    if scale > 0:
+        assert rel_l2(g, go) < 1e-3
+    else:
+        assert np.abs(g).max() == 0.0
 
 
 def test_autograd_function_matches_library_and_finite_differences():
