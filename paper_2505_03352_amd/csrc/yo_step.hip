@@ -1,6 +1,7 @@
-// Fused Yee time step for gfx950.  One launch per tile class advances every
-// tile of that class of every selected right-hand side by one full step (Ht
-// half step, then E step).  Two
+// Fused Yee time step for gfx950.  Each step is two launches over every
+// selected right-hand side of every plan in the call: the interior tiles
+// (clear of every absorbing slab, no CPML code) and the CPML shell; each
+// advances its tiles by one full step (Ht half step, then E step).  Two
 // small kernels bracket them: the running DFT of E^n (design box and port
 // planes) before the step, and the soft current source after it.
 //
@@ -10,13 +11,13 @@
 // every difference along axis a scaled by S_a = c dt / d_a; in a CPML slab
 // the difference d becomes d/k + psi with psi <- b psi + c d.
 //
-// Work decomposition (one wave = 64 lanes is the unit of work; waves of a
-// block are independent: no LDS, no barrier):
+// Work decomposition (one wave = 64 lanes):
 //   * lane l handles x = x0 - 1 + l.  Lanes 1..xn own their cells; lane 0
 //     (x0-1) and the lane after the last owned one are halo lanes whose
-//     values reach the owners through cross-lane shuffles.
-//   * a wave owns rows j0..j0+jn-1 (jn <= TY) and recomputes the Ht of row
-//     j0-1, which the E update of row j0 needs.
+//     values reach the owners through DPP whole-wave shifts.
+//   * a wave owns rows j0..j0+jn-1 (jn <= 4) and recomputes the Ht of row
+//     j0-1, which the E update of row j0 needs (or, in cooperative blocks,
+//     takes it and the E row above from its neighbours through LDS).
 //   * a wave marches z-planes k0..k1-1, carrying E of the next plane and the
 //     Ht of the previous plane in registers; it starts one plane early to
 //     recompute Ht(k0-1).
@@ -27,13 +28,13 @@
 // a zero ghost layer, so every load is unconditional: indices outside the
 // grid are clamped onto the ghost layer and read zero.
 //
-// Tiles are sorted into eight classes by the absorbing slabs (x, y, z)
-// their owned and halo sites touch; each class runs an instantiation that
-// contains the CPML code of exactly those axes (none for the interior).
+// A CPML tile's class (bit a: it meets the absorbing slab of axis a) picks
+// an instantiation with the CPML code of exactly those axes, or the shell
+// runs the code of all three.
 //
-// Launch: blocks of 4 waves, dispatched round-robin over the 8 XCDs; the
-// block index is remapped so each XCD receives one contiguous run of tiles
-// and neighbouring tiles (sharing halo rows) meet in the same L2.
+// Launch: blocks of 4 (or 8) waves, dispatched round-robin over the 8 XCDs;
+// the block index is remapped so each XCD receives one contiguous run of
+// tiles and neighbouring tiles (sharing halo rows) meet in the same L2.
 #include "yo_internal.h"
 
 namespace {
