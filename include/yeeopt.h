@@ -246,6 +246,20 @@ yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
 yo_status yo_time_kernel(yo_plan *plan, int cls, int n_launch, float *avg_ms, double *bytes,
                          double *cells, yo_stream stream);
 
+/* Unbinarity (Sec. 4): the fraction of the design area's high-resolution
+ * sub-pixels whose projected density rho lies strictly between lo and hi
+ * (0 <= lo < hi <= 1), for the design last set; FP32 written to dev_u[0]
+ * on `stream`.  YO_ESTATE before yo_set_design. */
+yo_status yo_unbinarity(yo_plan *plan, double lo, double hi, float *dev_u, yo_stream stream);
+
+/* One Adam step (Sec. 4, Eqs. (10)-(11)) on n controls, all FP32 device
+ * arrays: M <- b1 M + (1-b1) G, V <- b2 V + (1-b2) G^2,
+ * C <- C - lr (M / (1 - b1^step)) / (sqrt(V / (1 - b2^step)) + eps).
+ * step counts from 1; M and V start at zero.  Needs no plan.  YO_EINVAL for
+ * step < 1, b1 or b2 outside [0, 1), eps <= 0 or a null array. */
+yo_status yo_adam_step(float *dev_C, const float *dev_G, float *dev_M, float *dev_V, int n, int step,
+                       double lr, double b1, double b2, double eps, yo_stream stream);
+
 /* Launch timing inside a solve: with n_last > 0, every later yo_advance,
  * yo_run or yo_advance_many (with this plan first in its list) runs its
  * last n_last steps with plain launches and records a pair of HIP events on

@@ -444,6 +444,48 @@ __global__ void k_vjp_filter_y(YoChainBufs c, float *dFdC)
     dFdC[i] = acc;
 }
 
+
+// Unbinarity (Sec. 4): grey sub-pixels of the design area, those whose
+// projected density lies strictly between the two thresholds, given as
+// tanh values (rho = (1 + t) / 2).  One atomic add per wave (vector atomic
+// on an integer, so the count does not depend on the order).
+__global__ void k_gray_count(YoChainBufs c, float tlo, float thi, int *count)
+{
+    const int n = c.S * c.md * c.S * c.nd;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const float t = i < n ? c.tanh_[i] : -2.0f;
+    const bool grey = t > tlo && t < thi;
+    const unsigned long long m = __ballot(grey);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, __popcll(m));
+}
+
+__global__ void k_gray_finish(const int *count, float inv_total, float *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (float)count[0] * inv_total;
+}
+
+__global__ void k_set_int(int *p, int v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+// Adam (Sec. 4, Eqs. (10)-(11)) on the controls: M, V moving averages of the
+// gradient and its square; the update divides the bias-corrected first
+// moment by the square root of the bias-corrected second plus eps.
+// inv1 = 1 / (1 - b1^i), inv2 = 1 / (1 - b2^i) for step i (from the host).
+__global__ void k_adam(float *C, const float *G, float *M, float *V, int n, float lr, float b1,
+                       float b2, float eps, float inv1, float inv2)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const float g = G[i];
+    const float m = fmaf(b1, M[i], (1.0f - b1) * g);
+    const float v = fmaf(b2, V[i], (1.0f - b2) * (g * g));
+    M[i] = m;
+    V[i] = v;
+    C[i] = C[i] - lr * ((m * inv1) / (sqrtf(v * inv2) + eps));
+}
+
 }  // namespace
 
 hipError_t yo_launch_fill(float *p, size_t n, float v, hipStream_t s)
@@ -528,5 +570,24 @@ hipError_t yo_launch_zsum(const float *gbox, const int *box, int k_lo, int k_hi,
 {
     hipLaunchKernelGGL(k_zsum, dim3(nblk((size_t)box[3] * box[4])), dim3(BS), 0, s, gbox, box[0],
                        box[1], box[2], box[3], box[4], box[5], k_lo, k_hi, gmap, G0, G1);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_unbinarity(const YoChainBufs &c, float tlo, float thi, int *count, float *out,
+                                hipStream_t s)
+{
+    const size_t n = (size_t)c.S * c.md * c.S * c.nd;
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, count, 0);
+    hipLaunchKernelGGL(k_gray_count, dim3(nblk(n)), dim3(BS), 0, s, c, tlo, thi, count);
+    hipLaunchKernelGGL(k_gray_finish, dim3(1), dim3(64), 0, s, count, (float)(1.0 / (double)n), out);
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_adam(float *C, const float *G, float *M, float *V, int n, float lr, float b1, float b2,
+                          float eps, float inv1, float inv2, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adam, dim3(nblk((size_t)n)), dim3(BS), 0, s, C, G, M, V, n, lr, b1, b2, eps, inv1,
+                       inv2);
     return hipGetLastError();
 }

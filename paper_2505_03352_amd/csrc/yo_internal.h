@@ -173,6 +173,11 @@ struct YoGradArgs {
 };
 hipError_t yo_launch_grad_assemble(const YoGradArgs &a, hipStream_t s);
 hipError_t yo_launch_chain_vjp(const YoChainBufs &c, float beta, float *dFdC, hipStream_t s);
+// grey fraction of the design area: rho in (lo, hi) as tanh in (tlo, thi)
+hipError_t yo_launch_unbinarity(const YoChainBufs &c, float tlo, float thi, int *count, float *out,
+                                hipStream_t s);
+hipError_t yo_launch_adam(float *C, const float *G, float *M, float *V, int n, float lr, float b1, float b2,
+                          float eps, float inv1, float inv2, hipStream_t s);
 hipError_t yo_launch_zsum(const float *gbox, const int *box, int k_lo, int k_hi, float *gmap, int G0,
                           int G1, hipStream_t s);
 

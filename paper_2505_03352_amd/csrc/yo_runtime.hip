@@ -1235,6 +1235,33 @@ yo_status yo_chain_vjp(yo_plan *p, const float *gk, float *dFdC, yo_stream strea
     return YO_OK;
 }
 
+yo_status yo_unbinarity(yo_plan *p, double lo, double hi, float *dev_u, yo_stream stream)
+{
+    if (!p || !dev_u) return fail(YO_EINVAL, "null argument");
+    if (!(lo >= 0.0 && lo < hi && hi <= 1.0)) return fail(YO_EINVAL, "need 0 <= lo < hi <= 1");
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (!p->design_set) return fail(YO_ESTATE, "yo_set_design first");
+    // the counter sits after the step counter in the counter region
+    int *count = wsp<int>(p, p->L.ctr) + 16;
+    HIPCHK(yo_launch_unbinarity(p->chain, (float)(2.0 * lo - 1.0), (float)(2.0 * hi - 1.0), count, dev_u,
+                                (hipStream_t)stream));
+    return YO_OK;
+}
+
+yo_status yo_adam_step(float *dev_C, const float *dev_G, float *dev_M, float *dev_V, int n, int step,
+                       double lr, double b1, double b2, double eps, yo_stream stream)
+{
+    if (n < 0 || (n > 0 && (!dev_C || !dev_G || !dev_M || !dev_V))) return fail(YO_EINVAL, "bad arrays");
+    if (step < 1) return fail(YO_EINVAL, "steps count from 1");
+    if (!(b1 >= 0.0 && b1 < 1.0 && b2 >= 0.0 && b2 < 1.0 && eps > 0.0))
+        return fail(YO_EINVAL, "need 0 <= b1, b2 < 1 and eps > 0");
+    const double inv1 = 1.0 / (1.0 - std::pow(b1, step));
+    const double inv2 = 1.0 / (1.0 - std::pow(b2, step));
+    HIPCHK(yo_launch_adam(dev_C, dev_G, dev_M, dev_V, n, (float)lr, (float)b1, (float)b2, (float)eps,
+                          (float)inv1, (float)inv2, (hipStream_t)stream));
+    return YO_OK;
+}
+
 yo_status yo_set_timing(yo_plan *p, int part, int n_last)
 {
     if (!p) return fail(YO_EINVAL, "null argument");

@@ -12,7 +12,8 @@
                    mixture, 1-3 wavelengths each.
 * ``multiport()``  600x400x120 1-to-4 splitter-like grid, 250x150 controls,
                    r=4, beta=16, 5 wavelengths 1.50-1.60 um, 20 000 steps.
-* ``micro()``      very small devices for CPU tests of the oracle.
+* ``demux()``      two-wavelength demultiplexer analogue (optimizer loop).
+* ``micro()``, ``micro_demux()``  very small devices for tests.
 """
 from __future__ import annotations
 
@@ -108,11 +109,36 @@ def multiport(seed: int = 300, n_steps: int = 20000, wavelengths=None):
 
 def micro(seed: int = 7, n_steps: int = 600, nx: int = 30, ny: int = 26, nz: int = 18,
           npml: int = 5, md: int = 8, nd: int = 8, mc: int = 6, nc: int = 5,
-          wavelengths=None, beta: float = 4.0, filter_r: float = 1.5, layers: int = 3):
+          wavelengths=None, beta: float = 4.0, filter_r: float = 1.5, layers: int = 3,
+          out_offsets=(0.0,)):
     """A few-thousand-cell device for CPU tests of the oracle (40 nm cells,
     shorter wavelength so a few periods fit)."""
     wl = [0.8 * UM] if wavelengths is None else wavelengths
     return soi_device("micro", nx, ny, nz, 40e-9, npml, md=md, nd=nd, slab_layers=layers,
                       mc=mc, nc=nc, filter_r=filter_r, beta=beta, wavelengths=wl,
                       n_steps=n_steps, seed=seed, mode_w=(3.0, 1.5), ramp_periods=3.0,
-                      strip_width=240e-9, src_inset=3)
+                      strip_width=240e-9, src_inset=3, out_offsets=out_offsets)
+
+
+def demux(seed: int = 400, n_steps=None):
+    """Two-wavelength demultiplexer analogue of the paper's Sec. 4 example:
+    1.30 um to output 1, 1.55 um to output 2; 300x300x64 cells at 25 nm
+    (CPML 8), a 210x210-pixel design (5.25 um) with 36x36 controls, one
+    input stub and two output stubs 1.5 um apart.  The controls start grey
+    (C = 1/2, the uniform average material)."""
+    wl = [1.30 * UM, 1.55 * UM]
+    steps = steps_rule(300, 300, 25e-9, max(wl)) if n_steps is None else n_steps
+    dev = soi_device("demux", 300, 300, 64, 25e-9, 8, md=210, nd=210, slab_layers=9, mc=36, nc=36,
+                     filter_r=2.0, beta=10.0, wavelengths=wl, n_steps=steps, seed=seed,
+                     out_offsets=(-0.75 * UM, 0.75 * UM))
+    dev.C = np.full_like(dev.C, 0.5)
+    return dev
+
+
+def micro_demux(n_steps: int = 700):
+    """A few-thousand-cell two-port, two-wavelength device for tests of the
+    optimizer loop."""
+    dev = micro(seed=9, n_steps=n_steps, nx=32, ny=28, nz=18, md=10, nd=10, mc=5, nc=5,
+                wavelengths=[0.78 * UM, 0.86 * UM], out_offsets=(-0.16 * UM, 0.16 * UM))
+    dev.C = np.full_like(dev.C, 0.5)
+    return dev
