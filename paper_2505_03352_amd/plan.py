@@ -250,6 +250,13 @@ class Plan:
              ct.byref(c), _stream(stream))
         return float(ms.value), float(b.value), float(c.value)
 
+    def unbinarity(self, lo: float = 0.01, hi: float = 0.99, stream=None) -> torch.Tensor:
+        """Fraction of grey design sub-pixels (lo < rho < hi) of the design
+        last set, as a one-element device tensor."""
+        out = torch.empty(1, dtype=torch.float32, device=self.device)
+        call("yo_unbinarity", self._h, float(lo), float(hi), _ptr(out), _stream(stream))
+        return out
+
     def set_timing(self, part: int = 0, n_last: int = 100):
         """Time the launches of one part (0 interior, 1 CPML shell) over the
         last `n_last` steps of every later advance (0: off)."""
@@ -265,6 +272,19 @@ class Plan:
         b, c = ct.c_double(), ct.c_double()
         call("yo_model_bytes", self._h, which, ct.byref(b), ct.byref(c))
         return float(b.value), float(c.value)
+
+
+def adam_step(C: torch.Tensor, G: torch.Tensor, M: torch.Tensor, V: torch.Tensor, step: int,
+              lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, stream=None):
+    """One Adam step on device FP32 tensors of equal size, in place (C, M, V)."""
+    for t in (C, G, M, V):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("contiguous float32 device tensors expected")
+    n = C.numel()
+    if not (G.numel() == M.numel() == V.numel() == n):
+        raise ValueError("size mismatch")
+    call("yo_adam_step", _ptr(C), _ptr(G), _ptr(M), _ptr(V), n, int(step), float(lr), float(b1),
+         float(b2), float(eps), _stream(stream))
 
 
 def advance_many(plans: Sequence[Plan], which: Sequence[int], n_steps: int, chunk: int = 64,

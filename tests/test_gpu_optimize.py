@@ -1,0 +1,87 @@
+"""The Sec. 4 optimizer loop on the GPU against the FP64 oracle's loop: the
+Adam kernel, the unbinarity reduction, and whole iterations (objective,
+projection strength, grey fraction, controls)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import chain
+from oracle import optimize as O
+from workloads import configs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_built")]
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_available():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_03352_amd import _abi
+    _abi.lib()
+
+
+def test_adam_kernel_matches_formula():
+    from paper_2505_03352_amd.plan import adam_step
+    rng = np.random.default_rng(11)
+    n = 5000
+    C = rng.uniform(size=n)
+    M = np.zeros(n)
+    V = np.zeros(n)
+    Cd = torch.tensor(C, dtype=torch.float32, device="cuda")
+    Md = torch.zeros(n, dtype=torch.float32, device="cuda")
+    Vd = torch.zeros(n, dtype=torch.float32, device="cuda")
+    for i in range(1, 4):
+        G = rng.normal(size=n) * 10.0 ** rng.uniform(-4, 1, size=n)
+        C, M, V = O.adam_step(C, G, M, V, i, lr=1e-2)
+        adam_step(Cd, torch.tensor(G, dtype=torch.float32, device="cuda"), Md, Vd, i, lr=1e-2)
+    err = np.abs(Cd.cpu().numpy() - C).max()
+    say(f"adam max abs err {err:.2e}")
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("beta", [30.0, 300.0])
+def test_unbinarity_matches_oracle(beta):
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.tiny()
+    p = plan_for(dev, beta=beta)
+    u = float(p.unbinarity()[0])
+    p.close()
+    _, st = chain.kappa(dev, dev.C, beta)
+    uo = O.unbinarity(O.design_rho(dev, st))
+    say(f"beta {beta}: u gpu {u:.5f} oracle {uo:.5f}")
+    assert 0.0 < uo < 1.0
+    assert abs(u - uo) < 1e-3
+
+
+@pytest.mark.parametrize("start", ["grey", "random"])
+def test_optimizer_iterations_match_oracle(start):
+    from paper_2505_03352_amd import optimize
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro_demux(n_steps=700)
+    if start == "random":
+        dev.C = np.random.default_rng(5).uniform(size=dev.C.shape)
+    T = np.full((1, 2, 2), np.nan)
+    T[0, 0, 0] = 1.0          # wavelength 1 to output 1
+    T[0, 1, 1] = 1.0          # wavelength 2 to output 2
+    n_iter = 3
+    say(f"optimizer ({start}): GPU")
+    p = plan_for(dev)
+    C, h = optimize.optimize(p, dev.C, T, n_iter=n_iter, iters_total=10)
+    C = C.cpu().numpy()
+    p.close()
+    say(f"optimizer ({start}): oracle")
+    ho = O.optimize(dev, T, n_iter=n_iter, iters_total=10)
+    say(f"  F gpu {h.F} oracle {ho.F}; u {h.u} / {ho.u}; beta {h.beta} / {ho.beta}")
+    assert np.allclose(h.F, ho.F, rtol=1e-3)
+    assert np.allclose(h.u, ho.u, atol=1e-3)
+    assert np.allclose(h.beta, ho.beta, rtol=1e-3)
+    assert np.abs(C - ho.C[-1]).max() < 1e-4
+    if start == "grey":
+        assert h.F[-1] < h.F[0]
