@@ -93,10 +93,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="plain launches instead of HIP-graph replays (for counter collection)")
-    ap.add_argument("--workload", choices=("realistic", "batch", "serving"), default="realistic",
+    ap.add_argument("--workload", choices=("realistic", "batch", "serving", "optimize"),
+                    default="realistic",
                     help="realistic: the headline line; batch / serving: the batched and served "
                          "forms against one-at-a-time solves (their own JSON line)")
     ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
+    ap.add_argument("--iters", type=int, default=5, help="optimize: optimizer iterations")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: arrival rate, requests/s")
     ap.add_argument("--max-cells", type=float, default=4.5e7,
@@ -112,6 +114,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "optimize":
+        return bench_optimize(args)
 
     import torch
     from paper_2505_03352_amd import YO_BOTH, autotune
@@ -312,6 +316,42 @@ def bench_serving(args):
            "one_at_a_time": {"designs_per_h": round(b.throughput_per_h, 1),
                              "p50_s": round(b.p50_s, 3), "p99_s": round(b.p99_s, 3),
                              "gcell_updates_per_s": round(b.cell_updates / b.makespan_s / 1e9, 3)}})
+
+
+def bench_optimize(args):
+    """The Sec. 4 optimizer loop on the two-wavelength demultiplexer analogue
+    (1.30 um to output 1, 1.55 um to output 2): iterations per hour, with
+    the objective, grey fraction and projection strength of each iteration."""
+    import numpy as np
+    import torch
+    from paper_2505_03352_amd import YO_BOTH, autotune, optimize
+    from paper_2505_03352_amd.plan import plan_for
+    from workloads import configs
+    torch.cuda.set_device(0)
+    dev = configs.demux()
+    log(f"demux: {dev.nx}x{dev.ny}x{dev.nz}, {dev.n_steps} steps, {dev.mc}x{dev.nc} controls")
+    plan = plan_for(dev, device="cuda:0")
+    tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
+    T = np.array([[[1.0, 0.0], [0.0, 1.0]]])     # [source][port][wavelength]: demux, no crosstalk
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C, h = optimize.optimize(plan, dev.C, T, n_iter=args.iters, iters_total=100, chunk=args.chunk)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = plan.n_rhs * dev.cells * dev.n_steps * args.iters
+    for i, (F, u, b) in enumerate(zip(h.F, h.u, h.beta)):
+        log(f"iter {i}: F {F:.5f} u {u:.4f} beta {b:.2f} ({h.seconds[i]:.2f} s)")
+    plan.close()
+    _line("optimizer iterations/hour (demux analogue)", 3600.0 * args.iters / dt, "iterations/h",
+          dt / args.iters * 1e3, args,
+          {"workload": "demux analogue: 430x450x64 cells at 25 nm (CPML 8), 210x210-pixel design, "
+                       "36x36 controls from C = 1/2, 1.30/1.55 um, 1 forward + 2 adjoint per "
+                       f"wavelength, {dev.n_steps} steps; Adam lr 1e-3, beta_min 10, "
+                       "gamma 0.95, u0 0.01, schedule length 100",
+           "iterations": args.iters, "tiling": [tuned["rows"], tuned["zchunk"], tuned["flags"]]},
+          {"gcell_updates_per_s": round(cells / dt / 1e9, 3),
+           "F": [round(x, 6) for x in h.F], "unbinarity": [round(x, 5) for x in h.u],
+           "beta": [round(x, 3) for x in h.beta]})
 
 
 if __name__ == "__main__":

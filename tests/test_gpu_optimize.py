@@ -67,9 +67,8 @@ def test_optimizer_iterations_match_oracle(start):
     dev = configs.micro_demux(n_steps=700)
     if start == "random":
         dev.C = np.random.default_rng(5).uniform(size=dev.C.shape)
-    T = np.full((1, 2, 2), np.nan)
-    T[0, 0, 0] = 1.0          # wavelength 1 to output 1
-    T[0, 1, 1] = 1.0          # wavelength 2 to output 2
+    # wavelength 1 to output 1, wavelength 2 to output 2, no crosstalk
+    T = np.array([[[1.0, 0.0], [0.0, 1.0]]])
     n_iter = 3
     say(f"optimizer ({start}): GPU")
     p = plan_for(dev)

@@ -122,13 +122,14 @@ def micro(seed: int = 7, n_steps: int = 600, nx: int = 30, ny: int = 26, nz: int
 
 def demux(seed: int = 400, n_steps=None):
     """Two-wavelength demultiplexer analogue of the paper's Sec. 4 example:
-    1.30 um to output 1, 1.55 um to output 2; 300x300x64 cells at 25 nm
-    (CPML 8), a 210x210-pixel design (5.25 um) with 36x36 controls, one
-    input stub and two output stubs 1.5 um apart.  The controls start grey
-    (C = 1/2, the uniform average material)."""
+    1.30 um to output 1, 1.55 um to output 2; 430x450x64 cells (the
+    example's 12.38 M) at a uniform 25 nm (CPML 8), a 210x210-pixel design
+    (5.25 um) with 36x36 controls, one input stub and two output stubs
+    1.5 um apart.  The controls start grey (C = 1/2, the uniform average
+    material)."""
     wl = [1.30 * UM, 1.55 * UM]
-    steps = steps_rule(300, 300, 25e-9, max(wl)) if n_steps is None else n_steps
-    dev = soi_device("demux", 300, 300, 64, 25e-9, 8, md=210, nd=210, slab_layers=9, mc=36, nc=36,
+    steps = steps_rule(430, 450, 25e-9, max(wl)) if n_steps is None else n_steps
+    dev = soi_device("demux", 430, 450, 64, 25e-9, 8, md=210, nd=210, slab_layers=9, mc=36, nc=36,
                      filter_r=2.0, beta=10.0, wavelengths=wl, n_steps=steps, seed=seed,
                      out_offsets=(-0.75 * UM, 0.75 * UM))
     dev.C = np.full_like(dev.C, 0.5)
