@@ -22,10 +22,22 @@ Stages (in the paper's order):
     for i = x, y; E_z sees vertical sidewalls only (n_z = 0) so kappa_z = 1/<eps>;
   * extrusion along z through the slab; E_z planes on the two slab faces are
     half filled with normal z, kappa_z = (<1/eps> + 1/eps_clad) / 2.
+
+Optional morphological filtering (Eqs. 4-5, then Eq. 6), when the device
+names a sequence of operations (``dev.morph_ops``, 'd' dilate, 'e' erode,
+applied left to right): the projected density rho_0 of Eq. (3) goes through
+soft dilations rho~ = (1/a) log sum K exp(a rho) and erosions
+rho~ = 1 - (1/a) log sum K exp(a (1 - rho)) with the disc kernel K_m of
+diameter d (``dev.morph_d`` design pixels: the sub-pixel offsets whose
+length is at most d S / 2), normalised to unit sum, and sharpness a
+(``dev.morph_alpha``); then rho = (1 + tanh(beta (rho~ - 1/2))) / 2.  Each
+stage is evaluated on the design area of the canvas; kernel taps that fall
+in the margin read the fixed background there, and taps beyond the canvas
+read its nearest edge sub-pixel.  Without operations rho = rho_0.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 
@@ -87,6 +99,35 @@ def smooth_matrix(n: int) -> np.ndarray:
     return M
 
 
+def disc_taps(d: float, S: int):
+    """Sub-pixel offsets (dy, dx) of the disc kernel K_m of diameter d design
+    pixels: every offset of length at most d S / 2."""
+    R = d * S / 2.0
+    n = int(np.floor(R))
+    return [(dy, dx) for dy in range(-n, n + 1) for dx in range(-n, n + 1)
+            if dx * dx + dy * dy <= R * R]
+
+
+def morph_operator(dev, taps):
+    """Sparse K[x, q]: x runs over the design sub-pixels ([S nd][S md], row
+    major), q over the canvas ([V][U]); each tap adds 1/len(taps) at the canvas
+    sub-pixel x + delta, clamped into the canvas."""
+    from scipy import sparse
+    S, md, nd = dev.supersample, dev.md, dev.nd
+    U, V = S * (md + 4), S * (nd + 4)
+    vd, ud = np.meshgrid(np.arange(S * nd), np.arange(S * md), indexing="ij")
+    rows, cols = [], []
+    for dy, dx in taps:
+        v = np.clip(vd + 2 * S + dy, 0, V - 1)
+        u = np.clip(ud + 2 * S + dx, 0, U - 1)
+        rows.append((vd * (S * md) + ud).ravel())
+        cols.append((v * U + u).ravel())
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.full(rows.size, 1.0 / len(taps))
+    return sparse.csr_matrix((vals, (rows, cols)), shape=(S * S * md * nd, U * V))
+
+
 @dataclass
 class ChainOps:
     S: int
@@ -100,6 +141,11 @@ class ChainOps:
     Dy: np.ndarray
     Mx: np.ndarray
     My: np.ndarray
+    K: object = None    # morphological operator (None without operations)
+
+
+def morph_ops_of(dev) -> str:
+    return getattr(dev, "morph_ops", "") or ""
 
 
 def make_ops(dev) -> ChainOps:
@@ -112,8 +158,9 @@ def make_ops(dev) -> ChainOps:
     shifts_y = (0, half, 0)   # E_y window shifted half a cell in y
     Bx = [box_matrix(md + 4, S, shifts_x[c], U) for c in range(3)]
     By = [box_matrix(nd + 4, S, shifts_y[c], V) for c in range(3)]
+    K = morph_operator(dev, disc_taps(dev.morph_d, S)) if morph_ops_of(dev) else None
     return ChainOps(S, md, nd, Wx, Wy, Bx, By, diff_matrix(md + 4), diff_matrix(nd + 4),
-                    smooth_matrix(md + 4), smooth_matrix(nd + 4))
+                    smooth_matrix(md + 4), smooth_matrix(nd + 4), K)
 
 
 # ----------------------------------------------------------------- forward
@@ -133,6 +180,8 @@ class ChainState:
     ky: np.ndarray
     kz_in: np.ndarray
     kz_face: np.ndarray
+    stages: list = field(default_factory=list)   # per morphological stage: (input canvas, sums)
+    t2: np.ndarray = None                        # tanh of the Eq. (6) projection after them
 
 
 def design_slices(dev):
@@ -173,10 +222,49 @@ def project(dev, C, beta, ops: ChainOps):
     return phi, t, rho
 
 
+def morph_stage(dev, canvas: np.ndarray, op: str, alpha: float, K):
+    """One soft dilation (Eq. 4, op 'd') or erosion (Eq. 5, op 'e') of a
+    canvas; returns (output canvas, the kernel sums on the design area)."""
+    sv, su = design_slices(dev)
+    if op == "d":
+        sums = K @ np.exp(alpha * canvas).ravel()
+        y = np.log(sums) / alpha
+    elif op == "e":
+        sums = K @ np.exp(alpha * (1.0 - canvas)).ravel()
+        y = 1.0 - np.log(sums) / alpha
+    else:
+        raise ValueError(f"unknown morphological operation {op!r}")
+    out = canvas.copy()
+    out[sv, su] = y.reshape(out[sv, su].shape)
+    return out, sums
+
+
+def morph_stage_vjp(dev, canvas: np.ndarray, op: str, alpha: float, K, sums, g):
+    """Transpose of one stage's Jacobian: g on the design area of its output
+    -> gradient on the design area of its input.  Both operations have
+    d rho~(x) / d rho(q) = K[x, q] e(q) / sums(x) with e the exponential the
+    stage sums."""
+    sv, su = design_slices(dev)
+    e = np.exp(alpha * canvas) if op == "d" else np.exp(alpha * (1.0 - canvas))
+    gc = e.ravel() * (K.T @ (np.asarray(g).ravel() / sums))
+    return gc.reshape(canvas.shape)[sv, su]
+
+
 def forward(dev, C, beta, ops: ChainOps = None) -> ChainState:
     ops = ops or make_ops(dev)
     phi, t, rho = project(dev, C, beta, ops)
-    return ChainState(phi, t, rho, *smooth_kappa(dev, rho, ops))
+    stages, t2 = [], None
+    seq = morph_ops_of(dev)
+    if seq:
+        for op in seq:
+            out, sums = morph_stage(dev, rho, op, dev.morph_alpha, ops.K)
+            stages.append((rho, sums))
+            rho = out
+        sv, su = design_slices(dev)
+        t2 = np.tanh(beta * (rho[sv, su] - 0.5))           # Eq. (6)
+        rho = rho.copy()
+        rho[sv, su] = 0.5 * (1.0 + t2)
+    return ChainState(phi, t, rho, *smooth_kappa(dev, rho, ops), stages=stages, t2=t2)
 
 
 def written_region(dev):
@@ -258,5 +346,11 @@ def vjp(dev, st: ChainState, beta, gx, gy, gzi, gzf, ops: ChainOps = None):
     de = dev.eps_core - dev.eps_clad
     g_rho_tot = g_inv * (-de / st.eps ** 2) + g_eps * de + g_rho
     sv, su = design_slices(dev)
-    g_phi = g_rho_tot[sv, su] * 0.5 * beta * (1.0 - st.t ** 2)
+    g_d = g_rho_tot[sv, su]
+    seq = morph_ops_of(dev)
+    if seq:
+        g_d = g_d * 0.5 * beta * (1.0 - st.t2 ** 2)
+        for op, (canvas, sums) in zip(reversed(seq), reversed(st.stages)):
+            g_d = morph_stage_vjp(dev, canvas, op, dev.morph_alpha, ops.K, sums, g_d)
+    g_phi = g_d * 0.5 * beta * (1.0 - st.t ** 2)
     return ops.Wy.T @ g_phi @ ops.Wx

@@ -85,6 +85,9 @@ class Device:
     pml_sigma_scale: float = 1.0
     pml_kappa_max: float = 1.0
     pml_a_max: float = 0.0
+    morph_ops: str = ""           # morphological operations, 'd'/'e' left to right ('' = none)
+    morph_d: float = 0.0          # disc diameter, design pixels
+    morph_alpha: float = 20.0     # sharpness of the soft dilation/erosion
     extra: dict = field(default_factory=dict)
 
     # ---- time lengths (descriptions of the run, per wavelength) ----
