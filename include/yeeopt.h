@@ -114,6 +114,21 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *design, int n_ste
                          int n_ports, const yo_plane *port_planes, yo_plan **out);
 void yo_plan_destroy(yo_plan *plan);
 
+/* Morphological filters (Sec. 3, Eqs. (4)-(6)), host only, before
+ * yo_bind_workspace (YO_ESTATE after).  `ops` names the stages applied to
+ * the Eq. (3) density in order, 'd' for the soft dilation of Eq. (4) and
+ * 'e' for the soft erosion of Eq. (5), at most 8 (e.g. "edde": opening then
+ * closing); the stages are followed by the projection of Eq. (6) with the
+ * same beta.  The kernel K_m is the disc of `diameter` design pixels (every
+ * sub-pixel offset of length at most diameter * S / 2), normalised to unit
+ * sum; `alpha` is the sharpness.  Stages act on the design area; taps
+ * outside it read the canvas margin (the background fill), taps beyond the
+ * canvas its nearest edge sub-pixel.  NULL or "" turns the filters off.
+ * YO_EINVAL for other characters, more than 8 stages, diameter <= 0 or
+ * alpha outside (0, 80]; YO_EUNSUPPORTED for a disc radius above 32
+ * sub-pixels.  Changes yo_workspace_bytes. */
+yo_status yo_set_morphology(yo_plan *plan, const char *ops, double diameter, double alpha);
+
 /* Device bytes the plan needs (host only). */
 yo_status yo_workspace_bytes(const yo_plan *plan, size_t *bytes);
 
@@ -143,10 +158,11 @@ yo_status yo_set_port_mode(yo_plan *plan, int port, const double *host_e, const 
                            yo_stream stream);
 
 /* Parametrization (Sec. 3): dev_C FP32 [nc][mc] -> Eq. (2) level set with a
- * truncated Gaussian basis, tanh projection Eq. (3)/(6), density mix,
- * Yee-cell averages Eq. (8), Sobel normals, Eq. (7), extrusion through the
- * slab; writes kappa on the design area plus a one-pixel ring.  Must follow
- * yo_set_background.  Keeps what the gradient needs. */
+ * truncated Gaussian basis, tanh projection Eq. (3)/(6), the morphological
+ * stages if any (yo_set_morphology) followed by the Eq. (6) projection,
+ * density mix, Yee-cell averages Eq. (8), Sobel normals, Eq. (7), extrusion
+ * through the slab; writes kappa on the design area plus a one-pixel ring.
+ * Must follow yo_set_background.  Keeps what the gradient needs. */
 yo_status yo_set_design(yo_plan *plan, const float *dev_C, double beta, yo_stream stream);
 
 /* Time stepping.  `which` is YO_FORWARD, YO_ADJOINT or YO_BOTH.
@@ -247,7 +263,7 @@ yo_status yo_time_kernel(yo_plan *plan, int cls, int n_launch, float *avg_ms, do
                          double *cells, yo_stream stream);
 
 /* Unbinarity (Sec. 4): the fraction of the design area's high-resolution
- * sub-pixels whose projected density rho lies strictly between lo and hi
+ * sub-pixels whose final density rho lies strictly between lo and hi
  * (0 <= lo < hi <= 1), for the design last set; FP32 written to dev_u[0]
  * on `stream`.  YO_ESTATE before yo_set_design. */
 yo_status yo_unbinarity(yo_plan *plan, double lo, double hi, float *dev_u, yo_stream stream);

@@ -88,9 +88,9 @@ __global__ void k_alpha(const float2 *e, const float2 *w, int n, float2 *out)
 
 // ------------------------------------------------------------- forward chain
 // Eq. (2) with the truncated Gaussian basis (separable taps with clamped
-// control indices), then the tanh projection Eq. (3)/(6); the canvas margin
-// takes the background fill.
-__global__ void k_project(YoChainBufs c, const float *C, float beta)
+// control indices), then the tanh projection Eq. (3)/(6) into the canvas
+// `out`, whose margin takes the background fill.
+__global__ void k_project(YoChainBufs c, const float *C, float beta, float *out)
 {
     const int n = c.U * c.V;
     const int i = blockIdx.x * BS + threadIdx.x;
@@ -98,7 +98,7 @@ __global__ void k_project(YoChainBufs c, const float *C, float beta)
     const int v = i / c.U, u = i - v * c.U;
     const int ud = u - 2 * c.S, vd = v - 2 * c.S;
     if (ud < 0 || ud >= c.S * c.md || vd < 0 || vd >= c.S * c.nd) {
-        c.rho[i] = c.mask[i];
+        out[i] = c.mask[i];
         return;
     }
     const int xlo = c.tap_lo_x[ud], xn = c.tap_n_x[ud];
@@ -116,6 +116,53 @@ __global__ void k_project(YoChainBufs c, const float *C, float beta)
     phi -= 0.5f;
     const float t = tanhf(beta * phi);
     c.tanh_[vd * (c.S * c.md) + ud] = t;
+    out[i] = 0.5f * (1.0f + t);
+}
+
+// Eqs. (4)-(5): one soft dilation or erosion of the canvas `in` with the
+// normalised disc (mean over the taps), on the design area; taps are
+// clamped into the canvas, so near the design edge they read the fixed
+// margin.  Exponents are shifted so every term is at most one:
+// dilation 1 + log(mean e^{a(rho-1)}) / a, erosion -log(mean e^{-a rho}) / a
+// (the same values as Eqs. (4)-(5)).  The mean is kept for the transpose.
+__global__ void k_morph(YoChainBufs c, const float *in, float *out, float *sum, int dilate)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= c.U * c.V) return;
+    const int v = i / c.U, u = i - v * c.U;
+    const int ud = u - 2 * c.S, vd = v - 2 * c.S;
+    if (ud < 0 || ud >= c.S * c.md || vd < 0 || vd >= c.S * c.nd) {
+        out[i] = c.mask[i];
+        return;
+    }
+    const float a = c.malpha;
+    float acc = 0.0f;
+    for (int t = 0; t < c.n_mtaps; ++t) {
+        const int vv = clampi(v + c.mtap[2 * t], 0, c.V - 1);
+        const int uu = clampi(u + c.mtap[2 * t + 1], 0, c.U - 1);
+        const float r = in[vv * c.U + uu];
+        acc += dilate ? expf(a * (r - 1.0f)) : expf(-a * r);
+    }
+    const float m = acc * c.minv;
+    sum[vd * (c.S * c.md) + ud] = m;
+    const float l = logf(m) / a;
+    out[i] = dilate ? 1.0f + l : -l;
+}
+
+// The projection after the morphological stages, Eq. (6):
+// rho = (1 + tanh(beta (rho~ - 1/2))) / 2 on the design area.
+__global__ void k_morph_project(YoChainBufs c, const float *in, float beta)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= c.U * c.V) return;
+    const int v = i / c.U, u = i - v * c.U;
+    const int ud = u - 2 * c.S, vd = v - 2 * c.S;
+    if (ud < 0 || ud >= c.S * c.md || vd < 0 || vd >= c.S * c.nd) {
+        c.rho[i] = c.mask[i];
+        return;
+    }
+    const float t = tanhf(beta * (in[i] - 0.5f));
+    c.tanh2[vd * (c.S * c.md) + ud] = t;
     c.rho[i] = 0.5f * (1.0f + t);
 }
 
@@ -372,8 +419,9 @@ __device__ __forceinline__ int win_count(int m, int sh, int S, int u, int n_hr)
 }
 
 // Transpose of the box means to the canvas, the density mix and the
-// projection derivative (beta/2)(1 - tanh^2) on the design area.
-__global__ void k_vjp_canvas(YoChainBufs c, float beta)
+// derivative (beta/2)(1 - t^2) of the last projection (t = its tanh values)
+// on the design area, into gout [S nd][S md].
+__global__ void k_vjp_canvas(YoChainBufs c, float beta, const float *tproj, float *gout)
 {
     const int i = blockIdx.x * BS + threadIdx.x;
     if (i >= c.U * c.V) return;
@@ -406,8 +454,44 @@ __global__ void k_vjp_canvas(YoChainBufs c, float beta)
     const float de = c.eps_core - c.eps_clad;
     const float eps = fmaf(de, c.rho[i], c.eps_clad);
     const float grho = fmaf(gi, -de / (eps * eps), fmaf(ge, de, gr));
-    const float t = c.tanh_[vd * (c.S * c.md) + ud];
-    c.gphi[vd * (c.S * c.md) + ud] = grho * 0.5f * beta * (1.0f - t * t);
+    const float t = tproj[vd * (c.S * c.md) + ud];
+    gout[vd * (c.S * c.md) + ud] = grho * 0.5f * beta * (1.0f - t * t);
+}
+
+// Transpose of a morphological stage, first half: q = g / mean.
+__global__ void k_morph_q(YoChainBufs c, const float *g, const float *sum)
+{
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= c.S * c.md * c.S * c.nd) return;
+    c.mq[i] = g[i] / sum[i];
+}
+
+// Second half: d rho~(x) / d rho(x') = e(x') / (n mean(x)) for every tap
+// with x + delta = x', e the stage's shifted exponential, so the gradient at
+// x' gathers q over x = x' - delta (the disc is symmetric) within the
+// design area (taps that were clamped land in the margin, which has no
+// gradient).  With tproj, the Eq. (3) projection's derivative follows.
+__global__ void k_morph_vjp(YoChainBufs c, const float *in, int dilate, const float *tproj, float beta,
+                            float *gout)
+{
+    const int nud = c.S * c.md, nvd = c.S * c.nd;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= nud * nvd) return;
+    const int vd = i / nud, ud = i - vd * nud;
+    float acc = 0.0f;
+    for (int t = 0; t < c.n_mtaps; ++t) {
+        const int vq = vd - c.mtap[2 * t], uq = ud - c.mtap[2 * t + 1];
+        if (vq < 0 || vq >= nvd || uq < 0 || uq >= nud) continue;
+        acc += c.mq[vq * nud + uq];
+    }
+    const float r = in[(vd + 2 * c.S) * c.U + ud + 2 * c.S];
+    const float e = dilate ? expf(c.malpha * (r - 1.0f)) : expf(-c.malpha * r);
+    float g = e * acc * c.minv;
+    if (tproj) {
+        const float t = tproj[i];
+        g *= 0.5f * beta * (1.0f - t * t);
+    }
+    gout[i] = g;
 }
 
 // Transpose of the separable filter, x then y.  tmp[vd][a] = sum_ud gphi W_x(ud, a)
@@ -446,14 +530,14 @@ __global__ void k_vjp_filter_y(YoChainBufs c, float *dFdC)
 
 
 // Unbinarity (Sec. 4): grey sub-pixels of the design area, those whose
-// projected density lies strictly between the two thresholds, given as
-// tanh values (rho = (1 + t) / 2).  One atomic add per wave (vector atomic
+// final density lies strictly between the two thresholds, given as tanh
+// values of the last projection (rho = (1 + t) / 2).  One atomic add per wave (vector atomic
 // on an integer, so the count does not depend on the order).
-__global__ void k_gray_count(YoChainBufs c, float tlo, float thi, int *count)
+__global__ void k_gray_count(YoChainBufs c, const float *tproj, float tlo, float thi, int *count)
 {
     const int n = c.S * c.md * c.S * c.nd;
     const int i = blockIdx.x * BS + threadIdx.x;
-    const float t = i < n ? c.tanh_[i] : -2.0f;
+    const float t = i < n ? tproj[i] : -2.0f;
     const bool grey = t > tlo && t < thi;
     const unsigned long long m = __ballot(grey);
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, __popcll(m));
@@ -541,7 +625,14 @@ hipError_t yo_launch_chain_forward(const YoChainBufs &c, const float *C, float b
                                    int nx, int ny, int nz, int nxp, int i0, int j0, int k_lo,
                                    int k_hi, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_project, dim3(nblk((size_t)c.U * c.V)), dim3(BS), 0, s, c, C, beta);
+    const size_t UV = (size_t)c.U * c.V;
+    const size_t DD = (size_t)c.S * c.md * c.S * c.nd;
+    hipLaunchKernelGGL(k_project, dim3(nblk(UV)), dim3(BS), 0, s, c, C, beta, c.n_morph ? c.mcan : c.rho);
+    for (int k = 0; k < c.n_morph; ++k)
+        hipLaunchKernelGGL(k_morph, dim3(nblk(UV)), dim3(BS), 0, s, c, c.mcan + k * UV, c.mcan + (k + 1) * UV,
+                           c.msum + k * DD, (int)((c.mdil >> k) & 1u));
+    if (c.n_morph)
+        hipLaunchKernelGGL(k_morph_project, dim3(nblk(UV)), dim3(BS), 0, s, c, c.mcan + c.n_morph * UV, beta);
     hipLaunchKernelGGL(k_box, dim3(nblk((size_t)3 * c.G0 * c.G1)), dim3(BS), 0, s, c);
     hipLaunchKernelGGL(k_smooth, dim3(nblk((size_t)(c.md + 2) * (c.nd + 2))), dim3(BS), 0, s, c,
                        kappa, nx, ny, nz, nxp, i0, j0, k_lo, k_hi);
@@ -559,7 +650,18 @@ hipError_t yo_launch_chain_vjp(const YoChainBufs &c, float beta, float *dFdC, hi
     const size_t gsz = (size_t)c.G0 * c.G1;
     hipLaunchKernelGGL(k_vjp_pointwise, dim3(nblk(gsz)), dim3(BS), 0, s, c);
     hipLaunchKernelGGL(k_vjp_sobel, dim3(nblk(2 * gsz)), dim3(BS), 0, s, c);
-    hipLaunchKernelGGL(k_vjp_canvas, dim3(nblk((size_t)c.U * c.V)), dim3(BS), 0, s, c, beta);
+    const size_t UV = (size_t)c.U * c.V;
+    const size_t DD = (size_t)c.S * c.md * c.S * c.nd;
+    float *g = c.n_morph ? c.mg : c.gphi;
+    hipLaunchKernelGGL(k_vjp_canvas, dim3(nblk(UV)), dim3(BS), 0, s, c, beta, c.n_morph ? c.tanh2 : c.tanh_, g);
+    for (int k = c.n_morph - 1; k >= 0; --k) {
+        hipLaunchKernelGGL(k_morph_q, dim3(nblk(DD)), dim3(BS), 0, s, c, (const float *)g, c.msum + k * DD);
+        float *next = k == 0 ? c.gphi : (g == c.mg ? c.mg + DD : c.mg);
+        hipLaunchKernelGGL(k_morph_vjp, dim3(nblk(DD)), dim3(BS), 0, s, c, (const float *)(c.mcan + k * UV),
+                           (int)((c.mdil >> k) & 1u), k == 0 ? (const float *)c.tanh_ : (const float *)nullptr,
+                           beta, next);
+        g = next;
+    }
     hipLaunchKernelGGL(k_vjp_filter_x, dim3(nblk((size_t)c.S * c.nd * c.mc)), dim3(BS), 0, s, c);
     hipLaunchKernelGGL(k_vjp_filter_y, dim3(nblk((size_t)c.nc * c.mc)), dim3(BS), 0, s, c, dFdC);
     return hipGetLastError();
@@ -578,7 +680,8 @@ hipError_t yo_launch_unbinarity(const YoChainBufs &c, float tlo, float thi, int 
 {
     const size_t n = (size_t)c.S * c.md * c.S * c.nd;
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, count, 0);
-    hipLaunchKernelGGL(k_gray_count, dim3(nblk(n)), dim3(BS), 0, s, c, tlo, thi, count);
+    hipLaunchKernelGGL(k_gray_count, dim3(nblk(n)), dim3(BS), 0, s, c,
+                       (const float *)(c.n_morph ? c.tanh2 : c.tanh_), tlo, thi, count);
     hipLaunchKernelGGL(k_gray_finish, dim3(1), dim3(64), 0, s, count, (float)(1.0 / (double)n), out);
     return hipGetLastError();
 }

@@ -129,6 +129,18 @@ struct YoChainBufs {
     float *gR;        // [2][G1][G0]
     float *gphi;      // [S nd][S md]
     float *tmp;       // [S nd][mc]
+    // morphological filters (n_morph = 0: none; rho = the Eq. (3) projection)
+    int n_morph;      // stages
+    unsigned mdil;    // bit k set: stage k dilates, else erodes
+    int n_mtaps;      // disc taps
+    float malpha;     // sharpness
+    float minv;       // 1 / n_mtaps
+    int *mtap;        // [n_mtaps][2]: dy, dx (sub-pixels)
+    float *mcan;      // [n_morph + 1][V][U]: stage inputs, then the last output
+    float *msum;      // [n_morph][S nd][S md]: each stage's kernel sums
+    float *tanh2;     // [S nd][S md]: tanh of the projection after the stages
+    float *mg;        // [2][S nd][S md]: gradients between stages
+    float *mq;        // [S nd][S md]: gradient / kernel sum of the stage being transposed
 };
 
 // ---- kernel launchers ----

@@ -48,7 +48,7 @@ struct Region {
 
 struct Layout {
     Region fields, kappa, psi, dft_box, dft_mon, src_j, port_w, steptab, prof, desc_plan,
-        desc_rhs, ctr, tiles, chain_f, chain_i;
+        desc_rhs, ctr, tiles, chain_f, chain_i, morph;
     size_t total = 0;
     size_t add(Region &r, size_t bytes)
     {
@@ -113,6 +113,9 @@ struct yo_plan {
     YoChainBufs chain{};
     std::vector<int> tap_lo_x, tap_n_x, tap_lo_y, tap_n_y, urange_x, urange_y;
     std::vector<float> tap_w_x, tap_w_y;
+    std::string morph_ops;       // 'd'/'e' per stage, empty: no morphological filters
+    double morph_d = 0, morph_alpha = 0;
+    std::vector<int> mtaps;      // [n][2] dy, dx
     std::vector<float4> steptab;
     std::vector<float> prof;
     std::vector<float2> src_j_host, port_w_host;
@@ -547,6 +550,7 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     L.add(L.chain_f, sizeof(float) * (nf + 64 * 16));   // each of 15 buffers padded to 64 floats
     const size_t ni = 2 * (size_t)p->S * (d.md + d.nd) + 2 * (size_t)(d.mc + d.nc);
     L.add(L.chain_i, sizeof(int) * (ni + 64 * 8));     // each of 6 tables padded to 64 ints
+    L.add(L.morph, 0);           // last: yo_set_morphology sizes it before binding
 
     build_profiles(p);
     build_steptab(p);
@@ -736,6 +740,73 @@ static yo_status set_chain_ptrs(yo_plan *p)
     if ((char *)f > p->ws + p->L.chain_f.off + p->L.chain_f.bytes ||
         (char *)ip > p->ws + p->L.chain_i.off + p->L.chain_i.bytes)
         return fail(YO_EWORKSPACE, "internal: parametrization buffers exceed their region");
+    c.n_morph = (int)p->morph_ops.size();
+    c.mdil = 0;
+    for (int k = 0; k < c.n_morph; ++k)
+        if (p->morph_ops[k] == 'd') c.mdil |= 1u << k;
+    c.n_mtaps = (int)p->mtaps.size() / 2;
+    c.malpha = (float)p->morph_alpha;
+    c.minv = c.n_mtaps ? (float)(1.0 / c.n_mtaps) : 0.0f;
+    c.mtap = nullptr;
+    c.mcan = c.msum = c.tanh2 = c.mg = c.mq = nullptr;
+    if (c.n_morph) {
+        f = wsp<float>(p, p->L.morph);
+        c.mcan = take((size_t)(c.n_morph + 1) * UV);
+        c.msum = take((size_t)c.n_morph * DD);
+        c.tanh2 = take(DD);
+        c.mg = take(2 * DD);
+        c.mq = take(DD);
+        c.mtap = reinterpret_cast<int *>(take(p->mtaps.size()));
+        if ((char *)f > p->ws + p->L.morph.off + p->L.morph.bytes)
+            return fail(YO_EWORKSPACE, "internal: morphology buffers exceed their region");
+    }
+    return YO_OK;
+}
+
+// Bytes of the morphological region for n stages and t taps (each buffer
+// padded to 64 floats, as set_chain_ptrs carves them).
+static size_t morph_bytes(const yo_plan *p, size_t n, size_t t)
+{
+    const size_t UV = (size_t)p->U * p->V;
+    const size_t DD = (size_t)(p->S * p->des.md) * (p->S * p->des.nd);
+    auto pad = [](size_t v) { return (v + 63) & ~(size_t)63; };
+    return sizeof(float) * (pad((n + 1) * UV) + pad(n * DD) + pad(DD) + pad(2 * DD) + pad(DD) + pad(2 * t));
+}
+
+yo_status yo_set_morphology(yo_plan *p, const char *ops, double diameter, double alpha)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (p->ws) return fail(YO_ESTATE, "set the morphological filters before binding a workspace");
+    std::string seq = ops ? ops : "";
+    if (seq.empty()) {
+        p->morph_ops.clear();
+        p->mtaps.clear();
+        p->L.morph.bytes = 0;
+        p->L.total = p->L.morph.off;
+        return YO_OK;
+    }
+    if (seq.size() > 8) return fail(YO_EINVAL, "at most 8 morphological operations");
+    for (char ch : seq)
+        if (ch != 'd' && ch != 'e') return fail(YO_EINVAL, "operations are 'd' (dilate) and 'e' (erode)");
+    if (!(diameter > 0)) return fail(YO_EINVAL, "the disc diameter must be positive");
+    if (!(alpha > 0 && alpha <= 80)) return fail(YO_EINVAL, "alpha must be in (0, 80]");
+    const double R = diameter * p->S / 2.0;
+    if (R > 32.0) return fail(YO_EUNSUPPORTED, "disc radius above 32 sub-pixels");
+    std::vector<int> taps;
+    const int n = (int)std::floor(R);
+    for (int dy = -n; dy <= n; ++dy)
+        for (int dx = -n; dx <= n; ++dx)
+            if ((double)(dx * dx + dy * dy) <= R * R) {
+                taps.push_back(dy);
+                taps.push_back(dx);
+            }
+    p->morph_ops = seq;
+    p->morph_d = diameter;
+    p->morph_alpha = alpha;
+    p->mtaps = taps;
+    const size_t bytes = morph_bytes(p, seq.size(), taps.size() / 2);
+    p->L.morph.bytes = bytes;
+    p->L.total = p->L.morph.off + align256(bytes);
     return YO_OK;
 }
 
@@ -766,6 +837,7 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     if ((st = upload_to(c.urange_y, p->urange_y.data(), p->urange_y.size() * 4, s))) return st;
     if ((st = upload_to(c.tap_w_x, p->tap_w_x.data(), p->tap_w_x.size() * 4, s))) return st;
     if ((st = upload_to(c.tap_w_y, p->tap_w_y.data(), p->tap_w_y.size() * 4, s))) return st;
+    if (c.n_morph && (st = upload_to(c.mtap, p->mtaps.data(), p->mtaps.size() * 4, s))) return st;
     if ((st = upload_desc(p, s))) return st;
     // copies from pageable host memory are staged; make them complete before
     // the host vectors can change

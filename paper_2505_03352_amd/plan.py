@@ -85,6 +85,11 @@ class Plan:
         call("yo_plan_create", ct.byref(g), ct.byref(d), self.n_steps, self.n_freq, fr,
              self.n_src, sp, self.n_ports, pp, ct.byref(h))
         self._h = h
+        self.morph_ops = design.get("morph_ops", "") or ""
+        if self.morph_ops:
+            # Eqs. (4)-(6): before the workspace is sized and bound
+            call("yo_set_morphology", self._h, self.morph_ops.encode(),
+                 float(design["morph_d"]), float(design.get("morph_alpha", 20.0)))
         nb = ct.c_size_t()
         call("yo_workspace_bytes", self._h, ct.byref(nb))
         self.workspace_bytes = int(nb.value)
@@ -308,6 +313,8 @@ def grid_design_of(dev):
     design = dict(i0=dev.i0, j0=dev.j0, md=dev.md, nd=dev.nd, k_lo=dev.k_lo, k_hi=dev.k_hi,
                   mc=dev.mc, nc=dev.nc, filter_r=dev.filter_r, supersample=dev.supersample,
                   eps_core=dev.eps_core, eps_clad=dev.eps_clad, sobel_delta=dev.sobel_delta)
+    if getattr(dev, "morph_ops", ""):
+        design.update(morph_ops=dev.morph_ops, morph_d=dev.morph_d, morph_alpha=dev.morph_alpha)
     return grid, design
 
 

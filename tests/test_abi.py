@@ -138,3 +138,32 @@ def test_size_limits_rejected():
     with pytest.raises(_abi.YeeOptError) as e:
         _create(dev, grid={"nx": 3})
     assert e.value.status == _abi.YO_EINVAL
+
+
+def test_morphology_arguments_and_workspace():
+    dev = configs.tiny()
+    p = _create(dev)
+    base = p.workspace_bytes
+    L = _abi.lib()
+    h = p.handle
+    assert L.yo_set_morphology(h, b"edx", 3.0, 20.0) == _abi.YO_EINVAL
+    assert L.yo_set_morphology(h, b"ededededd", 3.0, 20.0) == _abi.YO_EINVAL
+    assert L.yo_set_morphology(h, b"ed", 0.0, 20.0) == _abi.YO_EINVAL
+    assert L.yo_set_morphology(h, b"ed", 3.0, 0.0) == _abi.YO_EINVAL
+    assert L.yo_set_morphology(h, b"ed", 3.0, 81.0) == _abi.YO_EINVAL
+    assert L.yo_set_morphology(h, b"ed", 16.5, 20.0) == _abi.YO_EUNSUPPORTED   # radius 33
+    assert L.yo_set_morphology(h, b"edde", 3.0, 20.0) == _abi.YO_OK
+    nb = ct.c_size_t()
+    assert L.yo_workspace_bytes(h, ct.byref(nb)) == _abi.YO_OK
+    S, U, V = dev.supersample, dev.supersample * (dev.md + 4), dev.supersample * (dev.nd + 4)
+    DD = S * dev.md * S * dev.nd
+    assert nb.value >= base + 4 * (5 * U * V + 4 * DD + 4 * DD + 2 * 113)
+    assert nb.value < base + 4 * (5 * U * V + 8 * DD + 2 * 113) + 4096
+    assert L.yo_set_morphology(h, None, 0.0, 0.0) == _abi.YO_OK          # off again
+    assert L.yo_workspace_bytes(h, ct.byref(nb)) == _abi.YO_OK and nb.value == base
+    p.close()
+    # through the binding: the device description carries the filters
+    dev.morph_ops, dev.morph_d, dev.morph_alpha = "edde", 3.0, 20.0
+    q = _create(dev)
+    assert q.morph_ops == "edde" and q.workspace_bytes > base
+    q.close()
