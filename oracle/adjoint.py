@@ -17,6 +17,13 @@ F = |alpha|^2),
     dF/d kappa_j = -eps_j^2 dF/d eps_j .
 The adjoint sources are unit-amplitude; the coefficient enters afterwards,
 which is the same as scaling the adjoint source by dF/dalpha (Appendix A).
+
+Pulse excitation (the other route of Sec. 2: Fourier transforms of field
+transients): each source and each port is excited once with a Gaussian pulse
+on a carrier, and the phasors of every wavelength come from the DFT of the
+whole run divided by the pulse's own spectrum (``fdtd.extract_pulse``).  Once
+the field has died away the DFT obeys the same frequency-domain equations,
+so alpha, the adjoint fields and Eq. (1) are used exactly as above.
 """
 from __future__ import annotations
 
@@ -86,6 +93,61 @@ def forward_adjoint(dev, C=None, beta=None, n_steps=None, ops=None, kap=None) ->
                 alpha[s, p, f] = ports.alpha(W[p], r.mon[p])
         for p in range(npo):
             adj[p][f] = solve(dev, kap, dev.ports[p].plane, W[p], lam, n_steps)
+    return Result(alpha, fwd, adj, kap, st, W, beta)
+
+
+@dataclass
+class Pulse:
+    """Gaussian pulse exp(-(t - t0)^2 / (2 sigma^2)) on the carrier omega_dt
+    (t in steps), run for n_steps; the last `tail` steps' DFT is also kept
+    apart to show how much the late field still contributes."""
+    omega_dt: float
+    sigma: float
+    t0: float
+    n_steps: int
+    tail: int = 0
+
+
+def solve_pulse(dev, kap, src_plane, src_j, pulse: Pulse) -> List[Solve]:
+    """Phasors at every wavelength of the device from one pulse run; the
+    residual of each is |DFT of the tail| / |DFT of the whole run|."""
+    wf = [dev.omega_dt(lam) for lam in dev.wavelengths]
+    n = pulse.n_steps
+    p = fdtd.SimParams(dev.nx, dev.ny, dev.nz, dev.courant, dev.courant, dev.courant,
+                       tuple(dev.npml), dev.pml_m, dev.pml_sigma_scale, dev.pml_kappa_max,
+                       dev.pml_a_max, n, pulse.omega_dt, 0.0, n - pulse.tail, n,
+                       pulse.sigma, pulse.t0, wf)
+    r = fdtd.run(p, kap, src_plane=src_plane, src_j=src_j, box=dev.dft_box(),
+                 mon_planes=[m.plane for m in dev.ports])
+    sig = fdtd.pulse_samples(n, pulse.omega_dt, pulse.sigma, pulse.t0)
+    out = []
+    for f, w in enumerate(wf):
+        S = fdtd.pulse_spectrum(sig, w)
+        box = fdtd.extract_pulse(r.box_sums[0, f] + r.box_sums[1, f], S)
+        late = fdtd.extract_pulse(r.box_sums[1, f], S)
+        mons = [fdtd.extract_pulse(m[0, f] + m[1, f], S) for m in r.mon_sums]
+        nrm = np.linalg.norm(box)
+        out.append(Solve(box, mons, float(np.linalg.norm(late) / nrm) if nrm > 0 else 0.0))
+    return out
+
+
+def forward_adjoint_pulse(dev, pulse: Pulse, C=None, beta=None, ops=None, kap=None) -> Result:
+    """forward_adjoint with one pulse run per source and per port."""
+    C = dev.C if C is None else C
+    beta = dev.beta if beta is None else beta
+    st = None
+    if kap is None:
+        kap, st = chain.kappa(dev, C, beta, ops)
+    W = [ports.monitor_weights(m.e, m.h) for m in dev.ports]
+    J = [ports.source_current(s.h) for s in dev.sources]
+    ns, npo, nf = len(dev.sources), len(dev.ports), dev.n_freq
+    alpha = np.zeros((ns, npo, nf), np.complex128)
+    fwd = [solve_pulse(dev, kap, dev.sources[s].plane, J[s], pulse) for s in range(ns)]
+    adj = [solve_pulse(dev, kap, dev.ports[p].plane, W[p], pulse) for p in range(npo)]
+    for s in range(ns):
+        for f in range(nf):
+            for p in range(npo):
+                alpha[s, p, f] = ports.alpha(W[p], fwd[s][f].mon[p])
     return Result(alpha, fwd, adj, kap, st, W, beta)
 
 

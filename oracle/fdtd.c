@@ -22,6 +22,14 @@
  *       j^{n+1/2}(r) = ramp(t) Re( jhat(r) exp(-i w t) ),  t = (n+1/2) dt;
  *   - running DFT sums of E^n exp(+i w n dt) over the window, split into two
  *     halves so the caller can measure how steady the field is;
+ *   - or (pulse excitation, the Fourier-transform-of-transients route of
+ *     Sec. 2): the source current of a Gaussian pulse on the carrier w,
+ *       j^{n+1/2}(r) = g(t) Re( jhat(r) exp(-i w t) ),
+ *       g(t) = exp(-(t - t0)^2 / (2 sigma^2)),  t = (n+1/2) dt,
+ *     and DFT sums of E^n exp(+i w_f n dt) over every step for each of
+ *     n_dft frequencies w_f, split at win_start (steps from win_start on go
+ *     to the second set, so the caller can see how much the late field
+ *     still contributes);
  *   - optionally the discrete energy
  *       W^n = sum eps |E^n|^2 + sum Ht^{n-1/2} . Ht^{n+1/2},
  *     which the scheme conserves exactly in a closed lossless box.
@@ -45,6 +53,10 @@ typedef struct {
     double omega_dt;        /* angular frequency times dt                      */
     double ramp_steps;      /* raised-cosine ramp length in steps (0 = none)   */
     int win_start, win_len; /* E^n summed for n in [win_start, win_start+len)  */
+    double pulse_sigma;     /* > 0: pulse excitation (steps); ramp and window unused */
+    double pulse_t0;        /* pulse centre (steps)                            */
+    int n_dft;              /* pulse excitation: number of DFT frequencies     */
+    const double *dft_omega_dt;  /* [n_dft] angular frequencies times dt       */
 } orc_sim;
 
 /* plane normal to `axis` at cell index `index`; (c0, c1) are the two other
@@ -152,10 +164,46 @@ int orc_run(const orc_sim *sim, const double *kappa, double *E, double *H,
     for (int p = 0; p < n_mon; p++) mon_total += 2 * (size_t)mon[p].n0 * mon[p].n1;
     const size_t box_total = box ? 3 * (size_t)box->bx * box->by * box->bz : 0;
 
+    const int pulse = sim->pulse_sigma > 0.0;
     for (int n = 0; n < sim->n_steps; n++) {
+        /* ---- pulse excitation: DFT of E^n at every frequency, every step ---- */
+        for (int f = 0; pulse && f < sim->n_dft; f++) {
+            int h = (n < sim->win_start) ? 0 : 1;
+            double cr = cos(sim->dft_omega_dt[f] * n), ci = sin(sim->dft_omega_dt[f] * n);
+            const double *comp[3] = {Ex, Ey, Ez};
+            if (box) {
+                double *acc = box_acc + 2 * ((size_t)h * sim->n_dft + f) * box_total;
+                for (int c = 0; c < 3; c++)
+                    for (int k = 0; k < box->bz; k++)
+                        for (int j = 0; j < box->by; j++)
+                            for (int i = 0; i < box->bx; i++) {
+                                size_t o = (((size_t)c * box->bz + k) * box->by + j) * box->bx + i;
+                                double e = comp[c][IDX(box->x0 + i, box->y0 + j, box->z0 + k)];
+                                acc[2 * o] += e * cr;
+                                acc[2 * o + 1] += e * ci;
+                            }
+            }
+            double *acc = mon_acc + 2 * ((size_t)h * sim->n_dft + f) * mon_total;
+            size_t off = 0;
+            for (int p = 0; p < n_mon; p++) {
+                int t1, t2;
+                plane_tangentials(mon[p].axis, &t1, &t2);
+                for (int t = 0; t < 2; t++)
+                    for (int b = 0; b < mon[p].n1; b++)
+                        for (int a = 0; a < mon[p].n0; a++) {
+                            int i, j, k;
+                            plane_cell(&mon[p], a, b, &i, &j, &k);
+                            double e = comp[t == 0 ? t1 : t2][IDX(i, j, k)];
+                            size_t o = off + ((size_t)t * mon[p].n1 + b) * mon[p].n0 + a;
+                            acc[2 * o] += e * cr;
+                            acc[2 * o + 1] += e * ci;
+                        }
+                off += 2 * (size_t)mon[p].n0 * mon[p].n1;
+            }
+        }
         /* ---- running DFT of E^n over the window ---- */
         int w = n - sim->win_start;
-        if (w >= 0 && w < sim->win_len) {
+        if (!pulse && w >= 0 && w < sim->win_len) {
             int h = (w < half) ? 0 : 1;
             double cr = cos(sim->omega_dt * n), ci = sin(sim->omega_dt * n);
             if (box) {
@@ -259,7 +307,10 @@ int orc_run(const orc_sim *sim, const double *kappa, double *E, double *H,
         if (src) {
             double t = n + 0.5;
             double r = 1.0;
-            if (sim->ramp_steps > 0.0 && t < sim->ramp_steps)
+            if (pulse) {
+                double d = (t - sim->pulse_t0) / sim->pulse_sigma;
+                r = exp(-0.5 * d * d);
+            } else if (sim->ramp_steps > 0.0 && t < sim->ramp_steps)
                 r = 0.5 * (1.0 - cos(M_PI * t / sim->ramp_steps));
             double ca = r * cos(sim->omega_dt * t), sa = r * sin(sim->omega_dt * t);
             int t1, t2;

@@ -29,7 +29,9 @@ class _Sim(ct.Structure):
                 ("pml_m", ct.c_double), ("pml_sigma_scale", ct.c_double),
                 ("pml_kappa_max", ct.c_double), ("pml_a_max", ct.c_double),
                 ("n_steps", ct.c_int), ("omega_dt", ct.c_double), ("ramp_steps", ct.c_double),
-                ("win_start", ct.c_int), ("win_len", ct.c_int)]
+                ("win_start", ct.c_int), ("win_len", ct.c_int),
+                ("pulse_sigma", ct.c_double), ("pulse_t0", ct.c_double),
+                ("n_dft", ct.c_int), ("dft_omega_dt", ct.POINTER(ct.c_double))]
 
 
 class _Plane(ct.Structure):
@@ -71,6 +73,9 @@ class SimParams:
     ramp_steps: float = 0.0
     win_start: int = 0
     win_len: int = 0
+    pulse_sigma: float = 0.0          # > 0: Gaussian pulse on the carrier omega_dt
+    pulse_t0: float = 0.0
+    dft_omega_dt: Sequence[float] = ()   # pulse excitation: DFT frequencies (every step)
 
 
 @dataclass
@@ -79,6 +84,7 @@ class RunResult:
     H: np.ndarray
     box_sums: Optional[np.ndarray]      # complex [2 halves][3][bz][by][bx]
     mon_sums: List[np.ndarray]          # per plane complex [2 halves][2][n1][n0]
+    # (pulse excitation: [2 parts][n_dft][...] with the part split at win_start)
     energy: Optional[np.ndarray]
 
 
@@ -94,9 +100,12 @@ def run(p: SimParams, kappa: np.ndarray, E0=None, H0=None, src_plane=None, src_j
     kappa = np.ascontiguousarray(kappa, dtype=np.float64).reshape(shape)
     E = np.zeros(shape) if E0 is None else np.array(E0, dtype=np.float64, order="C").reshape(shape)
     H = np.zeros(shape) if H0 is None else np.array(H0, dtype=np.float64, order="C").reshape(shape)
+    pulse = p.pulse_sigma > 0
+    wdft = np.ascontiguousarray(np.asarray(p.dft_omega_dt if pulse else [0.0], np.float64))
+    nd = len(wdft) if pulse else 0
     sim = _Sim(nx, ny, nz, p.sx, p.sy, p.sz, (ct.c_int * 6)(*p.npml), p.pml_m,
                p.pml_sigma_scale, p.pml_kappa_max, p.pml_a_max, p.n_steps, p.omega_dt,
-               p.ramp_steps, p.win_start, p.win_len)
+               p.ramp_steps, p.win_start, p.win_len, p.pulse_sigma, p.pulse_t0, nd, _pd(wdft))
     sp = None
     sj = None
     if src_plane is not None:
@@ -108,7 +117,7 @@ def run(p: SimParams, kappa: np.ndarray, E0=None, H0=None, src_plane=None, src_j
     box_acc = None
     if box is not None:
         bx = _Box(*box)
-        box_acc = np.zeros((2, 3, box[5], box[4], box[3]), np.complex128)
+        box_acc = np.zeros((2, max(nd, 1), 3, box[5], box[4], box[3]), np.complex128)
     planes = list(mon_planes)
     n_mon = len(planes)
     mons = (_Plane * max(1, n_mon))()
@@ -116,7 +125,7 @@ def run(p: SimParams, kappa: np.ndarray, E0=None, H0=None, src_plane=None, src_j
     for q, pl in enumerate(planes):
         mons[q] = _Plane(pl.axis, pl.index, pl.lo0, pl.lo1, pl.n0, pl.n1)
         tot += 2 * pl.n0 * pl.n1
-    mon_acc = np.zeros((2, max(tot, 1)), np.complex128)
+    mon_acc = np.zeros((2, max(nd, 1), max(tot, 1)), np.complex128)
     en = np.zeros(max(p.n_steps, 1)) if energy else None
     rc = lib().orc_run(ct.byref(sim), _pd(kappa), _pd(E), _pd(H),
                        ct.byref(sp) if sp is not None else None,
@@ -131,8 +140,11 @@ def run(p: SimParams, kappa: np.ndarray, E0=None, H0=None, src_plane=None, src_j
     off = 0
     for pl in planes:
         n = 2 * pl.n0 * pl.n1
-        mon_sums.append(mon_acc[:, off:off + n].reshape(2, 2, pl.n1, pl.n0))
+        m = mon_acc[:, :, off:off + n].reshape(2, max(nd, 1), 2, pl.n1, pl.n0)
+        mon_sums.append(m if pulse else m[:, 0])
         off += n
+    if box_acc is not None and not pulse:
+        box_acc = box_acc[:, 0]
     return RunResult(E, H, box_acc, mon_sums, en[:p.n_steps] if energy else None)
 
 
@@ -162,3 +174,26 @@ def extract_halves(sums2: np.ndarray, omega_dt: float, win_start: int, win_len: 
     nrm = np.linalg.norm(full)
     resid = float(np.linalg.norm(e2 - e1) / nrm) if nrm > 0 else 0.0
     return full, resid
+
+
+def pulse_samples(n_steps: int, omega_dt: float, sigma: float, t0: float) -> np.ndarray:
+    """The complex pulse signal s(t) = g(t) exp(-i w t) at t = n + 1/2 (in
+    steps) for n in [0, n_steps): the source current is Re(jhat s(t))."""
+    t = np.arange(n_steps, dtype=np.float64) + 0.5
+    return np.exp(-0.5 * ((t - t0) / sigma) ** 2) * np.exp(-1j * omega_dt * t)
+
+
+def pulse_spectrum(s: np.ndarray, omega_dt: float) -> complex:
+    """Discrete-time Fourier transform of the source signal at its sample
+    times: S(w) = sum_m s_m exp(+i w (m + 1/2))."""
+    t = np.arange(len(s), dtype=np.float64) + 0.5
+    return complex(np.sum(s * np.exp(1j * omega_dt * t)))
+
+
+def extract_pulse(sums: np.ndarray, S: complex) -> np.ndarray:
+    """Phasor from the DFT of a pulse response.  The response to the real
+    source Re(jhat s) is the real part of the response to jhat s, whose DFT
+    is S(w) Ehat(w); the conjugate half sits at -w and is negligible for a
+    smooth envelope, so Ehat(w) = 2 sum_n E^n exp(+i w n) / S(w)."""
+    return 2.0 * sums / S
+

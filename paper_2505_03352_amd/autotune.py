@@ -2,7 +2,7 @@
 
 Each step runs two launches, the interior tiles and the CPML shell; their
 layout choices are independent except for what the two share (z-planes per
-tile, waves per block, whether the x-shell is cut into full strips).  For
+tile, waves per block, how the x-shell strips are cut).  For
 each shared setting the tuner times every interior choice (cooperative
 blocks or not, prefetch or not) with the interior launch alone and every
 shell choice (cooperative, per-class code, prefetch) with the shell launch
@@ -25,8 +25,9 @@ import torch
 from ._abi import YO_BOTH
 
 ROWS = 4
-# shared settings: (z-planes per tile, flags from {1: x-strips, 2: 8 waves per block})
-SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b) for z in (8, 16, 32) for a in (0, 1)
+# shared settings: (z-planes per tile, flags from {1: full 62-cell x-shell strips,
+# 128: x-shell strips sized so the interior strips are whole, 2: 8 waves per block})
+SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b) for z in (8, 16, 32) for a in (0, 1, 128)
                                             for b in (0, 2))
 INTERIOR_FLAGS = (0, 16, 32, 16 | 32)          # cooperative, no prefetch
 SHELL_FLAGS = tuple(a | b | c for a in (0, 4) for b in (0, 8) for c in (0, 64))

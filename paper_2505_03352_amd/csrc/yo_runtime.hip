@@ -79,7 +79,8 @@ enum {
     YO_TILE_COOP_INT = 16,    // interior: cooperative blocks
     YO_TILE_NOPF_INT = 32,    // interior: no prefetch of the next plane
     YO_TILE_NOPF_SHELL = 64,  // CPML shell: no prefetch of the next plane
-    YO_TILE_ALL = 127
+    YO_TILE_XFULL = 128,      // x-shell strips as narrow as whole 62-cell interior strips allow
+    YO_TILE_ALL = 255
 };
 
 struct yo_plan {
@@ -308,7 +309,18 @@ void build_tiles(yo_plan *p)
     for (int a = 0; a < 3; ++a) {
         lo[a] = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
         hi[a] = n[a] - p->phi[a];
-        if (a == 0 && (p->tflags & YO_TILE_XSTRIPS)) {
+        if (a == 0 && (p->tflags & YO_TILE_XFULL) && hi[0] - lo[0] >= YO_TX) {
+            // the interior takes as many whole strips as fit; the rest of the
+            // row goes to the two shell strips (which then also carry
+            // interior columns)
+            const int whole = (hi[0] - lo[0]) / YO_TX * YO_TX;
+            const int rest = n[0] - whole;
+            int wlo = p->plo[0] > 0 ? (p->phi[0] > 0 ? rest / 2 : rest) : 0;
+            wlo = std::max(wlo, lo[0]);
+            wlo = std::min(wlo, n[0] - whole - (n[0] - hi[0]));
+            lo[0] = wlo;
+            hi[0] = wlo + whole;
+        } else if (a == 0 && (p->tflags & YO_TILE_XSTRIPS)) {
             // full-width CPML strips: the shell strips also carry interior columns
             if (p->plo[0] > 0) lo[0] = std::max(lo[0], std::min(YO_TX, n[0]));
             if (p->phi[0] > 0) hi[0] = std::min(hi[0], n[0] - YO_TX);

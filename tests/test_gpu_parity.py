@@ -120,6 +120,39 @@ def _sourced_box(nx=72, ny=40, nz=34, npml=6, seed=5):
     return kap, pl, h, w_dt, npml
 
 
+def test_whole_interior_strip_tilings_bitwise_equal():
+    """Tilings that cut the x-shell so the interior strips are whole (flag
+    128), on a grid wide enough for them, give bitwise the fields of the
+    plain tiling (which the test below checks against the oracle)."""
+    kap, pl, h, w_dt, npml = _sourced_box(nx=150)
+    _, nz, ny, nx = kap.shape
+    steps = 200
+    from paper_2505_03352_amd.plan import FreqSpec, Plan
+    grid = dict(nx=nx, ny=ny, nz=nz, dx=40e-9, dy=40e-9, dz=40e-9, courant=0.5, npml=(npml,) * 6)
+    design = dict(i0=30, j0=15, md=4, nd=4, k_lo=15, k_hi=16, mc=2, nc=2, filter_r=1.0,
+                  supersample=2, eps_core=12.11, eps_clad=2.085, sobel_delta=1e-6)
+    dt = 0.5 * 40e-9 / 299792458.0
+    f = FreqSpec(w_dt / dt, 40.0, steps - 60, 60)
+    outs = {}
+    for rows, zc, fl in [(4, 16, 0), (4, 16, 128), (4, 16, 201), (4, 8, 178), (4, 16, 129),
+                         (4, 4, 232)]:
+        say(f"whole-strip tiling=({rows},{zc},{fl})")
+        p = Plan(grid, design, steps, [f], [pl], [], device="cuda")
+        p.bind()
+        p.set_background(torch.as_tensor(kap, dtype=torch.float32), torch.zeros(p.canvas_shape))
+        p.set_source_mode(0, h)
+        p.set_tiling(rows, zc, fl)
+        p.reset(1)
+        p.advance(1, steps)
+        E, H = p.get_fields(0)
+        outs[(rows, zc, fl)] = (E.cpu().numpy(), H.cpu().numpy())
+        p.close()
+    ref = outs[(4, 16, 0)]
+    assert np.abs(ref[0]).max() > 0
+    for k, v in outs.items():
+        assert np.array_equal(v[0], ref[0]) and np.array_equal(v[1], ref[1]), k
+
+
 def test_fields_match_oracle_with_cpml_and_source():
     kap, pl, h, w_dt, npml = _sourced_box()
     _, nz, ny, nx = kap.shape
