@@ -93,12 +93,16 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="plain launches instead of HIP-graph replays (for counter collection)")
-    ap.add_argument("--workload", choices=("realistic", "batch", "serving", "optimize"),
+    ap.add_argument("--workload", choices=("realistic", "batch", "serving", "optimize", "broadband"),
                     default="realistic",
                     help="realistic: the headline line; batch / serving: the batched and served "
                          "forms against one-at-a-time solves (their own JSON line)")
     ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
     ap.add_argument("--iters", type=int, default=5, help="optimize: optimizer iterations")
+    ap.add_argument("--pulse-steps", type=int, default=10000,
+                    help="broadband: steps of the pulse runs")
+    ap.add_argument("--pulse-k", type=float, default=1.0,
+                    help="broadband: band edges in spectral widths of the pulse")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: arrival rate, requests/s")
     ap.add_argument("--max-cells", type=float, default=4.5e7,
@@ -116,6 +120,8 @@ def main():
         return bench_serving(args)
     if args.workload == "optimize":
         return bench_optimize(args)
+    if args.workload == "broadband":
+        return bench_broadband(args)
 
     import torch
     from paper_2505_03352_amd import YO_BOTH, autotune
@@ -223,9 +229,9 @@ def main():
     plan.close()
 
 
-def _line(metric, value, unit, ms, args, cfg, extra):
+def _line(metric, value, unit, ms, args, cfg, extra, steps=1, warmup=0):
     out = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
-           "steps": 1, "warmup": 0, "ms_per_step": round(ms, 2), "higher_is_better": True,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 2), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": cfg}
     out.update(extra)
@@ -316,6 +322,66 @@ def bench_serving(args):
            "one_at_a_time": {"designs_per_h": round(b.throughput_per_h, 1),
                              "p50_s": round(b.p50_s, 3), "p99_s": round(b.p99_s, 3),
                              "gcell_updates_per_s": round(b.cell_updates / b.makespan_s / 1e9, 3)}})
+
+
+def bench_broadband(args):
+    """Gradients of the realistic device's three wavelengths from pulse runs
+    (one per source and per port, every wavelength's DFT accumulated in the
+    same run) against the time-harmonic runs (one per source or port and
+    wavelength): gradients per hour of each, and how far apart the two
+    gradients and modal coefficients are."""
+    import numpy as np
+    import torch
+    from paper_2505_03352_amd import YO_BOTH, autotune
+    from paper_2505_03352_amd.plan import plan_for
+    from workloads import configs
+    torch.cuda.set_device(0)
+    dev = configs.realistic()
+    C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
+
+    def grad(plan):
+        plan.set_design(C, dev.beta)
+        plan.run(YO_BOTH, chunk=args.chunk, use_graph=not args.eager)
+        a = plan.alpha()
+        return a, plan.gradient(torch.conj(a))
+
+    def timed(plan, n):
+        grad(plan)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            a, g = grad(plan)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n, a.cpu().numpy(), g.cpu().numpy()
+
+    ph = plan_for(dev, device="cuda:0")
+    th = autotune.tune(ph, YO_BOTH, use_cache=False)
+    s_h, a_h, g_h = timed(ph, args.steps)
+    ph.close()
+    log(f"time-harmonic: {s_h * 1e3:.1f} ms per gradient ({ph.n_rhs} runs x {dev.n_steps} steps)")
+    dp = configs.realistic(n_steps=args.pulse_steps)
+    w0, sig, t0 = dp.pulse(k=args.pulse_k)
+    pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0))
+    tp = autotune.tune(pp, YO_BOTH, use_cache=False)
+    s_p, a_p, g_p = timed(pp, args.steps)
+    ea = float(np.abs(a_p - a_h).max() / np.abs(a_h).max())
+    eg = float(np.linalg.norm(g_p - g_h) / np.linalg.norm(g_h))
+    cells = pp.n_stepped * dp.cells * dp.n_steps
+    log(f"pulse: {s_p * 1e3:.1f} ms per gradient ({pp.n_stepped} runs x {dp.n_steps} steps, sigma "
+        f"{sig:.0f}, t0 {t0:.0f}); alpha max diff {ea:.2e}, gradient rel L2 diff {eg:.2e}")
+    pp.close()
+    _line("adjoint gradients/hour, 3 wavelengths (pulse excitation)", 3600.0 / s_p, "gradients/h",
+          s_p * 1e3, args,
+          {"workload": "realistic: 320x240x96 cells at 20 nm (CPML 8), 100x100 design/controls, "
+                       "r=3, beta=8, wavelengths 1.50/1.55/1.60 um; pulse runs (1 forward + 1 "
+                       f"adjoint, {dp.n_steps} steps, carrier mid-band, sigma {sig:.0f} steps, "
+                       f"t0 {t0:.0f}) against time-harmonic runs (3 x (1 + 1), {dev.n_steps} steps)",
+           "tiling_pulse": [tp["rows"], tp["zchunk"], tp["flags"]],
+           "tiling_harmonic": [th["rows"], th["zchunk"], th["flags"]]},
+          {"gcell_updates_per_s": round(cells / s_p / 1e9, 3),
+           "time_harmonic_gradients_per_hour": round(3600.0 / s_h, 1),
+           "speedup_vs_time_harmonic": round(s_h / s_p, 3),
+           "alpha_max_rel_diff": ea, "gradient_rel_l2_diff": eg}, steps=args.steps, warmup=1)
 
 
 def bench_optimize(args):

@@ -129,6 +129,25 @@ void yo_plan_destroy(yo_plan *plan);
  * sub-pixels.  Changes yo_workspace_bytes. */
 yo_status yo_set_morphology(yo_plan *plan, const char *ops, double diameter, double alpha);
 
+/* Pulse excitation (Sec. 2's other route to frequency-domain fields:
+ * Fourier transforms of field transients), host only, before
+ * yo_bind_workspace (YO_ESTATE after).  With sigma_steps > 0 every source
+ * and every port is stepped once instead of once per wavelength: its
+ * current is g(t) Re(jhat e^{-i omega0 t}), g(t) = exp(-(t - t0)^2 /
+ * (2 sigma^2)), t = (n + 1/2) dt in steps, and the DFT of every step is
+ * accumulated at each wavelength of the plan.  yo_finalize turns the sums
+ * into the phasors 2 DFT(w) / S(w), S(w) = sum_n s_n e^{+i w (n + 1/2) dt}
+ * of the injected samples s_n = g e^{-i omega0 t}, so yo_get_dft, yo_alpha
+ * and the gradients keep their meaning and numbering (one output
+ * right-hand side per source or port and wavelength).  The phasors are
+ * exact when the field has died away by the end of the run and the pulse
+ * spectrum at -w is negligible; the caller picks n_steps, sigma and t0 for
+ * that.  The yo_freq windows and ramps are not used.  The stepped
+ * right-hand sides (yo_set_fields / yo_get_fields) are the sources, then
+ * the ports.  sigma_steps <= 0 turns the pulse off.  YO_EINVAL for a
+ * carrier outside (0, pi/dt) or t0 < 0.  Changes yo_workspace_bytes. */
+yo_status yo_set_pulse(yo_plan *plan, double omega0, double sigma_steps, double t0_steps);
+
 /* Device bytes the plan needs (host only). */
 yo_status yo_workspace_bytes(const yo_plan *plan, size_t *bytes);
 
@@ -237,7 +256,8 @@ yo_status yo_rhs_count(const yo_plan *plan, int *n_rhs);
 yo_status yo_get_dft(const yo_plan *plan, int rhs, int region, float *dev_out, yo_stream stream);
 
 /* Test hooks: current fields of `rhs` as FP32 [3][nz][ny][nx] (E^n and
- * Ht^{n-1/2} after n steps). */
+ * Ht^{n-1/2} after n steps); rhs counts the stepped right-hand sides (under
+ * a pulse: the sources, then the ports). */
 yo_status yo_set_fields(yo_plan *plan, int rhs, const float *dev_E, const float *dev_H,
                         yo_stream stream);
 yo_status yo_get_fields(const yo_plan *plan, int rhs, float *dev_E, float *dev_H,

@@ -42,7 +42,8 @@ def cache_path() -> str:
 def shape_key(plan, which: int) -> str:
     g = plan.grid
     nxp = (g["nx"] + 31) // 32 * 32
-    r = plan.n_fwd if which == 1 else (plan.n_rhs - plan.n_fwd if which == 2 else plan.n_rhs)
+    nf, nr = plan.n_stepped_fwd, plan.n_stepped
+    r = nf if which == 1 else (nr - nf if which == 2 else nr)
     arch = "gfx950"
     try:
         arch = torch.cuda.get_device_properties(plan.device).gcnArchName.split(":")[0]

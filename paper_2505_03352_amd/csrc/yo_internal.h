@@ -37,13 +37,16 @@ struct YoRhsD {
     float *psi;
     float2 *dft_box;         // [3][bz][by][bx]
     float2 *dft_mon;         // concatenated port planes [2][n1][n0]
-    const float4 *steptab;   // [n_steps]: (ramp cos, ramp sin) at (n+1/2)dt, (cos, sin) at n dt
+    const float4 *steptab;   // [n_steps]: source signal (x, y) at (n+1/2)dt, (cos, sin) at n dt
     const float2 *src_j;     // [2][n1][n0], nullptr if no source
     YoPlaneD src;
     int win_start, win_len;
     float ginv[4];           // inverse Gram matrix of the steady-state fit
     int freq;
-    int pad_;
+    int n_dft;               // frequencies this right-hand side's DFT accumulates (1, or all under a pulse)
+    const float4 *dfttab;    // DFT phases (.z, .w) of frequency f at step n: dfttab[f * n_steps + n]
+    int box_fstride;         // float2 entries from one frequency's DFT box to the next
+    int mon_fstride;         // the same for the port planes
 };
 
 // One plan (one geometry): shared material and geometry description.

@@ -89,6 +89,12 @@ struct yo_plan {
     yo_grid grid{};
     yo_design des{};
     int n_steps = 0, n_freq = 0, n_src = 0, n_ports = 0, n_rhs = 0, n_fwd = 0;
+    // stepped right-hand sides: all of them, or under a pulse one per source
+    // and one per port (each then accumulates every frequency's DFT)
+    int n_phys = 0, n_pfwd = 0;
+    bool pulse = false;
+    double pulse_w = 0, pulse_sigma = 0, pulse_t0 = 0;
+    std::vector<float> fin;      // [n_freq][4] phasor matrices applied at finalize
     std::vector<yo_freq> freqs;
     std::vector<yo_plane> src_planes, port_planes;
     double dt = 0, sx = 0, sy = 0, sz = 0;
@@ -200,9 +206,54 @@ void build_profiles(yo_plan *p)
     }
 }
 
+size_t fields_per_rhs(const yo_plan *p);
+
+// Bytes of the morphological region for n stages and t taps (each buffer
+// padded to 64 floats, as set_chain_ptrs carves them).
+size_t morph_bytes(const yo_plan *p, size_t n, size_t t)
+{
+    const size_t UV = (size_t)p->U * p->V;
+    const size_t DD = (size_t)(p->S * p->des.md) * (p->S * p->des.nd);
+    auto pad = [](size_t v) { return (v + 63) & ~(size_t)63; };
+    return sizeof(float) * (pad((n + 1) * UV) + pad(n * DD) + pad(DD) + pad(2 * DD) + pad(DD) + pad(2 * t));
+}
+
+
+// Workspace regions (fields, CPML memories and descriptors per stepped
+// right-hand side; DFT results per output right-hand side).
+void build_layout(yo_plan *p)
+{
+    const yo_design &d = p->des;
+    const yo_grid &g = p->grid;
+    Layout &L = p->L;
+    L = Layout{};
+    L.add(L.fields, sizeof(float) * fields_per_rhs(p) * p->n_phys);
+    L.add(L.kappa, sizeof(float) * 3 * p->cells_p);
+    L.add(L.psi, sizeof(float) * p->psi_per_rhs * p->n_phys);
+    L.add(L.dft_box, sizeof(float2) * 3 * p->bsz * p->n_rhs);
+    L.add(L.dft_mon, sizeof(float2) * std::max<size_t>(p->mon_total, 1) * p->n_rhs);
+    L.add(L.src_j, sizeof(float2) * std::max<size_t>(p->src_total, 1));
+    L.add(L.port_w, sizeof(float2) * std::max<size_t>(p->port_total, 1));
+    L.add(L.steptab, sizeof(float4) * (size_t)(p->n_freq + 1) * p->n_steps);
+    L.add(L.prof, sizeof(float) * 6 * (size_t)(g.nx + g.ny + g.nz));
+    L.add(L.desc_plan, sizeof(YoPlanD));
+    L.add(L.desc_rhs, sizeof(YoRhsD) * p->n_phys);
+    L.add(L.ctr, 256);
+    L.add(L.tiles, sizeof(int4) * p->tiles_cap);
+    const size_t G = (size_t)p->G0 * p->G1;
+    const size_t UV = (size_t)p->U * p->V;
+    const size_t DD = (size_t)(p->S * d.md) * (p->S * d.nd);
+    const size_t nf = 2 * UV + DD /*tanh*/ + 9 * G + 6 * G + 4 * G + 6 * G + 4 * G + 2 * G + DD /*gphi*/ +
+                      (size_t)(p->S * d.nd) * d.mc /*tmp*/ + (size_t)p->tmax * p->S * (d.md + d.nd);
+    L.add(L.chain_f, sizeof(float) * (nf + 64 * 16));   // each of 15 buffers padded to 64 floats
+    const size_t ni = 2 * (size_t)p->S * (d.md + d.nd) + 2 * (size_t)(d.mc + d.nc);
+    L.add(L.chain_i, sizeof(int) * (ni + 64 * 8));     // each of 6 tables padded to 64 ints
+    L.add(L.morph, p->morph_ops.empty() ? 0 : morph_bytes(p, p->morph_ops.size(), p->mtaps.size() / 2));
+}
+
 void build_steptab(yo_plan *p)
 {
-    p->steptab.resize((size_t)p->n_freq * p->n_steps);
+    p->steptab.resize((size_t)(p->n_freq + (p->pulse ? 1 : 0)) * p->n_steps);
     p->ginv.assign(4 * (size_t)p->n_freq, 0.0f);
     for (int f = 0; f < p->n_freq; ++f) {
         const double w = p->omega_dt[f];
@@ -230,6 +281,36 @@ void build_steptab(yo_plan *p)
         p->ginv[4 * f + 1] = (float)(-g01 / det);
         p->ginv[4 * f + 2] = (float)(-g01 / det);
         p->ginv[4 * f + 3] = (float)(g00 / det);
+    }
+    p->fin = p->ginv;
+    if (!p->pulse) return;
+    // Pulse excitation: the source signal g(t) e^{-i w0 t}, g a Gaussian, at
+    // t = n + 1/2, stored like the ramped carrier (x = g cos, y = g sin, so
+    // the current is Re(jhat (x - i y))).  The response to the real source is
+    // the real part of the response to jhat s(t), whose DFT at w is
+    // S(w) Ehat(w) with S(w) = sum_m s_m e^{+i w (m + 1/2)} (the conjugate part
+    // lies at -w), so Ehat(w) = (2 / S(w)) DFT(w): applied at finalize as the
+    // real 2 x 2 matrix of that complex factor.  S is summed over the stored
+    // (rounded) samples, which are what the run injects.
+    float4 *row = p->steptab.data() + (size_t)p->n_freq * p->n_steps;
+    for (int n = 0; n < p->n_steps; ++n) {
+        const double t = n + 0.5;
+        const double d = (t - p->pulse_t0) / p->pulse_sigma;
+        const double gt = std::exp(-0.5 * d * d);
+        row[n] = make_float4((float)(gt * std::cos(p->pulse_w * t)), (float)(gt * std::sin(p->pulse_w * t)),
+                             0.0f, 0.0f);
+    }
+    for (int f = 0; f < p->n_freq; ++f) {
+        std::complex<double> S = 0.0;
+        for (int n = 0; n < p->n_steps; ++n) {
+            const std::complex<double> sm((double)row[n].x, -(double)row[n].y);
+            S += sm * std::polar(1.0, p->omega_dt[f] * (n + 0.5));
+        }
+        const std::complex<double> c = 2.0 / S;
+        p->fin[4 * f + 0] = (float)c.real();
+        p->fin[4 * f + 1] = (float)(-c.imag());
+        p->fin[4 * f + 2] = (float)c.imag();
+        p->fin[4 * f + 3] = (float)c.real();
     }
 }
 
@@ -390,13 +471,31 @@ yo_status upload_desc(yo_plan *p, hipStream_t s)
     return upload(p, p->L.desc_rhs, p->hrhs.data(), sizeof(YoRhsD) * p->hrhs.size(), s);
 }
 
+// stepped right-hand sides of `which`
 void set_rhs_range(const yo_plan *p, int which, int &r0, int &r1)
+{
+    r0 = (which & YO_FORWARD) ? 0 : p->n_pfwd;
+    r1 = (which & YO_ADJOINT) ? p->n_phys : p->n_pfwd;
+}
+
+// right-hand sides of `which` in the output numbering (DFT results)
+void set_out_range(const yo_plan *p, int which, int &r0, int &r1)
 {
     r0 = (which & YO_FORWARD) ? 0 : p->n_fwd;
     r1 = (which & YO_ADJOINT) ? p->n_rhs : p->n_fwd;
 }
 
 size_t fields_per_rhs(const yo_plan *p) { return 12 * p->cells_p; }   // 2 buffers x (E, H) x 3
+
+// DFT results of output right-hand side r (numbering of yo_rhs_count)
+float2 *box_of(const yo_plan *p, int r)
+{
+    return reinterpret_cast<float2 *>(p->ws + p->L.dft_box.off) + 3 * p->bsz * r;
+}
+float2 *mon_of(const yo_plan *p, int r)
+{
+    return reinterpret_cast<float2 *>(p->ws + p->L.dft_mon.off) + std::max<size_t>(p->mon_total, 1) * r;
+}
 
 }  // namespace
 
@@ -540,29 +639,9 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     p->tmax = 2 * (int)std::ceil(d.filter_r) + 2;
     p->tiles_cap = tiles_capacity(g, 4, 4);
 
-    Layout &L = p->L;
-    L.add(L.fields, sizeof(float) * fields_per_rhs(p) * p->n_rhs);
-    L.add(L.kappa, sizeof(float) * 3 * p->cells_p);
-    L.add(L.psi, sizeof(float) * p->psi_per_rhs * p->n_rhs);
-    L.add(L.dft_box, sizeof(float2) * 3 * p->bsz * p->n_rhs);
-    L.add(L.dft_mon, sizeof(float2) * std::max<size_t>(p->mon_total, 1) * p->n_rhs);
-    L.add(L.src_j, sizeof(float2) * std::max<size_t>(p->src_total, 1));
-    L.add(L.port_w, sizeof(float2) * std::max<size_t>(p->port_total, 1));
-    L.add(L.steptab, sizeof(float4) * (size_t)n_freq * n_steps);
-    L.add(L.prof, sizeof(float) * 6 * (size_t)(g.nx + g.ny + g.nz));
-    L.add(L.desc_plan, sizeof(YoPlanD));
-    L.add(L.desc_rhs, sizeof(YoRhsD) * p->n_rhs);
-    L.add(L.ctr, 256);
-    L.add(L.tiles, sizeof(int4) * p->tiles_cap);
-    const size_t G = (size_t)p->G0 * p->G1;
-    const size_t UV = (size_t)p->U * p->V;
-    const size_t DD = (size_t)(p->S * d.md) * (p->S * d.nd);
-    const size_t nf = 2 * UV + DD /*tanh*/ + 9 * G + 6 * G + 4 * G + 6 * G + 4 * G + 2 * G + DD /*gphi*/ +
-                      (size_t)(p->S * d.nd) * d.mc /*tmp*/ + (size_t)p->tmax * p->S * (d.md + d.nd);
-    L.add(L.chain_f, sizeof(float) * (nf + 64 * 16));   // each of 15 buffers padded to 64 floats
-    const size_t ni = 2 * (size_t)p->S * (d.md + d.nd) + 2 * (size_t)(d.mc + d.nc);
-    L.add(L.chain_i, sizeof(int) * (ni + 64 * 8));     // each of 6 tables padded to 64 ints
-    L.add(L.morph, 0);           // last: yo_set_morphology sizes it before binding
+    p->n_phys = p->n_rhs;
+    p->n_pfwd = p->n_fwd;
+    build_layout(p);
 
     build_profiles(p);
     build_steptab(p);
@@ -659,10 +738,10 @@ static yo_status rebuild_descriptors(yo_plan *p)
         P.mon_off[q] = (int)p->mon_off[q];
     }
     P.step_ctr = wsp<int>(p, p->L.ctr);
-    P.n_rhs = p->n_rhs;
+    P.n_rhs = p->n_phys;
     P.rhs = wsp<YoRhsD>(p, p->L.desc_rhs);
 
-    p->hrhs.assign(p->n_rhs, YoRhsD{});
+    p->hrhs.assign(p->n_phys, YoRhsD{});
     float *fields = wsp<float>(p, p->L.fields);
     float *psi = wsp<float>(p, p->L.psi);
     float2 *dbox = wsp<float2>(p, p->L.dft_box);
@@ -670,25 +749,29 @@ static yo_status rebuild_descriptors(yo_plan *p)
     const float2 *srcj = wsp<float2>(p, p->L.src_j);
     const float2 *portw = wsp<float2>(p, p->L.port_w);
     const float4 *stab = wsp<float4>(p, p->L.steptab);
-    for (int r = 0; r < p->n_rhs; ++r) {
+    for (int r = 0; r < p->n_phys; ++r) {
         YoRhsD &R = p->hrhs[r];
         float *f = fields + fields_per_rhs(p) * r;
         R.F[0] = f;
         R.F[1] = f + 6 * p->cells_p;
         R.psi = psi + p->psi_per_rhs * r;
-        R.dft_box = dbox + 3 * p->bsz * r;
-        R.dft_mon = dmon + std::max<size_t>(p->mon_total, 1) * r;
+        // under a pulse, stepped right-hand side r stands for the output
+        // right-hand sides of its source or port at every frequency; its
+        // DFT pointers are those of frequency 0
+        const int ro = !p->pulse ? r : (r < p->n_pfwd ? r : p->n_fwd + (r - p->n_pfwd));
+        R.dft_box = dbox + 3 * p->bsz * ro;
+        R.dft_mon = dmon + std::max<size_t>(p->mon_total, 1) * ro;
         int f_idx, srcp;
         const float2 *jp;
         YoPlaneD pl;
-        if (r < p->n_fwd) {
-            f_idx = r / std::max(p->n_src, 1);
-            srcp = r % std::max(p->n_src, 1);
+        if (ro < p->n_fwd) {
+            f_idx = ro / std::max(p->n_src, 1);
+            srcp = ro % std::max(p->n_src, 1);
             const yo_plane &q = p->src_planes[srcp];
             pl = YoPlaneD{q.axis, q.index, q.lo0, q.lo1, q.n0, q.n1};
             jp = p->src_set[srcp] ? srcj + p->src_off[srcp] : nullptr;
         } else {
-            const int ra = r - p->n_fwd;
+            const int ra = ro - p->n_fwd;
             f_idx = ra / p->n_ports;
             srcp = ra % p->n_ports;
             const yo_plane &q = p->port_planes[srcp];
@@ -702,6 +785,20 @@ static yo_status rebuild_descriptors(yo_plan *p)
         R.win_len = p->freqs[f_idx].win_len;
         for (int i = 0; i < 4; ++i) R.ginv[i] = p->ginv[4 * f_idx + i];
         R.freq = f_idx;
+        R.n_dft = 1;
+        R.dfttab = R.steptab;
+        R.box_fstride = 0;
+        R.mon_fstride = 0;
+        if (p->pulse) {
+            const int per = ro < p->n_fwd ? p->n_src : p->n_ports;   // output RHS per frequency
+            R.steptab = stab + (size_t)p->n_freq * p->n_steps;
+            R.win_start = 0;
+            R.win_len = p->n_steps;
+            R.n_dft = p->n_freq;
+            R.dfttab = stab;
+            R.box_fstride = (int)(3 * p->bsz * per);
+            R.mon_fstride = (int)(std::max<size_t>(p->mon_total, 1) * per);
+        }
     }
     return YO_OK;
 }
@@ -775,16 +872,6 @@ static yo_status set_chain_ptrs(yo_plan *p)
     return YO_OK;
 }
 
-// Bytes of the morphological region for n stages and t taps (each buffer
-// padded to 64 floats, as set_chain_ptrs carves them).
-static size_t morph_bytes(const yo_plan *p, size_t n, size_t t)
-{
-    const size_t UV = (size_t)p->U * p->V;
-    const size_t DD = (size_t)(p->S * p->des.md) * (p->S * p->des.nd);
-    auto pad = [](size_t v) { return (v + 63) & ~(size_t)63; };
-    return sizeof(float) * (pad((n + 1) * UV) + pad(n * DD) + pad(DD) + pad(2 * DD) + pad(DD) + pad(2 * t));
-}
-
 yo_status yo_set_morphology(yo_plan *p, const char *ops, double diameter, double alpha)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
@@ -793,8 +880,7 @@ yo_status yo_set_morphology(yo_plan *p, const char *ops, double diameter, double
     if (seq.empty()) {
         p->morph_ops.clear();
         p->mtaps.clear();
-        p->L.morph.bytes = 0;
-        p->L.total = p->L.morph.off;
+        build_layout(p);
         return YO_OK;
     }
     if (seq.size() > 8) return fail(YO_EINVAL, "at most 8 morphological operations");
@@ -816,9 +902,31 @@ yo_status yo_set_morphology(yo_plan *p, const char *ops, double diameter, double
     p->morph_d = diameter;
     p->morph_alpha = alpha;
     p->mtaps = taps;
-    const size_t bytes = morph_bytes(p, seq.size(), taps.size() / 2);
-    p->L.morph.bytes = bytes;
-    p->L.total = p->L.morph.off + align256(bytes);
+    build_layout(p);
+    return YO_OK;
+}
+
+yo_status yo_set_pulse(yo_plan *p, double omega0, double sigma_steps, double t0_steps)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (p->ws) return fail(YO_ESTATE, "set the pulse before binding a workspace");
+    if (!(sigma_steps > 0)) {
+        p->pulse = false;
+        p->n_phys = p->n_rhs;
+        p->n_pfwd = p->n_fwd;
+    } else {
+        const double w = omega0 * p->dt;
+        if (!(w > 0 && w < M_PI)) return fail(YO_EINVAL, "carrier outside (0, pi / dt)");
+        if (!(t0_steps >= 0)) return fail(YO_EINVAL, "negative pulse centre");
+        p->pulse = true;
+        p->pulse_w = w;
+        p->pulse_sigma = sigma_steps;
+        p->pulse_t0 = t0_steps;
+        p->n_phys = p->n_src + p->n_ports;
+        p->n_pfwd = p->n_src;
+    }
+    build_steptab(p);
+    build_layout(p);
     return YO_OK;
 }
 
@@ -982,10 +1090,14 @@ yo_status yo_reset(yo_plan *p, int which, yo_stream stream)
                               fields_per_rhs(p) * (r1 - r0), 0.0f, s));
         HIPCHK(yo_launch_fill(wsp<float>(p, p->L.psi) + p->psi_per_rhs * r0,
                               p->psi_per_rhs * (r1 - r0), 0.0f, s));
-        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.dft_box) + 6 * p->bsz * r0, 6 * p->bsz * (r1 - r0),
+    }
+    int o0, o1;
+    set_out_range(p, which, o0, o1);
+    if (o1 > o0) {
+        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.dft_box) + 6 * p->bsz * o0, 6 * p->bsz * (o1 - o0),
                               0.0f, s));
         const size_t mt = std::max<size_t>(p->mon_total, 1);
-        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.dft_mon) + 2 * mt * r0, 2 * mt * (r1 - r0), 0.0f, s));
+        HIPCHK(yo_launch_fill(wsp<float>(p, p->L.dft_mon) + 2 * mt * o0, 2 * mt * (o1 - o0), 0.0f, s));
     }
     YoCtrArgs ca{};
     ca.n = 1;
@@ -1116,6 +1228,7 @@ static bool chunk_needs_dft(yo_plan *const *plans, const int *which, int n, int 
     for (int i = 0; i < n; ++i) {
         const yo_plan *p = plans[i];
         const int a = p->steps_done, b = std::min(p->steps_done + count, p->n_steps);
+        if (p->pulse && b > a) return true;
         for (int f = 0; f < p->n_freq; ++f) {
             const int ws = p->freqs[f].win_start, we = ws + p->freqs[f].win_len;
             if (a < we && b > ws) return true;
@@ -1220,12 +1333,13 @@ yo_status yo_finalize(yo_plan *p, int which, yo_stream stream)
     if (p->steps_done < p->n_steps) return fail(YO_ESTATE, "finalize before all steps ran");
     hipStream_t s = (hipStream_t)stream;
     int r0, r1;
-    set_rhs_range(p, which, r0, r1);
+    set_out_range(p, which, r0, r1);
     const size_t mt = std::max<size_t>(p->mon_total, 1);
     for (int r = r0; r < r1; ++r) {
-        const YoRhsD &R = p->hrhs[r];
-        HIPCHK(yo_launch_finalize(R.dft_box, 3 * p->bsz, R.ginv[0], R.ginv[1], R.ginv[2], R.ginv[3], s));
-        HIPCHK(yo_launch_finalize(R.dft_mon, mt, R.ginv[0], R.ginv[1], R.ginv[2], R.ginv[3], s));
+        const int f = r < p->n_fwd ? r / std::max(p->n_src, 1) : (r - p->n_fwd) / p->n_ports;
+        const float *m = p->fin.data() + 4 * f;
+        HIPCHK(yo_launch_finalize(box_of(p, r), 3 * p->bsz, m[0], m[1], m[2], m[3], s));
+        HIPCHK(yo_launch_finalize(mon_of(p, r), mt, m[0], m[1], m[2], m[3], s));
     }
     p->finalized = true;
     return YO_OK;
@@ -1253,7 +1367,7 @@ yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
                 const int r = f * p->n_src + sidx;
                 const yo_plane &pl = p->port_planes[q];
                 float2 *out = reinterpret_cast<float2 *>(alpha) + ((size_t)sidx * p->n_ports + q) * p->n_freq + f;
-                HIPCHK(yo_launch_alpha(p->hrhs[r].dft_mon + p->mon_off[q], w + p->port_off[q],
+                HIPCHK(yo_launch_alpha(mon_of(p, r) + p->mon_off[q], w + p->port_off[q],
                                        2 * pl.n0 * pl.n1, out, s));
             }
         }
@@ -1266,9 +1380,8 @@ static yo_status grad_common(yo_plan *p, const float *coef, float *gbox, float *
     YoGradArgs a;
     memset(&a, 0, sizeof a);
     for (int f = 0; f < p->n_freq; ++f) {
-        for (int si = 0; si < p->n_src; ++si) a.EF[f * p->n_src + si] = p->hrhs[f * p->n_src + si].dft_box;
-        for (int q = 0; q < p->n_ports; ++q)
-            a.EA[f * p->n_ports + q] = p->hrhs[p->n_fwd + f * p->n_ports + q].dft_box;
+        for (int si = 0; si < p->n_src; ++si) a.EF[f * p->n_src + si] = box_of(p, f * p->n_src + si);
+        for (int q = 0; q < p->n_ports; ++q) a.EA[f * p->n_ports + q] = box_of(p, p->n_fwd + f * p->n_ports + q);
         a.sinth[f] = (float)std::sin(0.5 * p->omega_dt[f]);
     }
     a.coef = reinterpret_cast<const float2 *>(coef);
@@ -1438,15 +1551,15 @@ yo_status yo_get_dft(const yo_plan *p, int rhs, int region, float *out, yo_strea
     if (!p || !out) return fail(YO_EINVAL, "null argument");
     if (rhs < 0 || rhs >= p->n_rhs) return fail(YO_EINVAL, "rhs out of range");
     if (region < 0 || region > p->n_ports) return fail(YO_EINVAL, "region out of range");
-    const YoRhsD &R = p->hrhs[rhs];
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
     const void *src;
     size_t bytes;
     if (region == 0) {
-        src = R.dft_box;
+        src = box_of(p, rhs);
         bytes = sizeof(float2) * 3 * p->bsz;
     } else {
         const yo_plane &pl = p->port_planes[region - 1];
-        src = R.dft_mon + p->mon_off[region - 1];
+        src = mon_of(p, rhs) + p->mon_off[region - 1];
         bytes = sizeof(float2) * 2 * pl.n0 * pl.n1;
     }
     HIPCHK(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
@@ -1456,7 +1569,7 @@ yo_status yo_get_dft(const yo_plan *p, int rhs, int region, float *out, yo_strea
 yo_status yo_set_fields(yo_plan *p, int rhs, const float *E, const float *H, yo_stream stream)
 {
     if (!p || !E || !H) return fail(YO_EINVAL, "null argument");
-    if (rhs < 0 || rhs >= p->n_rhs) return fail(YO_EINVAL, "rhs out of range");
+    if (rhs < 0 || rhs >= p->n_phys) return fail(YO_EINVAL, "rhs out of range");
     const yo_grid &g = p->grid;
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
@@ -1469,7 +1582,7 @@ yo_status yo_set_fields(yo_plan *p, int rhs, const float *E, const float *H, yo_
 yo_status yo_get_fields(const yo_plan *p, int rhs, float *E, float *H, yo_stream stream)
 {
     if (!p || !E || !H) return fail(YO_EINVAL, "null argument");
-    if (rhs < 0 || rhs >= p->n_rhs) return fail(YO_EINVAL, "rhs out of range");
+    if (rhs < 0 || rhs >= p->n_phys) return fail(YO_EINVAL, "rhs out of range");
     const yo_grid &g = p->grid;
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
@@ -1503,6 +1616,7 @@ yo_status yo_model_bytes(const yo_plan *p, int which, double *bytes, double *cel
     double win = 0.0;
     for (auto &f : p->freqs) win += (double)f.win_len / p->n_steps;
     win /= p->n_freq;
+    if (p->pulse) win = p->n_freq;   // every step, every frequency
     *bytes = R * (48.0 * N + 32.0 * pml + 48.0 * (double)p->bsz * win) + 12.0 * N;
     *cells = R * N;
     return YO_OK;

@@ -670,7 +670,8 @@ __device__ __forceinline__ bool aux_point(const YoAuxArgs &a, int &s, int &r, in
 }
 
 // Running DFT of E^n (called before step n): S += E^n exp(+i w n dt) on the
-// design box (3 components) and the port planes (2 tangential components).
+// design box (3 components) and the port planes (2 tangential components),
+// for each frequency the right-hand side accumulates.
 __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
 {
     int s, r, q;
@@ -681,18 +682,19 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
     const YoRhsD &R = P.rhs[r];
     const int w = step - R.win_start;
     if (w < 0 || w >= R.win_len) return;
-    const float4 st = R.steptab[step];
     const float *F = R.F[step & 1];
     const int bx = P.box[3], by = P.box[4], bz = P.box[5];
     const int bsz = bx * by * bz;
     float e;
     float2 *acc;
+    int fstride;
     if (q < 3 * bsz) {
         const int c = q / bsz, rem = q - c * bsz;
         const int bk = rem / (bx * by), rem2 = rem - bk * bx * by;
         const int bj = rem2 / bx, bi = rem2 - bj * bx;
         e = F[yo_off(c, P.box[0] + bi, P.box[1] + bj, P.box[2] + bk, P.ny, P.nxp, 6)];
         acc = R.dft_box + q;
+        fstride = R.box_fstride;
     } else {
         const int qm = q - 3 * bsz;
         int p = 0;
@@ -708,11 +710,15 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
         const int cz = sel3(pl.axis, pl.lo1 + b, pl.lo1 + b, pl.index);
         e = F[yo_off(c, cx, cy, cz, P.ny, P.nxp, 6)];
         acc = R.dft_mon + qm;
+        fstride = R.mon_fstride;
     }
-    float2 v = *acc;
-    v.x = fmaf(e, st.z, v.x);
-    v.y = fmaf(e, st.w, v.y);
-    *acc = v;
+    for (int f = 0; f < R.n_dft; ++f) {
+        const float4 st = R.dfttab[(size_t)f * P.n_steps + step];
+        float2 v = acc[(size_t)f * fstride];
+        v.x = fmaf(e, st.z, v.x);
+        v.y = fmaf(e, st.w, v.y);
+        acc[(size_t)f * fstride] = v;
+    }
 }
 
 // Soft current source of step n (called after step n): E^{n+1} -= kappa j^{n+1/2}

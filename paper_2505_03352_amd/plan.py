@@ -56,7 +56,9 @@ class Plan:
     """
 
     def __init__(self, grid: dict, design: dict, n_steps: int, freqs: Sequence[FreqSpec],
-                 src_planes: Sequence, port_planes: Sequence, device="cuda"):
+                 src_planes: Sequence, port_planes: Sequence, device="cuda", pulse=None):
+        """pulse: None, or (omega0 rad/s, sigma steps, t0 steps) for pulse
+        excitation (one run per source and per port for all wavelengths)."""
         self.device = torch.device(device)
         self.grid = dict(grid)
         self.design = dict(design)
@@ -90,6 +92,9 @@ class Plan:
             # Eqs. (4)-(6): before the workspace is sized and bound
             call("yo_set_morphology", self._h, self.morph_ops.encode(),
                  float(design["morph_d"]), float(design.get("morph_alpha", 20.0)))
+        self.pulse = tuple(pulse) if pulse is not None else None
+        if self.pulse is not None:
+            call("yo_set_pulse", self._h, float(pulse[0]), float(pulse[1]), float(pulse[2]))
         nb = ct.c_size_t()
         call("yo_workspace_bytes", self._h, ct.byref(nb))
         self.workspace_bytes = int(nb.value)
@@ -98,6 +103,9 @@ class Plan:
         call("yo_rhs_count", self._h, ct.byref(n))
         self.n_rhs = int(n.value)
         self.n_fwd = self.n_src * self.n_freq
+        # stepped right-hand sides (get_fields / set_fields numbering)
+        self.n_stepped = (self.n_src + self.n_ports) if self.pulse is not None else self.n_rhs
+        self.n_stepped_fwd = self.n_src if self.pulse is not None else self.n_fwd
         nz, ny, nx = grid["nz"], grid["ny"], grid["nx"]
         self.shape = (3, nz, ny, nx)
         self.box = (design["i0"] - 1, design["j0"] - 1, design["k_lo"] - 1, design["md"] + 2,
@@ -327,11 +335,12 @@ def freqs_of(dev) -> List[FreqSpec]:
 
 
 def plan_for(dev, device="cuda", stream=None, C=None, beta=None, set_design=True,
-             workspace: Optional[torch.Tensor] = None) -> Plan:
-    """Create, bind and fill a plan for a device description."""
+             workspace: Optional[torch.Tensor] = None, pulse=None) -> Plan:
+    """Create, bind and fill a plan for a device description.  pulse:
+    (omega0 rad/s, sigma steps, t0 steps) for pulse excitation."""
     grid, design = grid_design_of(dev)
     p = Plan(grid, design, dev.n_steps, freqs_of(dev), [m.plane for m in dev.sources],
-             [m.plane for m in dev.ports], device=device)
+             [m.plane for m in dev.ports], device=device, pulse=pulse)
     p.bind(workspace, stream)
     p.set_background(torch.as_tensor(dev.kappa_bg, dtype=torch.float32),
                      torch.as_tensor(dev.mask_hr, dtype=torch.float32), stream)

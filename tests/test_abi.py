@@ -4,6 +4,7 @@ import ctypes as ct
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2505_03352_amd import _abi
@@ -167,3 +168,29 @@ def test_morphology_arguments_and_workspace():
     q = _create(dev)
     assert q.morph_ops == "edde" and q.workspace_bytes > base
     q.close()
+
+
+def test_pulse_arguments_and_workspace():
+    dev = configs.realistic()
+    p = _create(dev)
+    base = p.workspace_bytes
+    L = _abi.lib()
+    h = p.handle
+    w0, sig, t0 = dev.pulse()
+    om = w0 / dev.dt()
+    assert L.yo_set_pulse(h, -om, sig, t0) == _abi.YO_EINVAL
+    assert L.yo_set_pulse(h, om, sig, -1.0) == _abi.YO_EINVAL
+    assert L.yo_set_pulse(h, 1.2 * np.pi / dev.dt(), sig, t0) == _abi.YO_EINVAL   # above pi / dt
+    assert L.yo_set_pulse(h, om, sig, t0) == _abi.YO_OK
+    nb = ct.c_size_t()
+    assert L.yo_workspace_bytes(h, ct.byref(nb)) == _abi.YO_OK
+    # 2 stepped right-hand sides instead of 6: fields and CPML memories shrink 3x
+    assert nb.value < 0.45 * base
+    n = ct.c_int()
+    assert L.yo_rhs_count(h, ct.byref(n)) == _abi.YO_OK and n.value == 6   # output numbering kept
+    b, c = ct.c_double(), ct.c_double()
+    assert L.yo_model_bytes(h, _abi.YO_BOTH, ct.byref(b), ct.byref(c)) == _abi.YO_OK
+    assert c.value == 2 * dev.cells
+    assert L.yo_set_pulse(h, 0.0, 0.0, 0.0) == _abi.YO_OK                 # off again
+    assert L.yo_workspace_bytes(h, ct.byref(nb)) == _abi.YO_OK and nb.value == base
+    p.close()

@@ -1,0 +1,101 @@
+"""Pulse excitation (paper Sec. 2's Fourier-transform-of-transients route) on
+the GPU against the FP64 oracle's pulse route, through the C ABI: the
+phasors of every wavelength from one run per source and per port, alpha and
+the Eq. (9) gradient; and the GPU's pulse phasors against its own
+time-harmonic ones.  Tolerances are those of the time-harmonic path (DFT
+fields and alpha <= 1e-4 relative, gradients <= 1e-3 relative L2)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint
+from workloads import configs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_built")]
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_available():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_03352_amd import _abi
+    _abi.lib()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def pulse_args(dev):
+    w0, sig, t0 = dev.pulse()
+    return (w0 / dev.dt(), sig, t0), adjoint.Pulse(w0, sig, t0, dev.n_steps, tail=dev.n_steps // 8)
+
+
+@pytest.mark.parametrize("name", ["micro_demux", "tiny"])
+def test_pulse_phasors_alpha_gradient_match_oracle(name):
+    from paper_2505_03352_amd.plan import plan_for
+    if name == "micro_demux":
+        dev = configs.micro_demux(n_steps=2600)
+        dev.C = np.random.default_rng(41).uniform(0.3, 0.7, dev.C.shape)
+        T = np.array([[[1.0, 0.0], [0.0, 1.0]]])
+    else:
+        dev = configs.tiny(n_steps=2400)
+        T = np.array([[[0.8]]])
+    gpu_pulse, P = pulse_args(dev)
+    say(f"pulse {name}: oracle (sigma {P.sigma:.1f}, t0 {P.t0:.1f}, {dev.n_steps} steps)")
+    ref = adjoint.forward_adjoint_pulse(dev, P)
+    cref = 2.0 * (np.abs(ref.alpha) ** 2 - T) * np.conj(ref.alpha)
+    gref = adjoint.grad_C(dev, ref, cref)
+    say(f"pulse {name}: GPU")
+    p = plan_for(dev, pulse=gpu_pulse)
+    assert p.n_stepped == len(dev.sources) + len(dev.ports)
+    p.run(3)
+    ns, npo, nf = len(dev.sources), len(dev.ports), dev.n_freq
+    worst = 0.0
+    for f in range(nf):
+        for s in range(ns):
+            e = rel_l2(p.get_dft(f * ns + s).cpu().numpy(), ref.fwd[s][f].box)
+            worst = max(worst, e)
+        for q in range(npo):
+            e = rel_l2(p.get_dft(ns * nf + f * npo + q).cpu().numpy(), ref.adj[q][f].box)
+            worst = max(worst, e)
+    a = p.alpha().cpu().numpy()
+    ea = np.abs(a - ref.alpha).max() / np.abs(ref.alpha).max()
+    coef = torch.as_tensor(cref, dtype=torch.complex64, device="cuda")
+    g = p.gradient(coef).cpu().numpy()
+    eg = rel_l2(g, gref)
+    p.close()
+    say(f"  DFT worst rel L2 {worst:.2e}, alpha err {ea:.2e}, gradient rel L2 {eg:.2e}, "
+        f"tail residual {max(r.resid for r in ref.fwd[0]):.1e}")
+    assert worst < 1e-4
+    assert ea < 1e-4
+    assert eg < 1e-3
+
+
+def test_pulse_and_time_harmonic_runs_agree_on_the_gpu():
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro_demux(n_steps=2600)
+    gpu_pulse, _ = pulse_args(dev)
+    p = plan_for(dev, pulse=gpu_pulse)
+    p.run(3)
+    ap = p.alpha().cpu().numpy()
+    bp = [p.get_dft(r).cpu().numpy() for r in range(p.n_rhs)]
+    p.close()
+    dh = configs.micro_demux(n_steps=4000)
+    q = plan_for(dh)
+    q.run(3)
+    ah = q.alpha().cpu().numpy()
+    bh = [q.get_dft(r).cpu().numpy() for r in range(q.n_rhs)]
+    q.close()
+    e = max(rel_l2(x, y) for x, y in zip(bp, bh))
+    say(f"pulse vs time-harmonic on the GPU: DFT worst rel L2 {e:.2e}, "
+        f"alpha {np.abs(ap - ah).max() / np.abs(ah).max():.2e}")
+    assert e < 1e-4
+    assert np.abs(ap - ah).max() < 1e-4 * np.abs(ah).max()

@@ -101,6 +101,21 @@ class Device:
     def ramp_steps(self, lam: float) -> float:
         return self.ramp_periods * self.period_steps(lam)
 
+    def pulse(self, k: float = 1.5, m: float = 4.5, single_periods: float = 3.0):
+        """Pulse excitation covering the device's wavelengths, in steps:
+        (carrier omega dt, sigma, t0).  The carrier sits mid-band; the
+        Gaussian's spectral width 1/sigma puts the band edges k widths away
+        (one wavelength: sigma = `single_periods` periods); the centre is m
+        sigma after the start."""
+        w = [self.omega_dt(lam) for lam in self.wavelengths]
+        w0 = 0.5 * (min(w) + max(w))
+        half = 0.5 * (max(w) - min(w))
+        sigma = k / half if half > 0 else single_periods * 2.0 * np.pi / w0
+        return w0, sigma, m * sigma
+
+    def dt(self) -> float:
+        return self.courant * self.dx / 299792458.0
+
     def window(self, lam: float):
         wl = int(round(self.window_periods * self.period_steps(lam)))
         wl = max(2, min(wl, self.n_steps))
