@@ -99,8 +99,9 @@ def main():
                          "forms against one-at-a-time solves (their own JSON line)")
     ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
     ap.add_argument("--iters", type=int, default=5, help="optimize: optimizer iterations")
-    ap.add_argument("--pulse-steps", type=int, default=10000,
-                    help="broadband: steps of the pulse runs")
+    ap.add_argument("--pulse", action="store_true", help="optimize: gradients from pulse runs")
+    ap.add_argument("--pulse-steps", type=int, default=None,
+                    help="steps of the pulse runs (broadband: 10000, optimize: 12000)")
     ap.add_argument("--pulse-k", type=float, default=1.0,
                     help="broadband: band edges in spectral widths of the pulse")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
@@ -359,7 +360,7 @@ def bench_broadband(args):
     s_h, a_h, g_h = timed(ph, args.steps)
     ph.close()
     log(f"time-harmonic: {s_h * 1e3:.1f} ms per gradient ({ph.n_rhs} runs x {dev.n_steps} steps)")
-    dp = configs.realistic(n_steps=args.pulse_steps)
+    dp = configs.realistic(n_steps=args.pulse_steps or 10000)
     w0, sig, t0 = dp.pulse(k=args.pulse_k)
     pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0))
     tp = autotune.tune(pp, YO_BOTH, use_cache=False)
@@ -387,7 +388,10 @@ def bench_broadband(args):
 def bench_optimize(args):
     """The Sec. 4 optimizer loop on the two-wavelength demultiplexer analogue
     (1.30 um to output 1, 1.55 um to output 2): iterations per hour, with
-    the objective, grey fraction and projection strength of each iteration."""
+    the objective, grey fraction and projection strength of each iteration.
+    With --pulse the gradients come from pulse runs (one per source and per
+    port for both wavelengths, --pulse-steps steps); one gradient of each
+    kind at the same controls is compared first."""
     import numpy as np
     import torch
     from paper_2505_03352_amd import YO_BOTH, autotune, optimize
@@ -395,29 +399,61 @@ def bench_optimize(args):
     from workloads import configs
     torch.cuda.set_device(0)
     dev = configs.demux()
+    T = np.array([[[1.0, 0.0], [0.0, 1.0]]])     # [source][port][wavelength]: demux, no crosstalk
     log(f"demux: {dev.nx}x{dev.ny}x{dev.nz}, {dev.n_steps} steps, {dev.mc}x{dev.nc} controls")
     plan = plan_for(dev, device="cuda:0")
     tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
-    T = np.array([[[1.0, 0.0], [0.0, 1.0]]])     # [source][port][wavelength]: demux, no crosstalk
+    extra = {}
+    run_dev, how = dev, f"1 forward + 2 adjoint per wavelength, {dev.n_steps} steps"
+    if args.pulse:
+        Tt = torch.as_tensor(T, dtype=torch.float32, device="cuda:0")
+        Cc = torch.as_tensor(np.random.default_rng(3).uniform(0.3, 0.7, dev.C.shape),
+                             dtype=torch.float32, device="cuda:0")
+
+        def one(p):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            p.set_design(Cc, dev.beta)
+            p.run(YO_BOTH, chunk=args.chunk)
+            a = p.alpha()
+            g = p.gradient(2.0 * (a.abs() ** 2 - Tt) * torch.conj(a))
+            torch.cuda.synchronize()
+            return time.perf_counter() - t, a.cpu().numpy(), g.cpu().numpy()
+
+        s_h, a_h, g_h = one(plan)
+        plan.close()
+        run_dev = configs.demux(n_steps=args.pulse_steps or 12000)
+        w0, sig, t0 = run_dev.pulse(k=args.pulse_k)
+        plan = plan_for(run_dev, device="cuda:0", pulse=(w0 / run_dev.dt(), sig, t0))
+        tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
+        s_p, a_p, g_p = one(plan)
+        ea = float(np.abs(a_p - a_h).max() / np.abs(a_h).max())
+        eg = float(np.linalg.norm(g_p - g_h) / np.linalg.norm(g_h))
+        log(f"one gradient: time-harmonic {s_h:.2f} s, pulse {s_p:.2f} s; alpha max diff {ea:.2e}, "
+            f"gradient rel L2 diff {eg:.2e}")
+        how = (f"pulse runs: 1 forward + 2 adjoint for both wavelengths, {run_dev.n_steps} steps "
+               f"(sigma {sig:.0f}, t0 {t0:.0f})")
+        extra = {"time_harmonic_s_per_gradient": round(s_h, 3), "pulse_s_per_gradient": round(s_p, 3),
+                 "alpha_max_rel_diff_vs_time_harmonic": ea, "gradient_rel_l2_diff_vs_time_harmonic": eg}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     C, h = optimize.optimize(plan, dev.C, T, n_iter=args.iters, iters_total=100, chunk=args.chunk)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    cells = plan.n_rhs * dev.cells * dev.n_steps * args.iters
+    cells = plan.n_stepped * run_dev.cells * run_dev.n_steps * args.iters
     for i, (F, u, b) in enumerate(zip(h.F, h.u, h.beta)):
         log(f"iter {i}: F {F:.5f} u {u:.4f} beta {b:.2f} ({h.seconds[i]:.2f} s)")
     plan.close()
+    extra.update({"gcell_updates_per_s": round(cells / dt / 1e9, 3),
+                  "F": [round(x, 6) for x in h.F], "unbinarity": [round(x, 5) for x in h.u],
+                  "beta": [round(x, 3) for x in h.beta]})
     _line("optimizer iterations/hour (demux analogue)", 3600.0 * args.iters / dt, "iterations/h",
           dt / args.iters * 1e3, args,
           {"workload": "demux analogue: 430x450x64 cells at 25 nm (CPML 8), 210x210-pixel design, "
-                       "36x36 controls from C = 1/2, 1.30/1.55 um, 1 forward + 2 adjoint per "
-                       f"wavelength, {dev.n_steps} steps; Adam lr 1e-3, beta_min 10, "
-                       "gamma 0.95, u0 0.01, schedule length 100",
+                       f"36x36 controls from C = 1/2, 1.30/1.55 um, {how}; Adam lr 1e-3, "
+                       "beta_min 10, gamma 0.95, u0 0.01, schedule length 100",
            "iterations": args.iters, "tiling": [tuned["rows"], tuned["zchunk"], tuned["flags"]]},
-          {"gcell_updates_per_s": round(cells / dt / 1e9, 3),
-           "F": [round(x, 6) for x in h.F], "unbinarity": [round(x, 5) for x in h.u],
-           "beta": [round(x, 3) for x in h.beta]})
+          extra, steps=args.iters)
 
 
 if __name__ == "__main__":
