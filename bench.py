@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--pulse", action="store_true", help="optimize: gradients from pulse runs")
     ap.add_argument("--pulse-steps", type=int, default=None,
                     help="steps of the pulse runs (broadband: 10000, optimize: 12000)")
+    ap.add_argument("--device", choices=("realistic", "multiport"), default="realistic",
+                    help="broadband: the device (multiport: 600x400x120, 5 wavelengths, 4 ports)")
     ap.add_argument("--pulse-k", type=float, default=1.0,
                     help="broadband: band edges in spectral widths of the pulse")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
@@ -337,17 +339,33 @@ def bench_broadband(args):
     from paper_2505_03352_amd.plan import plan_for
     from workloads import configs
     torch.cuda.set_device(0)
-    dev = configs.realistic()
+    make = configs.multiport if args.device == "multiport" else configs.realistic
+    dev = make()
     C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
 
+    from paper_2505_03352_amd.plan import advance_many
+
     def grad(plan):
+        # the run in pieces of 2500 steps with a progress line after each
+        # (the same launches as one yo_run: reset, chunked graph replays,
+        # finalize)
         plan.set_design(C, dev.beta)
-        plan.run(YO_BOTH, chunk=args.chunk, use_graph=not args.eager)
+        plan.reset(YO_BOTH)
+        done = 0
+        while done < plan.n_steps:
+            k = min(2500, plan.n_steps - done)
+            advance_many([plan], [YO_BOTH], k, chunk=args.chunk, use_graph=not args.eager)
+            done += k
+            if args.device == "multiport":
+                torch.cuda.synchronize()
+                log(f"  {done}/{plan.n_steps} steps")
+        plan.finalize(YO_BOTH)
         a = plan.alpha()
         return a, plan.gradient(torch.conj(a))
 
     def timed(plan, n):
-        grad(plan)
+        if args.warmup > 0:
+            grad(plan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(n):
@@ -360,7 +378,8 @@ def bench_broadband(args):
     s_h, a_h, g_h = timed(ph, args.steps)
     ph.close()
     log(f"time-harmonic: {s_h * 1e3:.1f} ms per gradient ({ph.n_rhs} runs x {dev.n_steps} steps)")
-    dp = configs.realistic(n_steps=args.pulse_steps or 10000)
+    n_h = ph.n_rhs
+    dp = make(n_steps=args.pulse_steps or (10000 if args.device == "realistic" else 20000))
     w0, sig, t0 = dp.pulse(k=args.pulse_k)
     pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0))
     tp = autotune.tune(pp, YO_BOTH, use_cache=False)
@@ -371,18 +390,24 @@ def bench_broadband(args):
     log(f"pulse: {s_p * 1e3:.1f} ms per gradient ({pp.n_stepped} runs x {dp.n_steps} steps, sigma "
         f"{sig:.0f}, t0 {t0:.0f}); alpha max diff {ea:.2e}, gradient rel L2 diff {eg:.2e}")
     pp.close()
-    _line("adjoint gradients/hour, 3 wavelengths (pulse excitation)", 3600.0 / s_p, "gradients/h",
-          s_p * 1e3, args,
-          {"workload": "realistic: 320x240x96 cells at 20 nm (CPML 8), 100x100 design/controls, "
-                       "r=3, beta=8, wavelengths 1.50/1.55/1.60 um; pulse runs (1 forward + 1 "
-                       f"adjoint, {dp.n_steps} steps, carrier mid-band, sigma {sig:.0f} steps, "
-                       f"t0 {t0:.0f}) against time-harmonic runs (3 x (1 + 1), {dev.n_steps} steps)",
+    if args.device == "multiport":
+        what = ("multi-port: 600x400x120 cells at 20 nm (CPML 8), 250x150 design/controls, r=4, "
+                "beta=16, 5 wavelengths 1.500-1.600 um, 4 output ports")
+    else:
+        what = ("realistic: 320x240x96 cells at 20 nm (CPML 8), 100x100 design/controls, r=3, "
+                "beta=8, wavelengths 1.50/1.55/1.60 um")
+    _line(f"adjoint gradients/hour, {dev.n_freq} wavelengths (pulse excitation)", 3600.0 / s_p,
+          "gradients/h", s_p * 1e3, args,
+          {"workload": f"{what}; pulse runs (1 forward + {len(dev.ports)} adjoint, {dp.n_steps} "
+                       f"steps, carrier mid-band, sigma {sig:.0f} steps, t0 {t0:.0f}) against "
+                       f"time-harmonic runs ({n_h} runs, {dev.n_steps} steps)",
            "tiling_pulse": [tp["rows"], tp["zchunk"], tp["flags"]],
            "tiling_harmonic": [th["rows"], th["zchunk"], th["flags"]]},
           {"gcell_updates_per_s": round(cells / s_p / 1e9, 3),
            "time_harmonic_gradients_per_hour": round(3600.0 / s_h, 1),
            "speedup_vs_time_harmonic": round(s_h / s_p, 3),
-           "alpha_max_rel_diff": ea, "gradient_rel_l2_diff": eg}, steps=args.steps, warmup=1)
+           "alpha_max_rel_diff": ea, "gradient_rel_l2_diff": eg}, steps=args.steps,
+          warmup=min(args.warmup, 1))
 
 
 def bench_optimize(args):
