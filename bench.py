@@ -101,11 +101,13 @@ def main():
     ap.add_argument("--iters", type=int, default=5, help="optimize: optimizer iterations")
     ap.add_argument("--pulse", action="store_true", help="optimize: gradients from pulse runs")
     ap.add_argument("--pulse-steps", type=int, default=None,
-                    help="steps of the pulse runs (broadband: 10000, optimize: 12000)")
+                    help="steps of the pulse runs (broadband: 7000 realistic, 12000 multi-port; "
+                         "optimize: 12000)")
     ap.add_argument("--device", choices=("realistic", "multiport"), default="realistic",
                     help="broadband: the device (multiport: 600x400x120, 5 wavelengths, 4 ports)")
-    ap.add_argument("--pulse-k", type=float, default=1.0,
-                    help="broadband: band edges in spectral widths of the pulse")
+    ap.add_argument("--pulse-k", type=float, default=None,
+                    help="band edges in spectral widths of the pulse (broadband: 0.4, "
+                         "optimize: 1.0)")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: arrival rate, requests/s")
     ap.add_argument("--max-cells", type=float, default=4.5e7,
@@ -379,8 +381,8 @@ def bench_broadband(args):
     ph.close()
     log(f"time-harmonic: {s_h * 1e3:.1f} ms per gradient ({ph.n_rhs} runs x {dev.n_steps} steps)")
     n_h = ph.n_rhs
-    dp = make(n_steps=args.pulse_steps or (10000 if args.device == "realistic" else 20000))
-    w0, sig, t0 = dp.pulse(k=args.pulse_k)
+    dp = make(n_steps=args.pulse_steps or (7000 if args.device == "realistic" else 12000))
+    w0, sig, t0 = dp.pulse(k=0.4 if args.pulse_k is None else args.pulse_k)
     pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0))
     tp = autotune.tune(pp, YO_BOTH, use_cache=False)
     s_p, a_p, g_p = timed(pp, args.steps)
@@ -448,7 +450,7 @@ def bench_optimize(args):
         s_h, a_h, g_h = one(plan)
         plan.close()
         run_dev = configs.demux(n_steps=args.pulse_steps or 12000)
-        w0, sig, t0 = run_dev.pulse(k=args.pulse_k)
+        w0, sig, t0 = run_dev.pulse(k=1.0 if args.pulse_k is None else args.pulse_k)
         plan = plan_for(run_dev, device="cuda:0", pulse=(w0 / run_dev.dt(), sig, t0))
         tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
         s_p, a_p, g_p = one(plan)
