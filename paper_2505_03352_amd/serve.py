@@ -23,6 +23,11 @@ Each request keeps its own fields, counters and results, and a right-hand
 side's update does not depend on what else shares the launch, so a result
 is the same alone and in a mix.
 
+A request with several wavelengths may instead be evaluated from pulse
+runs (one per source and per port for all its wavelengths, Sec. 2's
+Fourier-transform route) when that takes fewer cell-updates than one
+time-harmonic run per wavelength (`GpuExecutor(pulse_multi=True)`).
+
 The scheduler is independent of the GPU: it drives an executor (prepare,
 start, advance, finish, ready, collect, release) and a clock, so the
 admission logic runs on the CPU with a simulated executor in the tests.
@@ -247,6 +252,27 @@ class _Done:
 
 
 # ---------------------------------------------------------------- GPU executor
+def pulse_plan(dev, periods: float = 2.0, m: float = 4.5, frac: float = 1.0, tail: int = 1000):
+    """Pulse excitation for a multi-wavelength device, or None when one
+    time-harmonic run per wavelength is cheaper.  The carrier sits mid-band,
+    sigma is `periods` carrier periods (its spectrum stays within a few per
+    cent of flat over a 1.50-1.60 um band), the centre m sigma from the
+    start; the run lasts `frac` of the time-harmonic run, at least the pulse
+    (2 m sigma) plus `tail` steps for the field to die away.  Returns
+    (omega0 rad/s, sigma, t0, n_steps) with times in steps."""
+    if dev.n_freq < 2:
+        return None
+    w = [dev.omega_dt(lam) for lam in dev.wavelengths]
+    w0 = 0.5 * (min(w) + max(w))
+    sigma = periods * 2.0 * np.pi / w0
+    t0 = m * sigma
+    n = int(max(frac * dev.n_steps, 2 * t0 + tail))
+    if n >= dev.n_freq * dev.n_steps:
+        return None
+    dt = dev.courant * dev.dx / 299792458.0
+    return w0 / dt, sigma, t0, n
+
+
 class GpuExecutor:
     """Runs jobs through the library.  Set-up (workspace, background,
     modes, design) is enqueued on a set-up stream so it overlaps the
@@ -256,7 +282,7 @@ class GpuExecutor:
     progress."""
 
     def __init__(self, build: Callable, device="cuda:0", tiling=(4, 16, 73), use_graph=False,
-                 chunk: int = 100):
+                 chunk: int = 100, pulse_multi: bool = False):
         import torch
         from . import _abi  # noqa: F401  (fails loudly without the library)
         self.torch = torch
@@ -265,6 +291,7 @@ class GpuExecutor:
         self.tiling = tiling
         self.use_graph = use_graph
         self.chunk = chunk
+        self.pulse_multi = pulse_multi
         self.compute = torch.cuda.Stream(self.device)
         self.setup = torch.cuda.Stream(self.device)
         self._inflight = collections.deque()
@@ -283,9 +310,13 @@ class GpuExecutor:
     def prepare(self, req: Request) -> Job:
         from .plan import Plan, freqs_of, grid_design_of
         dev = self.build(req.payload)
+        pulse = pulse_plan(dev) if self.pulse_multi else None
+        if pulse is not None:
+            dev.n_steps = pulse[3]
         grid, design = grid_design_of(dev)
         plan = Plan(grid, design, dev.n_steps, freqs_of(dev), [m.plane for m in dev.sources],
-                    [m.plane for m in dev.ports], device=self.device)
+                    [m.plane for m in dev.ports], device=self.device,
+                    pulse=None if pulse is None else pulse[:3])
         plan.set_tiling(*self.tiling)
         host = dict(kappa=self.torch.as_tensor(dev.kappa_bg, dtype=self.torch.float32),
                     mask=self.torch.as_tensor(dev.mask_hr, dtype=self.torch.float32),
@@ -295,7 +326,7 @@ class GpuExecutor:
         extra = 4 * (3 * dev.cells + plan.canvas_shape[0] * plan.canvas_shape[1]
                      + 2 * dev.mc * dev.nc) + 8 * plan.n_rhs + 4096
         job = Job(req, plan.workspace_bytes + 256 + extra, dev.n_steps)
-        job.state = dict(plan=plan, dev=dev, host=host, cells=dev.cells * plan.n_rhs)
+        job.state = dict(plan=plan, dev=dev, host=host, cells=dev.cells * plan.n_stepped)
         return job
 
     def start(self, job: Job):

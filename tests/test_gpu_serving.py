@@ -52,14 +52,14 @@ def test_batch_solve_matches_individual_runs():
         p.close()
 
 
-def _serve(payloads, arrivals, max_slots, chunk=100):
+def _serve(payloads, arrivals, max_slots, chunk=100, pulse=False):
     from paper_2505_03352_amd.serve import GpuExecutor, Request, Scheduler
 
     def build(p):
         i, cls, lams, steps = p
         return configs.serving_request(i, cls, lams, n_steps=steps)
 
-    ex = GpuExecutor(build, tiling=(4, 16, 1), chunk=chunk)
+    ex = GpuExecutor(build, tiling=(4, 16, 1), chunk=chunk, pulse_multi=pulse)
     reqs = [Request(i, t, p) for i, (t, p) in enumerate(zip(arrivals, payloads))]
     st = Scheduler(ex, max_slots=max_slots, chunk=chunk, prep_workers=2).run(reqs)
     torch.cuda.synchronize()
@@ -82,3 +82,56 @@ def test_served_results_equal_alone_results():
         assert np.array_equal(a.result["grad"], m.result["grad"])
     say(f"alone makespan {st1.makespan_s:.3f} s, mixed {st2.makespan_s:.3f} s, "
         f"p50 {st2.p50_s:.3f} p99 {st2.p99_s:.3f}")
+
+
+def test_served_pulse_results_equal_alone_results():
+    """With pulse runs for multi-wavelength requests: the 3-wavelength
+    request runs as pulses, the others time-harmonic; each result is the
+    same alone and in the mix."""
+    from paper_2505_03352_amd.serve import pulse_plan
+    payloads = [(0, "small", [1.55 * UM], 900),
+                (1, "small", [1.50 * UM, 1.55 * UM, 1.60 * UM], 2000),
+                (2, "small", [1.50 * UM], 1000)]
+    assert pulse_plan(configs.serving_request(*payloads[1])) is not None
+    assert pulse_plan(configs.serving_request(*payloads[0])) is None
+    alone, st1 = _serve(payloads, [0.0] * 3, max_slots=1, pulse=True)
+    mixed, st2 = _serve(payloads, [0.0, 0.01, 0.02], max_slots=3, chunk=50, pulse=True)
+    assert st1.n_done == 3 and st2.n_done == 3 and st2.max_active >= 2
+    for a, m in zip(alone, mixed):
+        assert np.abs(a.result["alpha"]).max() > 0
+        assert np.array_equal(a.result["alpha"], m.result["alpha"])
+        assert np.array_equal(a.result["grad"], m.result["grad"])
+
+
+@pytest.mark.parametrize("i", [0, 2, 8])
+def test_pulse_requests_match_time_harmonic(i):
+    """The serving trace's multi-wavelength requests evaluated from pulse
+    runs (the executor's choice of pulse and run length) against one
+    time-harmonic run per wavelength: gradients within the gradient
+    tolerance (1e-3 relative L2), alpha within 1e-3 of its largest entry."""
+    from paper_2505_03352_amd.plan import plan_for
+    from paper_2505_03352_amd.serve import pulse_plan
+    _, cls, lams = configs.serving_trace()[i]
+    dev = configs.serving_request(i, cls, lams)
+    pp = pulse_plan(dev)
+    assert pp is not None
+    say(f"request {i} ({cls}, {len(lams)} wavelengths): time-harmonic {dev.n_steps} steps")
+    ph = plan_for(dev)
+    ph.run(3)
+    ah = ph.alpha()
+    gh = ph.gradient(torch.conj(ah)).cpu().numpy()
+    ah = ah.cpu().numpy()
+    ph.close()
+    dp = configs.serving_request(i, cls, lams, n_steps=pp[3])
+    say(f"  pulse {pp[3]} steps (sigma {pp[1]:.0f}, t0 {pp[2]:.0f})")
+    q = plan_for(dp, pulse=pp[:3])
+    q.run(3)
+    ap = q.alpha()
+    gp = q.gradient(torch.conj(ap)).cpu().numpy()
+    ap = ap.cpu().numpy()
+    q.close()
+    ea = np.abs(ap - ah).max() / np.abs(ah).max()
+    eg = np.linalg.norm(gp - gh) / np.linalg.norm(gh)
+    say(f"  alpha max diff {ea:.2e}, gradient rel L2 diff {eg:.2e}")
+    assert ea < 1e-3
+    assert eg < 1e-3
