@@ -199,7 +199,8 @@ yo_status yo_finalize(yo_plan *plan, int which, yo_stream stream);
 /* Step several plans together: every launch covers every tile of every
  * plan's selected right-hand sides; each plan keeps its own step counter and
  * stops at its own n_steps.  Graph mode captures `chunk` launches once per
- * distinct plan list and relaunches them. */
+ * distinct plan list and relaunches them.  The plans must share their
+ * yo_set_tiling flags except 1 and 128 (YO_EINVAL otherwise). */
 yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n_plans, int n_steps,
                           int chunk, int use_graph, yo_stream stream);
 

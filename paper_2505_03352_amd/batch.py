@@ -19,9 +19,10 @@ from ._abi import YO_BOTH
 from .plan import Plan, advance_many
 
 
-# x-strips, CPML shell with per-class code and no prefetch: the
-# split the autotuner picks on the realistic device
-DEFAULT_FLAGS = 73
+# x-shell strips that leave whole interior strips, CPML shell with
+# per-class code and no prefetch: the split the autotuner picks on the
+# realistic device
+DEFAULT_FLAGS = 200
 
 
 def shared_tiling(plans: Sequence[Plan], rows: int = 4, flags: int = DEFAULT_FLAGS,

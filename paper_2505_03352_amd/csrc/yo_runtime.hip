@@ -1184,7 +1184,7 @@ static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, 
 // Launch `n_launch` steps (k_offset 0..n_launch-1) of a plan list, then add
 // n_launch to every plan's counter.  Per step: DFT of E^n (when `with_dft`),
 // the step launches (interior, CPML shell), the source.  Plans must share
-// every tiling flag but the x-strip one.
+// every tiling flag but the x-split ones.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
                               bool with_dft, hipStream_t s, yo_plan *timed = nullptr)
 {
@@ -1247,8 +1247,11 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         yo_plan *p = plans[i];
         if (!p || !p->ws) return fail(YO_EWORKSPACE, "plan %d has no workspace", i);
         if (which[i] != p->active) return fail(YO_ESTATE, "plan %d: which differs from its reset", i);
-        if ((p->tflags & ~YO_TILE_XSTRIPS) != (plans[0]->tflags & ~YO_TILE_XSTRIPS))
-            return fail(YO_EINVAL, "plans in one call must share the tiling flags (but the x-strip one)");
+        // the x-split flags only shape each plan's own tile table; the others
+        // pick the kernel variant, which one launch shares
+        const int own = YO_TILE_XSTRIPS | YO_TILE_XFULL;
+        if ((p->tflags & ~own) != (plans[0]->tflags & ~own))
+            return fail(YO_EINVAL, "plans in one call must share the tiling flags (but the x-split ones)");
         for (int j = 0; j < i; ++j)
             if (plans[j] == p) return fail(YO_EINVAL, "plan listed twice");
     }

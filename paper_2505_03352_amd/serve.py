@@ -281,7 +281,7 @@ class GpuExecutor:
     are in flight, which keeps admission decisions close to the GPU's
     progress."""
 
-    def __init__(self, build: Callable, device="cuda:0", tiling=(4, 16, 73), use_graph=False,
+    def __init__(self, build: Callable, device="cuda:0", tiling=(4, 16, 200), use_graph=False,
                  chunk: int = 100, pulse_multi: bool = False):
         import torch
         from . import _abi  # noqa: F401  (fails loudly without the library)
