@@ -361,7 +361,7 @@ def test_realistic_full_size_short_run_fields_match_oracle():
     dev = configs.realistic(n_steps=150, wavelengths=[1.55e-6])
     say("realistic full-size fields: GPU")
     p = plan_for(dev)
-    p.set_tiling(4, 16, 73)
+    p.set_tiling(4, 16, 200)
     p.reset(1)
     p.advance(1, 150)
     E, H = p.get_fields(0)
@@ -390,7 +390,7 @@ def test_multiport_full_size_short_run_fields_match_oracle():
     dev = configs.multiport(n_steps=100, wavelengths=[1.55e-6])
     say("multi-port full-size fields: GPU")
     p = plan_for(dev)
-    p.set_tiling(4, 16, 73)
+    p.set_tiling(4, 16, 200)
     p.reset(3)
     p.advance(3, 100)
     E, H = p.get_fields(0)

@@ -99,3 +99,28 @@ def test_pulse_and_time_harmonic_runs_agree_on_the_gpu():
         f"alpha {np.abs(ap - ah).max() / np.abs(ah).max():.2e}")
     assert e < 1e-4
     assert np.abs(ap - ah).max() < 1e-4 * np.abs(ah).max()
+
+
+def test_realistic_full_size_pulse_dft_matches_oracle():
+    """The 320x240x96 grid with its three wavelengths under a pulse, in the
+    broadband benchmark's launch configuration: 500 steps of the forward run
+    (pulse centred at step 250, so the front crosses the design box), every box phasor
+    of every wavelength against the oracle."""
+    from paper_2505_03352_amd.plan import plan_for
+    from oracle import ports
+    dev = configs.realistic(n_steps=500)
+    w0, sig, _ = dev.pulse(k=0.4)
+    t0 = 250.0
+    say("realistic full-size pulse: GPU")
+    p = plan_for(dev, pulse=(w0 / dev.dt(), sig, t0))
+    p.set_tiling(4, 8, 192)
+    p.run(1)
+    boxes = [p.get_dft(f * len(dev.sources)).cpu().numpy() for f in range(dev.n_freq)]
+    kap = p.get_kappa().cpu().numpy().astype(np.float64)
+    p.close()
+    say("realistic full-size pulse: oracle")
+    P = adjoint.Pulse(w0, sig, t0, dev.n_steps, tail=dev.n_steps // 8)
+    ref = adjoint.solve_pulse(dev, kap, dev.sources[0].plane, ports.source_current(dev.sources[0].h), P)
+    eb = [rel_l2(b, r.box) for b, r in zip(boxes, ref)]
+    say(f"  box phasors rel L2 per wavelength {', '.join(f'{e:.2e}' for e in eb)}")
+    assert max(eb) < 1e-4
