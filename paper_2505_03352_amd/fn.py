@@ -12,7 +12,8 @@ sum 2 Re(coef dalpha/dC) = dL/dC.
 Nothing is checkpointed: the time-harmonic adjoint needs no time history,
 only the steady-state phasors in the design box, which stay resident in the
 plan's workspace between forward and backward (about 3 MB per right-hand
-side for the 100x100 design).  A plan serves one live graph at a time; a
+side for the 100x100 design).  A plan under pulse excitation works the same
+way: its runs accumulate every wavelength's phasors as they go.  A plan serves one live graph at a time; a
 second forward on the same plan before backward is detected and rejected.
 """
 from __future__ import annotations

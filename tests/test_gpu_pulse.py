@@ -124,3 +124,27 @@ def test_realistic_full_size_pulse_dft_matches_oracle():
     eb = [rel_l2(b, r.box) for b, r in zip(boxes, ref)]
     say(f"  box phasors rel L2 per wavelength {', '.join(f'{e:.2e}' for e in eb)}")
     assert max(eb) < 1e-4
+
+
+def test_autograd_function_with_pulse_plan_matches_oracle():
+    """The torch.autograd.Function over a pulse plan: C.grad of the Eq. (9)
+    objective against the oracle's pulse-route gradient."""
+    from paper_2505_03352_amd import fn
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro_demux(n_steps=2600)
+    dev.C = np.random.default_rng(42).uniform(0.3, 0.7, dev.C.shape)
+    gpu_pulse, P = pulse_args(dev)
+    T = np.array([[[1.0, 0.0], [0.0, 1.0]]])
+    ref = adjoint.forward_adjoint_pulse(dev, P)
+    cref = 2.0 * (np.abs(ref.alpha) ** 2 - T) * np.conj(ref.alpha)
+    gref = adjoint.grad_C(dev, ref, cref)
+    p = plan_for(dev, pulse=gpu_pulse)
+    C = torch.tensor(dev.C, dtype=torch.float32, device="cuda", requires_grad=True)
+    a = fn.modal_coefficients(C, p, dev.beta)
+    loss = fn.transmission_objective(a, torch.as_tensor(T, dtype=torch.float32, device="cuda"))
+    loss.backward()
+    g = C.grad.cpu().numpy()
+    p.close()
+    eg = rel_l2(g, gref)
+    say(f"autograd over a pulse plan: dL/dC rel L2 {eg:.2e}")
+    assert eg < 1e-3
