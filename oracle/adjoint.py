@@ -51,15 +51,25 @@ class Solve:
     box: np.ndarray          # complex [3][bz][by][bx]
     mon: List[np.ndarray]    # per port plane complex [2][n1][n0]
     resid: float
+    hmon: List[np.ndarray] = None   # per port plane, tangential Hhat [2][n1][n0] (two-term)
 
 
-def solve(dev, kap, src_plane, src_j, lam, n_steps=None) -> Solve:
+def solve(dev, kap, src_plane, src_j, lam, n_steps=None, hmon=False, m_plane=None,
+          m_src=None) -> Solve:
+    """One time-harmonic run: an electric current on src_plane, optionally a
+    magnetic current m_src on the H sites of m_plane, optionally recording
+    the tangential H of the port planes."""
     p = sim_params(dev, lam, n_steps)
-    r = fdtd.run(p, kap, src_plane=src_plane, src_j=src_j, box=dev.dft_box(),
-                 mon_planes=[m.plane for m in dev.ports])
+    planes = [m.plane for m in dev.ports]
+    r = fdtd.run(p, kap, src_plane=src_plane, src_j=src_j, box=dev.dft_box(), mon_planes=planes,
+                 hmon_planes=planes if hmon else (), msrc_plane=m_plane, msrc_m=m_src)
     box, res = fdtd.extract_halves(r.box_sums, p.omega_dt, p.win_start, p.win_len)
     mons = [fdtd.extract_halves(s, p.omega_dt, p.win_start, p.win_len)[0] for s in r.mon_sums]
-    return Solve(box, mons, res)
+    hm = None
+    if hmon:
+        G = fdtd.gram_half(p.omega_dt, p.win_start, p.win_start + p.win_len)
+        hm = [fdtd.extract(s[0] + s[1], G) for s in r.hmon_sums]
+    return Solve(box, mons, res, hm)
 
 
 @dataclass
@@ -73,7 +83,17 @@ class Result:
     beta: float
 
 
-def forward_adjoint(dev, C=None, beta=None, n_steps=None, ops=None, kap=None) -> Result:
+def forward_adjoint(dev, C=None, beta=None, n_steps=None, ops=None, kap=None,
+                    two_term: bool = False) -> Result:
+    """Forward and unit adjoint runs.  two_term: the Appendix A coefficient
+    with both terms, alpha = wE . Ehat + u . Hhat, read from the E and H
+    phasors of the port planes; the adjoint of port p then carries the
+    electric current wE on the plane's E sites and the magnetic current -u
+    on its H sites (a magnetic current m enters the E equation as the
+    electric current -curl_h m / (2 i sin theta) and curl_h is the transpose
+    of curl_e, so -u reproduces the H term's weights on E sites)."""
+    if two_term:
+        return _forward_adjoint_two_term(dev, C, beta, n_steps, ops, kap)
     C = dev.C if C is None else C
     beta = dev.beta if beta is None else beta
     st = None
@@ -94,6 +114,30 @@ def forward_adjoint(dev, C=None, beta=None, n_steps=None, ops=None, kap=None) ->
         for p in range(npo):
             adj[p][f] = solve(dev, kap, dev.ports[p].plane, W[p], lam, n_steps)
     return Result(alpha, fwd, adj, kap, st, W, beta)
+
+
+def _forward_adjoint_two_term(dev, C, beta, n_steps, ops, kap) -> Result:
+    C = dev.C if C is None else C
+    beta = dev.beta if beta is None else beta
+    st = None
+    if kap is None:
+        kap, st = chain.kappa(dev, C, beta, ops)
+    WU = [ports.two_term_weights(m.e, m.h, m.plane.axis) for m in dev.ports]
+    J = [ports.source_current(s.h) for s in dev.sources]
+    ns, npo, nf = len(dev.sources), len(dev.ports), dev.n_freq
+    alpha = np.zeros((ns, npo, nf), np.complex128)
+    fwd = [[None] * nf for _ in range(ns)]
+    adj = [[None] * nf for _ in range(npo)]
+    for f, lam in enumerate(dev.wavelengths):
+        for s in range(ns):
+            r = solve(dev, kap, dev.sources[s].plane, J[s], lam, n_steps, hmon=True)
+            fwd[s][f] = r
+            for p in range(npo):
+                alpha[s, p, f] = ports.alpha_two_term(WU[p][0], WU[p][1], r.mon[p], r.hmon[p])
+        for p in range(npo):
+            pl = dev.ports[p].plane
+            adj[p][f] = solve(dev, kap, pl, WU[p][0], lam, n_steps, m_plane=pl, m_src=-WU[p][1])
+    return Result(alpha, fwd, adj, kap, st, WU, beta)
 
 
 @dataclass

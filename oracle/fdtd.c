@@ -30,6 +30,12 @@
  *     n_dft frequencies w_f, split at win_start (steps from win_start on go
  *     to the second set, so the caller can see how much the late field
  *     still contributes);
+ *   - optionally (the two-term modal coefficient of Appendix A): running DFT
+ *     sums of the tangential Ht^{n+1/2} exp(+i w (n+1/2) dt) over the window
+ *     on planes of H sites (half a cell past the plane's E sites along its
+ *     normal), and one magnetic current plane,
+ *       Ht^{n+1/2} -= ramp(n dt) Re( mhat(r) exp(-i w n dt) )
+ *     on those tangential H sites, applied right after the H update;
  *   - optionally the discrete energy
  *       W^n = sum eps |E^n|^2 + sum Ht^{n-1/2} . Ht^{n+1/2},
  *     which the scheme conserves exactly in a closed lossless box.
@@ -65,6 +71,15 @@ typedef struct {
  * i.e. axis x -> (y, z), axis y -> (z, x), axis z -> (x, y). */
 typedef struct { int axis, index, lo0, lo1, n0, n1; } orc_plane;
 typedef struct { int x0, y0, z0, bx, by, bz; } orc_box;
+
+/* H monitors and the magnetic current plane (NULL: none) */
+typedef struct {
+    int n_hmon;
+    const orc_plane *hmon;   /* [n_hmon] */
+    double *hmon_acc;        /* complex, [2 halves][sum of 2 n0 n1] like mon_acc */
+    const orc_plane *msrc;   /* NULL: no magnetic source */
+    const double *msrc_m;    /* complex [2][n1][n0]: mhat_t1, mhat_t2 */
+} orc_ext;
 
 #define IDX(i, j, k) (((size_t)(k) * ny + (size_t)(j)) * nx + (size_t)(i))
 
@@ -132,7 +147,7 @@ int orc_run(const orc_sim *sim, const double *kappa, double *E, double *H,
             const orc_plane *src, const double *src_j,
             const orc_box *box, double *box_acc,
             int n_mon, const orc_plane *mon, double *mon_acc,
-            double *energy)
+            double *energy, const orc_ext *ext)
 {
     const int nx = sim->nx, ny = sim->ny, nz = sim->nz;
     const size_t N = (size_t)nx * ny * nz;
@@ -272,6 +287,55 @@ int orc_run(const orc_sim *sim, const double *kappa, double *E, double *H,
                     Hx[q] = hx; Hy[q] = hy; Hz[q] = hz;
                 }
         if (energy) energy[n] = wsum_e + wsum_h;
+
+        /* ---- magnetic current on the tangential H sites of its plane ---- */
+        if (ext && ext->msrc) {
+            const orc_plane *mp = ext->msrc;
+            double t = n;
+            double r = 1.0;
+            if (sim->ramp_steps > 0.0 && t < sim->ramp_steps)
+                r = 0.5 * (1.0 - cos(M_PI * t / sim->ramp_steps));
+            double ca = r * cos(sim->omega_dt * t), sa = r * sin(sim->omega_dt * t);
+            int t1, t2;
+            plane_tangentials(mp->axis, &t1, &t2);
+            double *hcomp[3] = {Hx, Hy, Hz};
+            for (int tt = 0; tt < 2; tt++)
+                for (int b = 0; b < mp->n1; b++)
+                    for (int a = 0; a < mp->n0; a++) {
+                        int i, j, k;
+                        plane_cell(mp, a, b, &i, &j, &k);
+                        size_t o = ((size_t)tt * mp->n1 + b) * mp->n0 + a;
+                        double mv = ext->msrc_m[2 * o] * ca + ext->msrc_m[2 * o + 1] * sa;
+                        hcomp[tt == 0 ? t1 : t2][IDX(i, j, k)] -= mv;
+                    }
+        }
+
+        /* ---- DFT of the tangential Ht^{n+1/2} on the H monitor planes ---- */
+        if (ext && ext->n_hmon > 0 && w >= 0 && w < sim->win_len && !pulse) {
+            int h = (w < half) ? 0 : 1;
+            double cr = cos(sim->omega_dt * (n + 0.5)), ci = sin(sim->omega_dt * (n + 0.5));
+            size_t htot = 0;
+            for (int p = 0; p < ext->n_hmon; p++) htot += 2 * (size_t)ext->hmon[p].n0 * ext->hmon[p].n1;
+            double *acc = ext->hmon_acc + 2 * h * htot;
+            const double *hcomp[3] = {Hx, Hy, Hz};
+            size_t off = 0;
+            for (int p = 0; p < ext->n_hmon; p++) {
+                const orc_plane *hp = &ext->hmon[p];
+                int t1, t2;
+                plane_tangentials(hp->axis, &t1, &t2);
+                for (int tt = 0; tt < 2; tt++)
+                    for (int b = 0; b < hp->n1; b++)
+                        for (int a = 0; a < hp->n0; a++) {
+                            int i, j, k;
+                            plane_cell(hp, a, b, &i, &j, &k);
+                            double hv = hcomp[tt == 0 ? t1 : t2][IDX(i, j, k)];
+                            size_t o = off + ((size_t)tt * hp->n1 + b) * hp->n0 + a;
+                            acc[2 * o] += hv * cr;
+                            acc[2 * o + 1] += hv * ci;
+                        }
+                off += 2 * (size_t)hp->n0 * hp->n1;
+            }
+        }
 
         /* ---- E update: E += kappa curl_h Ht (backward differences) ---- */
 #pragma omp parallel for schedule(static)

@@ -39,6 +39,11 @@ class _Plane(ct.Structure):
                 ("lo1", ct.c_int), ("n0", ct.c_int), ("n1", ct.c_int)]
 
 
+class _Ext(ct.Structure):
+    _fields_ = [("n_hmon", ct.c_int), ("hmon", ct.c_void_p), ("hmon_acc", ct.c_void_p),
+                ("msrc", ct.c_void_p), ("msrc_m", ct.c_void_p)]
+
+
 class _Box(ct.Structure):
     _fields_ = [("x0", ct.c_int), ("y0", ct.c_int), ("z0", ct.c_int),
                 ("bx", ct.c_int), ("by", ct.c_int), ("bz", ct.c_int)]
@@ -86,6 +91,7 @@ class RunResult:
     mon_sums: List[np.ndarray]          # per plane complex [2 halves][2][n1][n0]
     # (pulse excitation: [2 parts][n_dft][...] with the part split at win_start)
     energy: Optional[np.ndarray]
+    hmon_sums: List[np.ndarray] = None  # per H plane complex [2 halves][2][n1][n0] (t = n + 1/2)
 
 
 def _pd(a):
@@ -93,7 +99,8 @@ def _pd(a):
 
 
 def run(p: SimParams, kappa: np.ndarray, E0=None, H0=None, src_plane=None, src_j=None,
-        box=None, mon_planes=(), energy=False) -> RunResult:
+        box=None, mon_planes=(), energy=False, hmon_planes=(), msrc_plane=None,
+        msrc_m=None) -> RunResult:
     """Advance the Yee scheme ``p.n_steps`` steps from (E0, H0) (zero if None)."""
     nx, ny, nz = p.nx, p.ny, p.nz
     shape = (3, nz, ny, nx)
@@ -127,13 +134,35 @@ def run(p: SimParams, kappa: np.ndarray, E0=None, H0=None, src_plane=None, src_j
         tot += 2 * pl.n0 * pl.n1
     mon_acc = np.zeros((2, max(nd, 1), max(tot, 1)), np.complex128)
     en = np.zeros(max(p.n_steps, 1)) if energy else None
+    hplanes = list(hmon_planes)
+    ext = None
+    keep = []
+    if hplanes or msrc_plane is not None:
+        hp = (_Plane * max(1, len(hplanes)))()
+        htot = 0
+        for q, pl in enumerate(hplanes):
+            hp[q] = _Plane(pl.axis, pl.index, pl.lo0, pl.lo1, pl.n0, pl.n1)
+            htot += 2 * pl.n0 * pl.n1
+        hacc = np.zeros((2, max(htot, 1)), np.complex128)
+        mp = None
+        mm = None
+        if msrc_plane is not None:
+            mp = _Plane(msrc_plane.axis, msrc_plane.index, msrc_plane.lo0, msrc_plane.lo1,
+                        msrc_plane.n0, msrc_plane.n1)
+            mm = np.ascontiguousarray(np.asarray(msrc_m, np.complex128).reshape(
+                2, msrc_plane.n1, msrc_plane.n0)).view(np.float64)
+        keep = [hp, hacc, mp, mm]
+        ext = _Ext(len(hplanes), ct.addressof(hp), hacc.ctypes.data,
+                   ct.addressof(mp) if mp is not None else None,
+                   mm.ctypes.data if mm is not None else None)
     rc = lib().orc_run(ct.byref(sim), _pd(kappa), _pd(E), _pd(H),
                        ct.byref(sp) if sp is not None else None,
                        _pd(sj) if sj is not None else None,
                        ct.byref(bx) if bx is not None else None,
                        _pd(box_acc.view(np.float64)) if box_acc is not None else None,
                        n_mon, mons, _pd(mon_acc.view(np.float64)),
-                       _pd(en) if en is not None else None)
+                       _pd(en) if en is not None else None,
+                       ct.byref(ext) if ext is not None else None)
     if rc != 0:
         raise MemoryError("oracle FDTD failed to allocate")
     mon_sums = []
@@ -145,13 +174,27 @@ def run(p: SimParams, kappa: np.ndarray, E0=None, H0=None, src_plane=None, src_j
         off += n
     if box_acc is not None and not pulse:
         box_acc = box_acc[:, 0]
-    return RunResult(E, H, box_acc, mon_sums, en[:p.n_steps] if energy else None)
+    hmon_sums = []
+    if ext is not None:
+        off = 0
+        for pl in hplanes:
+            n = 2 * pl.n0 * pl.n1
+            hmon_sums.append(keep[1][:, off:off + n].reshape(2, 2, pl.n1, pl.n0).copy())
+            off += n
+    return RunResult(E, H, box_acc, mon_sums, en[:p.n_steps] if energy else None, hmon_sums)
 
 
 def gram(omega_dt: float, n0: int, n1: int) -> np.ndarray:
     """Sum over n in [n0, n1) of [[c^2, c s], [c s, s^2]], c=cos(w n dt), s=sin(w n dt)."""
     n = np.arange(n0, n1, dtype=np.float64)
     c, s = np.cos(omega_dt * n), np.sin(omega_dt * n)
+    return np.array([[np.sum(c * c), np.sum(c * s)], [np.sum(c * s), np.sum(s * s)]])
+
+
+def gram_half(omega_dt: float, n0: int, n1: int) -> np.ndarray:
+    """gram() at the half-step times t = n + 1/2 of the H samples."""
+    t = np.arange(n0, n1, dtype=np.float64) + 0.5
+    c, s = np.cos(omega_dt * t), np.sin(omega_dt * t)
     return np.array([[np.sum(c * c), np.sum(c * s)], [np.sum(c * s), np.sum(s * s)]])
 
 
