@@ -129,6 +129,23 @@ void yo_plan_destroy(yo_plan *plan);
  * sub-pixels.  Changes yo_workspace_bytes. */
 yo_status yo_set_morphology(yo_plan *plan, const char *ops, double diameter, double alpha);
 
+/* Modal coefficient (App. A), host only, before yo_bind_workspace
+ * (YO_ESTATE after).  terms = 1 (default): the E-dependent term alone,
+ * alpha = (1/(2N)) sum (E_t1 h_t2* - E_t2 h_t1*) dA.  terms = 2: both terms,
+ * alpha = (1/4) ((1/N) sum (E x h*) . n + (1/N*) sum (e* x H) . n) dA, with
+ * H the tangential H on the sites half a cell past the plane along its
+ * normal.  The library evaluates the H term on E sites through the Yee
+ * update's H step (Hhat = curl_e Ehat / (2 i sin(w dt / 2))): each port then
+ * records five component planes (E_t1, E_t2 on the plane, the normal E half
+ * a cell past it, E_t1, E_t2 on the next plane; yo_get_dft region 1+p is
+ * complex64 [5][n1][n0]), and its adjoint source carries the same weights,
+ * which depend on the wavelength.  Weights of H sites whose curl would reach
+ * past the plane (its last row along t2 for H_t1, last column along t1 for
+ * H_t2) are dropped.  Call yo_set_port_mode after this.  YO_EINVAL for
+ * other values or a port whose next plane leaves the grid interior;
+ * YO_EUNSUPPORTED under a pulse.  Changes yo_workspace_bytes. */
+yo_status yo_set_alpha_terms(yo_plan *plan, int terms);
+
 /* Pulse excitation (Sec. 2's other route to frequency-domain fields:
  * Fourier transforms of field transients), host only, before
  * yo_bind_workspace (YO_ESTATE after).  With sigma_steps > 0 every source
@@ -142,7 +159,8 @@ yo_status yo_set_morphology(yo_plan *plan, const char *ops, double diameter, dou
  * right-hand side per source or port and wavelength).  The phasors are
  * exact when the field has died away by the end of the run and the pulse
  * spectrum at -w is negligible; the caller picks n_steps, sigma and t0 for
- * that.  The yo_freq windows and ramps are not used.  The stepped
+ * that.  The yo_freq windows and ramps are not used.  YO_EUNSUPPORTED with
+ * the two-term coefficient.  The stepped
  * right-hand sides (yo_set_fields / yo_get_fields) are the sources, then
  * the ports.  sigma_steps <= 0 turns the pulse off.  YO_EINVAL for a
  * carrier outside (0, pi/dt) or t0 < 0.  Changes yo_workspace_bytes. */

@@ -47,6 +47,8 @@ struct YoRhsD {
     const float4 *dfttab;    // DFT phases (.z, .w) of frequency f at step n: dfttab[f * n_steps + n]
     int box_fstride;         // float2 entries from one frequency's DFT box to the next
     int mon_fstride;         // the same for the port planes
+    int src_nc;              // component planes of the source (see YoPlanD::mon_nc)
+    int pad2;
 };
 
 // One plan (one geometry): shared material and geometry description.
@@ -66,7 +68,10 @@ struct YoPlanD {
     int mon_total;
     int *step_ctr;           // device step counter of this plan
     int n_rhs;
-    int pad1;
+    // component planes of a port's monitor (and of its adjoint source): 2 =
+    // the tangential E on the plane; 5 = those, the normal E half a cell past
+    // the plane, and the tangential E one cell past it
+    int mon_nc;
     const YoRhsD *rhs;       // [n_rhs]
 };
 

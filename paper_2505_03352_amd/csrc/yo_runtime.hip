@@ -95,6 +95,7 @@ struct yo_plan {
     bool pulse = false;
     double pulse_w = 0, pulse_sigma = 0, pulse_t0 = 0;
     std::vector<float> fin;      // [n_freq][4] phasor matrices applied at finalize
+    int mon_nc = 2;              // component planes per port (5: two-term coefficient)
     std::vector<yo_freq> freqs;
     std::vector<yo_plane> src_planes, port_planes;
     double dt = 0, sx = 0, sy = 0, sz = 0;
@@ -208,6 +209,25 @@ void build_profiles(yo_plan *p)
 
 size_t fields_per_rhs(const yo_plan *p);
 
+// Port monitors and port weights: mon_nc component planes per port; the
+// two-term weights depend on the frequency, so then each frequency has a
+// block of port_total entries.
+void build_port_tables(yo_plan *p)
+{
+    p->mon_off.clear();
+    p->port_off.clear();
+    p->mon_total = 0;
+    p->port_total = 0;
+    for (auto &pl : p->port_planes) {
+        p->mon_off.push_back(p->mon_total);
+        p->mon_total += (size_t)p->mon_nc * pl.n0 * pl.n1;
+        p->port_off.push_back(p->port_total);
+        p->port_total += (size_t)p->mon_nc * pl.n0 * pl.n1;
+    }
+}
+
+size_t port_w_blocks(const yo_plan *p) { return p->mon_nc == 5 ? (size_t)p->n_freq : 1; }
+
 // Bytes of the morphological region for n stages and t taps (each buffer
 // padded to 64 floats, as set_chain_ptrs carves them).
 size_t morph_bytes(const yo_plan *p, size_t n, size_t t)
@@ -233,7 +253,7 @@ void build_layout(yo_plan *p)
     L.add(L.dft_box, sizeof(float2) * 3 * p->bsz * p->n_rhs);
     L.add(L.dft_mon, sizeof(float2) * std::max<size_t>(p->mon_total, 1) * p->n_rhs);
     L.add(L.src_j, sizeof(float2) * std::max<size_t>(p->src_total, 1));
-    L.add(L.port_w, sizeof(float2) * std::max<size_t>(p->port_total, 1));
+    L.add(L.port_w, sizeof(float2) * std::max<size_t>(p->port_total, 1) * port_w_blocks(p));
     L.add(L.steptab, sizeof(float4) * (size_t)(p->n_freq + 1) * p->n_steps);
     L.add(L.prof, sizeof(float) * 6 * (size_t)(g.nx + g.ny + g.nz));
     L.add(L.desc_plan, sizeof(YoPlanD));
@@ -619,17 +639,10 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
     p->box[4] = d.nd + 2;
     p->box[5] = d.k_hi - d.k_lo + 3;
     p->bsz = (size_t)p->box[3] * p->box[4] * p->box[5];
-    for (auto &pl : p->port_planes) {
-        p->mon_off.push_back(p->mon_total);
-        p->mon_total += 2 * (size_t)pl.n0 * pl.n1;
-    }
+    build_port_tables(p);
     for (auto &pl : p->src_planes) {
         p->src_off.push_back(p->src_total);
         p->src_total += 2 * (size_t)pl.n0 * pl.n1;
-    }
-    for (auto &pl : p->port_planes) {
-        p->port_off.push_back(p->port_total);
-        p->port_total += 2 * (size_t)pl.n0 * pl.n1;
     }
     p->S = d.supersample;
     p->U = p->S * (d.md + 4);
@@ -730,6 +743,7 @@ static yo_status rebuild_descriptors(yo_plan *p)
     }
     P.psi_total = (int)p->psi_per_rhs;
     P.n_ports = p->n_ports;
+    P.mon_nc = p->mon_nc;
     P.n_steps = p->n_steps;
     P.mon_total = (int)p->mon_total;
     for (int q = 0; q < p->n_ports; ++q) {
@@ -776,7 +790,9 @@ static yo_status rebuild_descriptors(yo_plan *p)
             srcp = ra % p->n_ports;
             const yo_plane &q = p->port_planes[srcp];
             pl = YoPlaneD{q.axis, q.index, q.lo0, q.lo1, q.n0, q.n1};
-            jp = p->port_set[srcp] ? portw + p->port_off[srcp] : nullptr;
+            jp = p->port_set[srcp]
+                     ? portw + (p->mon_nc == 5 ? (size_t)f_idx * p->port_total : 0) + p->port_off[srcp]
+                     : nullptr;
         }
         R.steptab = stab + (size_t)f_idx * p->n_steps;
         R.src_j = jp;
@@ -785,6 +801,7 @@ static yo_status rebuild_descriptors(yo_plan *p)
         R.win_len = p->freqs[f_idx].win_len;
         for (int i = 0; i < 4; ++i) R.ginv[i] = p->ginv[4 * f_idx + i];
         R.freq = f_idx;
+        R.src_nc = ro < p->n_fwd ? 2 : p->mon_nc;
         R.n_dft = 1;
         R.dfttab = R.steptab;
         R.box_fstride = 0;
@@ -906,6 +923,28 @@ yo_status yo_set_morphology(yo_plan *p, const char *ops, double diameter, double
     return YO_OK;
 }
 
+yo_status yo_set_alpha_terms(yo_plan *p, int terms)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (p->ws) return fail(YO_ESTATE, "choose the coefficient before binding a workspace");
+    if (terms != 1 && terms != 2) return fail(YO_EINVAL, "terms must be 1 or 2");
+    if (terms == 2) {
+        if (p->pulse) return fail(YO_EUNSUPPORTED, "no two-term coefficient under a pulse");
+        for (int q = 0; q < p->n_ports; ++q) {
+            yo_plane next = p->port_planes[q];
+            next.index += 1;
+            if (!plane_ok(p, next))
+                return fail(YO_EINVAL, "port %d: the plane after it leaves the grid interior", q);
+        }
+    }
+    p->mon_nc = terms == 2 ? 5 : 2;
+    build_port_tables(p);
+    p->port_w_host.clear();
+    std::fill(p->port_set.begin(), p->port_set.end(), 0);
+    build_layout(p);
+    return YO_OK;
+}
+
 yo_status yo_set_pulse(yo_plan *p, double omega0, double sigma_steps, double t0_steps)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
@@ -917,6 +956,9 @@ yo_status yo_set_pulse(yo_plan *p, double omega0, double sigma_steps, double t0_
     } else {
         const double w = omega0 * p->dt;
         if (!(w > 0 && w < M_PI)) return fail(YO_EINVAL, "carrier outside (0, pi / dt)");
+        if (p->mon_nc == 5)
+            return fail(YO_EUNSUPPORTED, "the two-term coefficient's adjoint weights depend on the "
+                                         "frequency; no pulse with it");
         if (!(t0_steps >= 0)) return fail(YO_EINVAL, "negative pulse centre");
         p->pulse = true;
         p->pulse_w = w;
@@ -1043,17 +1085,69 @@ yo_status yo_set_port_mode(yo_plan *p, int port, const double *e, const double *
         N += cget(e, i) * std::conj(cget(h, n + i)) - cget(e, n + i) * std::conj(cget(h, i));
     N *= 0.5;
     if (std::abs(N) == 0.0) return fail(YO_EINVAL, "mode normalisation N is zero");
-    if (p->port_w_host.size() < p->port_total) p->port_w_host.assign(p->port_total, float2{0, 0});
-    for (size_t i = 0; i < n; ++i) {
-        const std::complex<double> w1 = std::conj(cget(h, n + i)) / (2.0 * N);
-        const std::complex<double> w2 = -std::conj(cget(h, i)) / (2.0 * N);
-        p->port_w_host[p->port_off[port] + i] = float2{(float)w1.real(), (float)w1.imag()};
-        p->port_w_host[p->port_off[port] + n + i] = float2{(float)w2.real(), (float)w2.imag()};
-    }
+    const size_t blocks = port_w_blocks(p);
+    if (p->port_w_host.size() < p->port_total * blocks)
+        p->port_w_host.assign(p->port_total * blocks, float2{0, 0});
+    auto put = [&](size_t k, std::complex<double> v) {
+        p->port_w_host[k] = float2{(float)v.real(), (float)v.imag()};
+    };
     hipStream_t s = (hipStream_t)stream;
-    yo_status st0 = upload_to(p->ws + p->L.port_w.off + sizeof(float2) * p->port_off[port],
-                              p->port_w_host.data() + p->port_off[port], sizeof(float2) * 2 * n, s);
-    if (st0) return st0;
+    if (p->mon_nc == 2) {
+        for (size_t i = 0; i < n; ++i) {
+            put(p->port_off[port] + i, std::conj(cget(h, n + i)) / (2.0 * N));
+            put(p->port_off[port] + n + i, -std::conj(cget(h, i)) / (2.0 * N));
+        }
+        yo_status st0 = upload_to(p->ws + p->L.port_w.off + sizeof(float2) * p->port_off[port],
+                                  p->port_w_host.data() + p->port_off[port], sizeof(float2) * 2 * n, s);
+        if (st0) return st0;
+    } else {
+        // Two-term coefficient (App. A): alpha = 1/4 (1/N sum E x h* + 1/N* sum e* x H)
+        // = wE . E + u . H with wE half the E-only weights, u_t1 = -conj(e_t2)/(4 conj N),
+        // u_t2 = conj(e_t1)/(4 conj N) on the tangential H sites half a cell past the
+        // plane.  The Yee update's H step gives Hhat = curl_e Ehat / (2 i sin theta), so
+        // u . H is a sum over E sites: the tangential E on this plane and the next and
+        // the normal E between them.  u is dropped where its curl would reach past the
+        // plane (last row along t2 for u_t1, last column along t1 for u_t2).
+        const int a = pl.axis, t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+        const bool t1_cols = t1 < t2;            // t1 runs along the plane's columns (index % n0)
+        const double S[3] = {p->sx, p->sy, p->sz};
+        std::vector<std::complex<double>> u0(n), u1(n);
+        const std::complex<double> cN = std::conj(N);
+        for (size_t i = 0; i < n; ++i) {
+            const int col = (int)(i % pl.n0), row = (int)(i / pl.n0);
+            const bool last_t2 = t1_cols ? row == pl.n1 - 1 : col == pl.n0 - 1;
+            const bool last_t1 = t1_cols ? col == pl.n0 - 1 : row == pl.n1 - 1;
+            u0[i] = last_t2 ? 0.0 : -std::conj(cget(e, n + i)) / (4.0 * cN);
+            u1[i] = last_t1 ? 0.0 : std::conj(cget(e, i)) / (4.0 * cN);
+        }
+        // index of the cell one step back along t1 / t2, or -1 at the first one
+        auto back = [&](size_t i, bool along_t1) -> long {
+            const int col = (int)(i % pl.n0), row = (int)(i / pl.n0);
+            const bool cols = along_t1 == t1_cols;
+            if (cols) return col > 0 ? (long)i - 1 : -1;
+            return row > 0 ? (long)i - pl.n0 : -1;
+        };
+        for (int f = 0; f < p->n_freq; ++f) {
+            const std::complex<double> fac = 1.0 / std::complex<double>(0.0, 2.0 * std::sin(0.5 * p->omega_dt[f]));
+            const size_t base = (size_t)f * p->port_total + p->port_off[port];
+            for (size_t i = 0; i < n; ++i) {
+                const std::complex<double> w1 = std::conj(cget(h, n + i)) / (4.0 * N);
+                const std::complex<double> w2 = -std::conj(cget(h, i)) / (4.0 * N);
+                put(base + i, w1 - S[a] * u1[i] * fac);
+                put(base + n + i, w2 + S[a] * u0[i] * fac);
+                std::complex<double> qn = (-S[t2] * u0[i] + S[t1] * u1[i]) * fac;
+                const long i2 = back(i, false), i1 = back(i, true);
+                if (i2 >= 0) qn += S[t2] * u0[i2] * fac;
+                if (i1 >= 0) qn -= S[t1] * u1[i1] * fac;
+                put(base + 2 * n + i, qn);
+                put(base + 3 * n + i, S[a] * u1[i] * fac);
+                put(base + 4 * n + i, -S[a] * u0[i] * fac);
+            }
+            yo_status st0 = upload_to(p->ws + p->L.port_w.off + sizeof(float2) * base,
+                                      p->port_w_host.data() + base, sizeof(float2) * 5 * n, s);
+            if (st0) return st0;
+        }
+    }
     p->port_set[port] = 1;
     rebuild_descriptors(p);
     yo_status st = upload_desc(p, s);
@@ -1124,7 +1218,8 @@ static void aux_args(yo_plan *const *plans, const int *which, int cnt, bool dft,
         if (dft) {
             npts = (int)(3 * p->bsz + p->mon_total);
         } else {
-            for (int r = r0; r < r1; ++r) npts = std::max(npts, 2 * p->hrhs[r].src.n0 * p->hrhs[r].src.n1);
+            for (int r = r0; r < r1; ++r)
+                npts = std::max(npts, p->hrhs[r].src_nc * p->hrhs[r].src.n0 * p->hrhs[r].src.n1);
         }
         a.plan[i] = wsp<YoPlanD>(p, p->L.desc_plan);
         a.rhs0[i] = r0;
@@ -1370,8 +1465,9 @@ yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
                 const int r = f * p->n_src + sidx;
                 const yo_plane &pl = p->port_planes[q];
                 float2 *out = reinterpret_cast<float2 *>(alpha) + ((size_t)sidx * p->n_ports + q) * p->n_freq + f;
-                HIPCHK(yo_launch_alpha(mon_of(p, r) + p->mon_off[q], w + p->port_off[q],
-                                       2 * pl.n0 * pl.n1, out, s));
+                const size_t wb = p->mon_nc == 5 ? (size_t)f * p->port_total : 0;
+                HIPCHK(yo_launch_alpha(mon_of(p, r) + p->mon_off[q], w + wb + p->port_off[q],
+                                       p->mon_nc * pl.n0 * pl.n1, out, s));
             }
         }
     return YO_OK;
@@ -1563,7 +1659,7 @@ yo_status yo_get_dft(const yo_plan *p, int rhs, int region, float *out, yo_strea
     } else {
         const yo_plane &pl = p->port_planes[region - 1];
         src = mon_of(p, rhs) + p->mon_off[region - 1];
-        bytes = sizeof(float2) * 2 * pl.n0 * pl.n1;
+        bytes = sizeof(float2) * p->mon_nc * pl.n0 * pl.n1;
     }
     HIPCHK(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return YO_OK;

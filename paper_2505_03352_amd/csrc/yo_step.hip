@@ -669,6 +669,16 @@ __device__ __forceinline__ bool aux_point(const YoAuxArgs &a, int &s, int &r, in
     return true;
 }
 
+// Component plane tt of a port or source plane (normal `axis`, cell index
+// `index`): 0, 1 the tangential E (t1, t2) on the plane; 2 the normal E
+// (its sites lie half a cell past the plane, stored at the same index);
+// 3, 4 the tangential E on the next plane.
+__device__ __forceinline__ void plane_component(int axis, int index, int tt, int &c, int &idx)
+{
+    c = tt == 2 ? axis : (axis + 1 + (tt < 2 ? tt : tt - 3)) % 3;
+    idx = index + (tt >= 3 ? 1 : 0);
+}
+
 // Running DFT of E^n (called before step n): S += E^n exp(+i w n dt) on the
 // design box (3 components) and the port planes (2 tangential components),
 // for each frequency the right-hand side accumulates.
@@ -704,10 +714,11 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
         const int plane = pl.n0 * pl.n1;
         const int tt = loc / plane, rem = loc - tt * plane;
         const int b = rem / pl.n0, ai = rem - b * pl.n0;
-        const int c = (pl.axis + 1 + tt) % 3;
-        const int cx = sel3(pl.axis, pl.index, pl.lo0 + ai, pl.lo0 + ai);
-        const int cy = sel3(pl.axis, pl.lo0 + ai, pl.index, pl.lo1 + b);
-        const int cz = sel3(pl.axis, pl.lo1 + b, pl.lo1 + b, pl.index);
+        int c, idx;
+        plane_component(pl.axis, pl.index, tt, c, idx);
+        const int cx = sel3(pl.axis, idx, pl.lo0 + ai, pl.lo0 + ai);
+        const int cy = sel3(pl.axis, pl.lo0 + ai, idx, pl.lo1 + b);
+        const int cz = sel3(pl.axis, pl.lo1 + b, pl.lo1 + b, idx);
         e = F[yo_off(c, cx, cy, cz, P.ny, P.nxp, 6)];
         acc = R.dft_mon + qm;
         fstride = R.mon_fstride;
@@ -734,14 +745,15 @@ __global__ __launch_bounds__(256) void k_source(const YoAuxArgs a)
     if (!R.src_j) return;
     const YoPlaneD pl = R.src;
     const int plane = pl.n0 * pl.n1;
-    if (q >= 2 * plane) return;
+    if (q >= R.src_nc * plane) return;
     const float4 st = R.steptab[step];
     const int tt = q / plane, rem = q - tt * plane;
     const int b = rem / pl.n0, ai = rem - b * pl.n0;
-    const int c = (pl.axis + 1 + tt) % 3;
-    const int cx = sel3(pl.axis, pl.index, pl.lo0 + ai, pl.lo0 + ai);
-    const int cy = sel3(pl.axis, pl.lo0 + ai, pl.index, pl.lo1 + b);
-    const int cz = sel3(pl.axis, pl.lo1 + b, pl.lo1 + b, pl.index);
+    int c, idx;
+    plane_component(pl.axis, pl.index, tt, c, idx);
+    const int cx = sel3(pl.axis, idx, pl.lo0 + ai, pl.lo0 + ai);
+    const int cy = sel3(pl.axis, pl.lo0 + ai, idx, pl.lo1 + b);
+    const int cz = sel3(pl.axis, pl.lo1 + b, pl.lo1 + b, idx);
     const size_t o = yo_off(c, cx, cy, cz, P.ny, P.nxp, 6);
     const float2 jv = R.src_j[q];
     const float j = fmaf(jv.x, st.x, jv.y * st.y);

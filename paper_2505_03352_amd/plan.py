@@ -56,9 +56,11 @@ class Plan:
     """
 
     def __init__(self, grid: dict, design: dict, n_steps: int, freqs: Sequence[FreqSpec],
-                 src_planes: Sequence, port_planes: Sequence, device="cuda", pulse=None):
+                 src_planes: Sequence, port_planes: Sequence, device="cuda", pulse=None,
+                 two_term: bool = False):
         """pulse: None, or (omega0 rad/s, sigma steps, t0 steps) for pulse
-        excitation (one run per source and per port for all wavelengths)."""
+        excitation (one run per source and per port for all wavelengths).
+        two_term: the modal coefficient with both of its terms (App. A)."""
         self.device = torch.device(device)
         self.grid = dict(grid)
         self.design = dict(design)
@@ -92,6 +94,9 @@ class Plan:
             # Eqs. (4)-(6): before the workspace is sized and bound
             call("yo_set_morphology", self._h, self.morph_ops.encode(),
                  float(design["morph_d"]), float(design.get("morph_alpha", 20.0)))
+        self.mon_nc = 5 if two_term else 2
+        if two_term:
+            call("yo_set_alpha_terms", self._h, 2)
         self.pulse = tuple(pulse) if pulse is not None else None
         if self.pulse is not None:
             call("yo_set_pulse", self._h, float(pulse[0]), float(pulse[1]), float(pulse[2]))
@@ -231,7 +236,7 @@ class Plan:
             shape = (3, bz, by, bx)
         else:
             pl = self.port_planes[region - 1]
-            shape = (2, pl.n1, pl.n0)
+            shape = (self.mon_nc, pl.n1, pl.n0)
         out = torch.empty(shape, dtype=torch.complex64, device=self.device)
         call("yo_get_dft", self._h, rhs, region, _ptr(out), _stream(stream))
         return out
@@ -335,12 +340,13 @@ def freqs_of(dev) -> List[FreqSpec]:
 
 
 def plan_for(dev, device="cuda", stream=None, C=None, beta=None, set_design=True,
-             workspace: Optional[torch.Tensor] = None, pulse=None) -> Plan:
+             workspace: Optional[torch.Tensor] = None, pulse=None, two_term: bool = False) -> Plan:
     """Create, bind and fill a plan for a device description.  pulse:
-    (omega0 rad/s, sigma steps, t0 steps) for pulse excitation."""
+    (omega0 rad/s, sigma steps, t0 steps) for pulse excitation; two_term:
+    the two-term modal coefficient."""
     grid, design = grid_design_of(dev)
     p = Plan(grid, design, dev.n_steps, freqs_of(dev), [m.plane for m in dev.sources],
-             [m.plane for m in dev.ports], device=device, pulse=pulse)
+             [m.plane for m in dev.ports], device=device, pulse=pulse, two_term=two_term)
     p.bind(workspace, stream)
     p.set_background(torch.as_tensor(dev.kappa_bg, dtype=torch.float32),
                      torch.as_tensor(dev.mask_hr, dtype=torch.float32), stream)

@@ -194,3 +194,28 @@ def test_pulse_arguments_and_workspace():
     assert L.yo_set_pulse(h, 0.0, 0.0, 0.0) == _abi.YO_OK                 # off again
     assert L.yo_workspace_bytes(h, ct.byref(nb)) == _abi.YO_OK and nb.value == base
     p.close()
+
+
+def test_two_term_coefficient_arguments_and_workspace():
+    dev = configs.micro_demux()
+    p = _create(dev)
+    base = p.workspace_bytes
+    L = _abi.lib()
+    h = p.handle
+    assert L.yo_set_alpha_terms(h, 3) == _abi.YO_EINVAL
+    assert L.yo_set_alpha_terms(h, 2) == _abi.YO_OK
+    nb = ct.c_size_t()
+    assert L.yo_workspace_bytes(h, ct.byref(nb)) == _abi.YO_OK and nb.value > base
+    w0, sig, t0 = dev.pulse()
+    assert L.yo_set_pulse(h, w0 / dev.dt(), sig, t0) == _abi.YO_EUNSUPPORTED
+    assert L.yo_set_alpha_terms(h, 1) == _abi.YO_OK
+    assert L.yo_workspace_bytes(h, ct.byref(nb)) == _abi.YO_OK and nb.value == base
+    assert L.yo_set_pulse(h, w0 / dev.dt(), sig, t0) == _abi.YO_OK
+    assert L.yo_set_alpha_terms(h, 2) == _abi.YO_EUNSUPPORTED
+    p.close()
+    # a port whose next plane would enter the CPML
+    m = dev.ports[0].plane
+    edge = type(m)(m.axis, dev.nx - dev.npml[1] - 1, m.lo0, m.lo1, m.n0, m.n1)
+    q = _create(dev, ports=[edge, dev.ports[1].plane])
+    assert _abi.lib().yo_set_alpha_terms(q.handle, 2) == _abi.YO_EINVAL
+    q.close()
