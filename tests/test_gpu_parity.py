@@ -504,3 +504,46 @@ def test_launch_timing_keeps_results_and_counts_launches():
         p.close()
     for a, b in zip(*res):
         assert np.array_equal(a, b)
+
+
+def test_largest_grid_random_fields_match_oracle():
+    """A grid at the size limit (one right-hand side's 6-component state
+    just under 2 GiB, so the kernels' 32-bit buffer offsets reach their
+    largest values): random fields everywhere, CPML on every face, random
+    kappa in a block; two steps against the oracle, every value."""
+    from paper_2505_03352_amd.plan import FreqSpec, Plan
+    nx, ny, nz, npml = 640, 480, 270, 8
+    nxp = (nx + 2 + 31) // 32 * 32
+    state = 6 * 4 * (nz + 2) * (ny + 2) * nxp
+    assert 0.98 * 2 ** 31 < state < 2 ** 31
+    rng = np.random.default_rng(70)
+    kap = np.full((3, nz, ny, nx), 1.0 / 2.085, np.float32)
+    kap[:, 100:180, 150:350, 200:500] = (1.0 / rng.uniform(2.085, 12.11, (3, 80, 200, 300))).astype(np.float32)
+    E0 = rng.standard_normal((3, nz, ny, nx), dtype=np.float32)
+    H0 = rng.standard_normal((3, nz, ny, nx), dtype=np.float32)
+    # tangential E on the PEC planes i = 0, j = 0, k = 0 starts at zero, as the scheme keeps it
+    E0[0, 0, :, :] = E0[0, :, 0, :] = 0.0
+    E0[1, 0, :, :] = E0[1, :, :, 0] = 0.0
+    E0[2, :, 0, :] = E0[2, :, :, 0] = 0.0
+    grid = dict(nx=nx, ny=ny, nz=nz, dx=40e-9, dy=40e-9, dz=40e-9, courant=0.5, npml=(npml,) * 6)
+    design = dict(i0=300, j0=220, md=4, nd=4, k_lo=130, k_hi=131, mc=2, nc=2, filter_r=1.0,
+                  supersample=2, eps_core=12.11, eps_clad=2.085, sobel_delta=1e-6)
+    f = FreqSpec(2 * np.pi * 299792458.0 / 1.55e-6, 0.0, 0, 2)
+    say(f"largest grid {nx}x{ny}x{nz}: GPU")
+    p = Plan(grid, design, 2, [f], [Plane(0, 20, 20, 20, 4, 4)], [], device="cuda")
+    p.bind()
+    p.set_background(torch.as_tensor(kap), torch.zeros(p.canvas_shape))
+    p.set_tiling(4, 16, 200)
+    p.reset(1)
+    p.set_fields(0, torch.as_tensor(E0), torch.as_tensor(H0))
+    p.advance(1, 2)
+    E, H = p.get_fields(0)
+    E, H = E.cpu().numpy(), H.cpu().numpy()
+    p.close()
+    say("largest grid: oracle")
+    prm = fdtd.SimParams(nx, ny, nz, npml=(npml,) * 6, n_steps=2, omega_dt=0.1, win_start=0, win_len=2)
+    r = fdtd.run(prm, kap.astype(np.float64), E0=E0.astype(np.float64), H0=H0.astype(np.float64))
+    eE = np.abs(E - r.E).max() / np.abs(r.E).max()
+    eH = np.abs(H - r.H).max() / np.abs(r.H).max()
+    say(f"  max rel err E {eE:.2e} H {eH:.2e}")
+    assert eE < 1e-5 and eH < 1e-5
