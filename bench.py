@@ -93,7 +93,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="plain launches instead of HIP-graph replays (for counter collection)")
-    ap.add_argument("--workload", choices=("realistic", "batch", "serving", "optimize", "broadband"),
+    ap.add_argument("--workload", choices=("realistic", "batch", "serving", "optimize", "broadband",
+                                           "batch-fd"),
                     default="realistic",
                     help="realistic: the headline line; batch / serving: the batched and served "
                          "forms against one-at-a-time solves (their own JSON line)")
@@ -129,6 +130,8 @@ def main():
         return bench_optimize(args)
     if args.workload == "broadband":
         return bench_broadband(args)
+    if args.workload == "batch-fd":
+        return bench_batch_fd(args)
 
     import torch
     from paper_2505_03352_amd import YO_BOTH, autotune
@@ -334,6 +337,62 @@ def bench_serving(args):
            "one_at_a_time": {"designs_per_h": round(b.throughput_per_h, 1),
                              "p50_s": round(b.p50_s, 3), "p99_s": round(b.p99_s, 3),
                              "gcell_updates_per_s": round(b.cell_updates / b.makespan_s / 1e9, 3)}})
+
+
+def bench_batch_fd(args):
+    """The differentiable batch's check: for each of the 8 batch designs, the
+    autograd Function's gradient of sum |alpha|^2 against central
+    differences (h = 1e-3) on 16 random control entries, the 32 perturbed
+    forward runs of a design advancing together in shared launches."""
+    import numpy as np
+    import torch
+    from paper_2505_03352_amd import YO_BOTH, YO_FORWARD, batch, fn
+    from paper_2505_03352_amd.plan import plan_for
+    from workloads import configs
+    torch.cuda.set_device(0)
+    h = 1e-3
+    worst, rows = 0.0, []
+    t0 = time.perf_counter()
+    for d, dev in enumerate(configs.batch(8)):
+        rng = np.random.default_rng(500 + d)
+        flat = rng.choice(dev.C.size, size=16, replace=False)
+        idx = [np.unravel_index(k, dev.C.shape) for k in flat]
+        p = plan_for(dev, device="cuda:0")
+        batch.shared_tiling([p], 4, batch.DEFAULT_FLAGS, zchunk=16)
+        C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0").requires_grad_(True)
+        a = fn.modal_coefficients(C, p, dev.beta, chunk=args.chunk)
+        (a.abs() ** 2).sum().backward()
+        g = C.grad.detach().cpu().numpy()
+        p.close()
+        plans = []
+        for k in idx:
+            for sgn in (1.0, -1.0):
+                Cp = dev.C.copy()
+                Cp[k] += sgn * h
+                plans.append(plan_for(dev, device="cuda:0", C=Cp))
+        batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS, zchunk=16)
+        batch.solve(plans, which=YO_FORWARD, chunk=args.chunk)
+        vals = [float((q.alpha().abs() ** 2).sum()) for q in plans]
+        for q in plans:
+            q.close()
+        fd = np.array([(vals[2 * i] - vals[2 * i + 1]) / (2 * h) for i in range(16)])
+        ga = np.array([g[k] for k in idx])
+        err = float(np.max(np.abs(fd - ga)) / np.abs(g).max())
+        rel = float(np.linalg.norm(fd - ga) / np.linalg.norm(ga))
+        worst = max(worst, err)
+        rows.append({"grid": [dev.nx, dev.ny, dev.nz], "steps": dev.n_steps,
+                     "max_err_over_max_grad": err, "rel_l2_16": rel})
+        log(f"design {d} {dev.nx}x{dev.ny}x{dev.nz}/{dev.n_steps}: max |fd - autograd| / max|g| "
+            f"{err:.2e}, rel L2 over the 16 entries {rel:.2e} ({time.perf_counter() - t0:.0f} s)")
+    out = {"metric": "autograd gradient vs central differences (batch designs)", "value": worst,
+           "unit": "max |fd - autograd| / max |gradient|", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": round((time.perf_counter() - t0) * 1e3, 1), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch: 8 designs, axes uniform in 128..320 x 96..240 x 64..96 at "
+                                  "20 nm, 1 wavelength, F = sum |alpha|^2; central differences "
+                                  "h = 1e-3 on 16 random controls per design (seeds 500..507)"},
+           "designs": rows}
+    print(json.dumps(out), flush=True)
 
 
 def bench_broadband(args):
