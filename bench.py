@@ -99,6 +99,8 @@ def main():
                     help="realistic: the headline line; batch / serving: the batched and served "
                          "forms against one-at-a-time solves (their own JSON line)")
     ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
+    ap.add_argument("--no-baseline", action="store_true",
+                    help="serving: skip the one-request-at-a-time baseline")
     ap.add_argument("--iters", type=int, default=5, help="optimize: optimizer iterations")
     ap.add_argument("--pulse", action="store_true",
                     help="optimize: gradients from pulse runs; serving: pulse runs for "
@@ -310,19 +312,26 @@ def bench_serving(args):
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
     out = {}
-    for name, slots in (("served", args.slots), ("one_at_a_time", 1)):
+    runs = (("served", args.slots),) if args.no_baseline else (("served", args.slots), ("one_at_a_time", 1))
+    for name, slots in runs:
         # --pulse: the served loop evaluates multi-wavelength requests from
         # pulse runs where that is cheaper; the one-at-a-time baseline stays
         # time-harmonic
         ex = GpuExecutor(build, device="cuda:0", chunk=args.chunk, pulse_multi=args.pulse and slots > 1)
         reqs = [Request(i, t, (i, cls, lams)) for i, (t, cls, lams) in enumerate(trace)]
         cap = args.max_cells if slots > 1 else None
+        t_start = time.perf_counter()
+
+        def done(r, name=name):
+            if r.rid % 10 == 9:
+                log(f"{name}: request {r.rid} done at {time.perf_counter() - t_start:.1f} s")
+
         st = Scheduler(ex, max_slots=slots, hbm_budget=budget, chunk=args.chunk,
-                       max_active_cells=cap).run(reqs)
+                       max_active_cells=cap, on_done=done).run(reqs)
         torch.cuda.synchronize()
         out[name] = st
         log(f"{name}: {st.as_dict()}")
-    s, b = out["served"], out["one_at_a_time"]
+    s, b = out["served"], out.get("one_at_a_time")
     _line("p50/p99 request latency and designs/hour (continuous batching)", s.throughput_per_h,
           "designs/h", s.makespan_s * 1e3, args,
           {"workload": f"serving: first {args.requests} of 200 Poisson arrivals at {args.rate:g} req/s, "
@@ -334,9 +343,10 @@ def bench_serving(args):
            "hbm_budget_bytes": budget},
           {"p50_s": round(s.p50_s, 3), "p99_s": round(s.p99_s, 3),
            "gcell_updates_per_s": round(s.cell_updates / s.makespan_s / 1e9, 3),
-           "one_at_a_time": {"designs_per_h": round(b.throughput_per_h, 1),
-                             "p50_s": round(b.p50_s, 3), "p99_s": round(b.p99_s, 3),
-                             "gcell_updates_per_s": round(b.cell_updates / b.makespan_s / 1e9, 3)}})
+           "one_at_a_time": None if b is None else {
+               "designs_per_h": round(b.throughput_per_h, 1), "p50_s": round(b.p50_s, 3),
+               "p99_s": round(b.p99_s, 3),
+               "gcell_updates_per_s": round(b.cell_updates / b.makespan_s / 1e9, 3)}})
 
 
 def bench_batch_fd(args):

@@ -113,7 +113,8 @@ class Scheduler:
     """FIFO admission by slot and HBM footprint; chunked shared stepping."""
 
     def __init__(self, executor, max_slots: int = 8, hbm_budget: int = 64 << 30, chunk: int = 100,
-                 clock=None, prep_workers: int = 2, max_active_cells: Optional[float] = None):
+                 clock=None, prep_workers: int = 2, max_active_cells: Optional[float] = None,
+                 on_done: Optional[Callable] = None):
         if max_slots < 1 or chunk < 1:
             raise ValueError("max_slots and chunk must be >= 1")
         self.ex = executor
@@ -123,6 +124,7 @@ class Scheduler:
         self.clock = clock or RealClock()
         self.prep_workers = prep_workers
         self.max_active_cells = max_active_cells
+        self.on_done = on_done               # called with each finished request
         self.events: List[tuple] = []      # (time, kind, rid) for inspection
 
     def _log(self, kind, rid):
@@ -164,6 +166,8 @@ class Scheduler:
                         used -= j.footprint
                         retiring.remove(j)
                         done.append(j.req)
+                        if self.on_done is not None:
+                            self.on_done(j.req)
                         self._log("done", j.req.rid)
                 # admissions, FIFO
                 while queue and len(active) + len(retiring) < self.max_slots:
