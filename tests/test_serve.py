@@ -171,3 +171,16 @@ def test_work_cap_limits_concurrency_but_not_progress():
     assert st.n_done == 6
     assert max(len(c) for c in ex.calls) == 2
     assert any(c == (5,) for c in ex.calls)               # the big one ran alone
+
+
+def test_completion_callback_sees_every_finished_request():
+    reqs = make([(0.01 * i, (200000, 100, 1 << 20)) for i in range(6)])
+    seen = []
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    sch = Scheduler(ex, max_slots=3, hbm_budget=1 << 30, chunk=50, clock=clock, prep_workers=0,
+                    on_done=lambda r: seen.append((r.rid, r.t_done is not None)))
+    st = sch.run(reqs)
+    assert st.n_done == 6
+    assert sorted(rid for rid, _ in seen) == list(range(6))
+    assert all(ok for _, ok in seen)
