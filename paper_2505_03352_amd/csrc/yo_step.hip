@@ -71,6 +71,15 @@ __device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff)
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, voff, soff, 0);
 }
 
+// Store of a new field value: no wave of this launch reads it again, so it
+// is marked non-temporal (cache-policy bit 1) to leave the caches to the
+// halo rows and planes that neighbouring tiles do re-read.  (The CPML
+// memories keep the default policy: marked the same way, measured slower.)
+__device__ __forceinline__ void bstore_nt(float v, Rsrc r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, voff, soff, 2);
+}
+
 __device__ __forceinline__ int slab_index(int u, int n, int lo, int hi)
 {
     if (u < 0 || u >= n) return -1;
@@ -512,9 +521,9 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             Hc[2][r] = hz;
             if (own) {
                 const int o = ro(j, k) + hb;
-                bstore(hx, Fn, xo, o);
-                bstore(hy, Fn, xo, rowb + o);
-                bstore(hz, Fn, xo, 2 * rowb + o);
+                bstore_nt(hx, Fn, xo, o);
+                bstore_nt(hy, Fn, xo, rowb + o);
+                bstore_nt(hz, Fn, xo, 2 * rowb + o);
             }
         }
         if (COOP) {
@@ -554,9 +563,9 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             ez = (x == 0 || j == 0) ? 0.0f : ez;
             if (own_x) {
                 const int o = ro(j, k) + eb;
-                bstore(ex, Fn, xo, o);
-                bstore(ey, Fn, xo, rowb + o);
-                bstore(ez, Fn, xo, 2 * rowb + o);
+                bstore_nt(ex, Fn, xo, o);
+                bstore_nt(ey, Fn, xo, rowb + o);
+                bstore_nt(ez, Fn, xo, 2 * rowb + o);
             }
         }
 #pragma unroll
