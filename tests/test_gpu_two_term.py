@@ -81,3 +81,34 @@ def test_one_term_path_unchanged_next_to_two_term_plan():
     a1 = p.alpha().cpu().numpy()
     p.close()
     assert np.array_equal(a0, a1)
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_two_term_on_y_and_z_normal_ports(axis):
+    """Ports normal to y and to z (whose in-plane storage order differs from
+    the (t1, t2) order for y), with random mode profiles: alpha and the
+    gradient of the two-term coefficient against the oracle."""
+    from paper_2505_03352_amd.plan import plan_for
+    from workloads import Mode, Plane
+    dev = configs.micro(n_steps=1600)
+    dev.C = np.random.default_rng(61).uniform(0.3, 0.7, dev.C.shape)
+    rng = np.random.default_rng(62 + axis)
+    # a plane clear of the CPML, the source and the design, crossed by the field
+    pl = {1: Plane(1, 17, 9, 5, 12, 8), 2: Plane(2, 11, 9, 6, 12, 10)}[axis]
+    shape = (2, pl.n1, pl.n0)
+    e = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    h = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    dev.ports = [Mode(pl, e, h)]
+    ref = adjoint.forward_adjoint(dev, two_term=True)
+    cref = np.conj(ref.alpha)
+    gref = adjoint.grad_C(dev, ref, cref)
+    p = plan_for(dev, two_term=True)
+    p.run(3)
+    a = p.alpha().cpu().numpy()
+    g = p.gradient(torch.as_tensor(cref, dtype=torch.complex64, device="cuda")).cpu().numpy()
+    p.close()
+    ea = np.abs(a - ref.alpha).max() / np.abs(ref.alpha).max()
+    eg = rel_l2(g, gref)
+    say(f"two-term, port normal to axis {axis}: alpha err {ea:.2e}, gradient rel L2 {eg:.2e}")
+    assert ea < 1e-4
+    assert eg < 1e-3
