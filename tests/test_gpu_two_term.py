@@ -83,11 +83,13 @@ def test_one_term_path_unchanged_next_to_two_term_plan():
     assert np.array_equal(a0, a1)
 
 
+@pytest.mark.parametrize("two", [True, False])
 @pytest.mark.parametrize("axis", [1, 2])
-def test_two_term_on_y_and_z_normal_ports(axis):
+def test_ports_normal_to_y_and_z(axis, two):
     """Ports normal to y and to z (whose in-plane storage order differs from
     the (t1, t2) order for y), with random mode profiles: alpha and the
-    gradient of the two-term coefficient against the oracle."""
+    gradient of the two-term (and of the E-only) coefficient against the
+    oracle."""
     from paper_2505_03352_amd.plan import plan_for
     from workloads import Mode, Plane
     dev = configs.micro(n_steps=1600)
@@ -99,16 +101,17 @@ def test_two_term_on_y_and_z_normal_ports(axis):
     e = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     h = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     dev.ports = [Mode(pl, e, h)]
-    ref = adjoint.forward_adjoint(dev, two_term=True)
+    ref = adjoint.forward_adjoint(dev, two_term=two)
     cref = np.conj(ref.alpha)
     gref = adjoint.grad_C(dev, ref, cref)
-    p = plan_for(dev, two_term=True)
+    p = plan_for(dev, two_term=two)
     p.run(3)
     a = p.alpha().cpu().numpy()
     g = p.gradient(torch.as_tensor(cref, dtype=torch.complex64, device="cuda")).cpu().numpy()
     p.close()
     ea = np.abs(a - ref.alpha).max() / np.abs(ref.alpha).max()
     eg = rel_l2(g, gref)
-    say(f"two-term, port normal to axis {axis}: alpha err {ea:.2e}, gradient rel L2 {eg:.2e}")
+    say(f"{'two-term' if two else 'E-only'}, port normal to axis {axis}: alpha err {ea:.2e}, "
+        f"gradient rel L2 {eg:.2e}")
     assert ea < 1e-4
     assert eg < 1e-3
