@@ -71,9 +71,11 @@ def cpu_baseline(dev, target_s: float):
         fdtd.run(prm, kap, src_plane=src.plane, src_j=J)
         return time.perf_counter() - t
 
-    probe = 10
-    t = run(probe)
-    n = int(max(probe, min(2000, probe * target_s / max(t, 1e-3))))
+    # the per-step cost from two short runs (their difference drops the
+    # set-up every run pays), then one run sized to about target_s
+    t10, t30 = run(10), run(30)
+    per_step = max((t30 - t10) / 20.0, 1e-4)
+    n = int(max(30, min(5000, (target_s - t10) / per_step)))
     t = run(n)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": dev.cells * n / t / 1e9, "unit": "Gcell-updates/s", "cores": threads,
