@@ -241,6 +241,8 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
  *   64  shell: no prefetch
  *  128  the CPML x-shell strips take what is left of each row once the
  *       interior is cut into whole 62-cell strips (overrides 1)
+ *  256  tiles that meet only the x-slabs run in the interior launch, which
+ *       then carries the x-axis CPML code
  * Other bits: YO_EINVAL.  Results do not depend on the split (bitwise).
  * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);

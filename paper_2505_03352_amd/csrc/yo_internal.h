@@ -152,7 +152,8 @@ struct YoChainBufs {
 };
 
 // ---- kernel launchers ----
-// pm: 0 = interior tiles (no CPML code), 7 = CPML tiles with the code of all
+// pm: 0 = interior tiles (no CPML code), 1 = interior tiles plus tiles inside
+// the x-slabs only (the x-axis CPML code), 7 = CPML tiles with the code of all
 // three axes, 8 = CPML tiles each running its own class's code (int4 .w);
 // coop: one tile per block, its waves stacked in y (tiles of YO_TY * wpb
 // rows); prefetch: operands of the next plane loaded during this one

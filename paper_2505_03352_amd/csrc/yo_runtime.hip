@@ -80,7 +80,8 @@ enum {
     YO_TILE_NOPF_INT = 32,    // interior: no prefetch of the next plane
     YO_TILE_NOPF_SHELL = 64,  // CPML shell: no prefetch of the next plane
     YO_TILE_XFULL = 128,      // x-shell strips as narrow as whole 62-cell interior strips allow
-    YO_TILE_ALL = 255
+    YO_TILE_XINT = 256,       // tiles inside the x-slabs only run in the interior launch (x CPML code)
+    YO_TILE_ALL = 511
 };
 
 struct yo_plan {
@@ -398,7 +399,9 @@ void split_axis(int n, int lo, int hi, int w, std::vector<std::pair<int, int>> &
 // (z, y, x fastest).  Along each axis the region clear of the absorbing
 // slabs is [lo + 1, n - hi) for a CPML of lo/hi cells (no owned site and no
 // recomputed halo site one below meets a CPML coefficient); a tile is
-// interior when it lies in that region along all three axes.  A shell tile's
+// interior when it lies in that region along all three axes (with
+// YO_TILE_XINT also when it leaves it along x only: the interior launch then
+// runs the x-axis CPML code, at the interior's register budget).  A shell tile's
 // class (int4 .w) has bit a set when it is not clear along axis a.  The two
 // parts may use different row counts (cooperative blocks take YO_TY rows per
 // wave of the block).
@@ -439,7 +442,8 @@ void build_tiles(yo_plan *p)
             for (size_t j = 0; j < ay.size(); ++j)
                 for (size_t i = 0; i < ax.size(); ++i) {
                     const int c = (ix[i] ? 0 : 1) | (iy[j] ? 0 : 2) | (iz[k] ? 0 : 4);
-                    if ((c != 0) != shell) continue;
+                    const bool in_shell = c != 0 && !(c == 1 && (p->tflags & YO_TILE_XINT));
+                    if (in_shell != shell) continue;
                     int4 t;
                     t.x = ax[i].first | (ax[i].second << 16);
                     t.y = ay[j].first | (ay[j].second << 16);
@@ -1271,7 +1275,8 @@ static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, 
 {
     const int f = p0->tflags;
     if (part == 0)
-        return yo_launch_step(0, (f & YO_TILE_COOP_INT) != 0, !(f & YO_TILE_NOPF_INT), a, blocks, s);
+        return yo_launch_step((f & YO_TILE_XINT) ? 1 : 0, (f & YO_TILE_COOP_INT) != 0,
+                              !(f & YO_TILE_NOPF_INT), a, blocks, s);
     return yo_launch_step((f & YO_TILE_CLASS_CODE) ? 8 : 7, (f & YO_TILE_COOP_SHELL) != 0,
                           !(f & YO_TILE_NOPF_SHELL), a, blocks, s);
 }

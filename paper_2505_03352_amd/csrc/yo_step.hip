@@ -808,6 +808,7 @@ hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &ar
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
     switch (pm) {
     case 0: launch_pm<0>(coop, prefetch, args, blocks, s); break;
+    case 1: launch_pm<1>(coop, prefetch, args, blocks, s); break;
     case 7: launch_pm<7>(coop, prefetch, args, blocks, s); break;
     case YO_PM_ANY: launch_pm<YO_PM_ANY>(coop, prefetch, args, blocks, s); break;
     default: return hipErrorInvalidValue;

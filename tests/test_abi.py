@@ -113,9 +113,9 @@ def test_calls_before_bind_fail_cleanly():
     assert L.yo_set_tiling(p.handle, 8, 16, 0) == _abi.YO_EINVAL
     assert L.yo_set_tiling(p.handle, 4, 3, 0) == _abi.YO_EINVAL
     assert L.yo_set_tiling(p.handle, 4, 64, 0) == _abi.YO_EINVAL
-    assert L.yo_set_tiling(p.handle, 4, 16, 256) == _abi.YO_EINVAL
+    assert L.yo_set_tiling(p.handle, 4, 16, 512) == _abi.YO_EINVAL
     assert L.yo_set_tiling(p.handle, 4, 8, 3) == _abi.YO_OK
-    assert L.yo_set_tiling(p.handle, 4, 16, 255) == _abi.YO_OK
+    assert L.yo_set_tiling(p.handle, 4, 16, 511) == _abi.YO_OK
     p.close()
 
 

@@ -122,8 +122,9 @@ def _sourced_box(nx=72, ny=40, nz=34, npml=6, seed=5):
 
 def test_whole_interior_strip_tilings_bitwise_equal():
     """Tilings that cut the x-shell so the interior strips are whole (flag
-    128), on a grid wide enough for them, give bitwise the fields of the
-    plain tiling (which the test below checks against the oracle)."""
+    128) or run the x-slab tiles in the interior launch (flag 256), on a
+    grid wide enough for them, give bitwise the fields of the plain tiling
+    (which the test below checks against the oracle)."""
     kap, pl, h, w_dt, npml = _sourced_box(nx=150)
     _, nz, ny, nx = kap.shape
     steps = 200
@@ -135,7 +136,7 @@ def test_whole_interior_strip_tilings_bitwise_equal():
     f = FreqSpec(w_dt / dt, 40.0, steps - 60, 60)
     outs = {}
     for rows, zc, fl in [(4, 16, 0), (4, 16, 128), (4, 16, 201), (4, 8, 178), (4, 16, 129),
-                         (4, 4, 232)]:
+                         (4, 4, 232), (4, 16, 329), (4, 16, 456), (4, 8, 256), (4, 16, 304)]:
         say(f"whole-strip tiling=({rows},{zc},{fl})")
         p = Plan(grid, design, steps, [f], [pl], [], device="cuda")
         p.bind()
