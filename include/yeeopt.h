@@ -40,7 +40,8 @@
  *   - Calls taking a hipStream_t are asynchronous on that stream, except
  *     where noted; host arrays passed to them are copied before return.
  *   - Errors: a negative yo_status and a thread-local message from
- *     yo_last_error().  Device faults surface as YO_EHIP.
+ *     yo_last_error().  Device faults surface as YO_EHIP; a run that
+ *     diverged surfaces as YO_EUNSTABLE from yo_finalize (watchdog below).
  */
 #ifndef YEEOPT_H
 #define YEEOPT_H
@@ -61,7 +62,8 @@ enum {
     YO_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. too many ports)   */
     YO_EHIP = -3,          /* HIP runtime error                                 */
     YO_EWORKSPACE = -4,    /* no workspace bound or too small                   */
-    YO_EUNSTABLE = -5,     /* Courant number above the stability limit          */
+    YO_EUNSTABLE = -5,     /* Courant number above the stability limit, or a run
+                              whose phasors came out non-finite (watchdog)      */
     YO_ESTATE = -6         /* call out of order (e.g. gradient before a run)    */
 };
 
@@ -206,7 +208,15 @@ yo_status yo_set_design(yo_plan *plan, const float *dev_C, double beta, yo_strea
  * yo_run: zero the selected right-hand sides' fields, step n_steps times in
  * one launch per step over all of them, then fit the steady-state phasors.
  * The step launches are replayed from a captured HIP graph of `chunk` steps
- * when use_graph != 0. */
+ * when use_graph != 0.
+ *
+ * Watchdog: yo_finalize (the end of yo_run) checks every fitted phasor of
+ * the selected right-hand sides and synchronises `stream` to read the
+ * result.  If any value is Inf or NaN (the fields diverged, e.g. from a
+ * background kappa <= 0 or non-finite fields set through yo_set_fields) it
+ * returns YO_EUNSTABLE, and yo_alpha, yo_gradient and yo_gradient_kappa
+ * return YO_EUNSTABLE until the next yo_reset; yo_get_dft still returns the
+ * phasors for inspection. */
 yo_status yo_run(yo_plan *plan, int which, int chunk, int use_graph, yo_stream stream);
 
 /* Lower-level pieces of yo_run (used by the batch executor and tests). */

@@ -37,7 +37,9 @@ def shared_tiling(plans: Sequence[Plan], rows: int = 4, flags: int = DEFAULT_FLA
 def solve(plans: Sequence[Plan], which: int = YO_BOTH, chunk: int = 100, use_graph: bool = True,
           stream=None, reset: bool = True) -> None:
     """Run every plan of the list to its own step count in shared launches,
-    then finalize them (asynchronous on `stream`)."""
+    then finalize them (the steps are asynchronous on `stream`; finalize
+    synchronises it to read the watchdog and raises YeeOptError(YO_EUNSTABLE)
+    for a plan whose fields diverged)."""
     plans = list(plans)
     if reset:
         for p in plans:

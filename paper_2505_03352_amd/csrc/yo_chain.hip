@@ -53,14 +53,22 @@ __global__ void k_from_ghost(const float *src, float *dst, int ncomp, int c0, in
 }
 
 // Ehat = (g00 Re S + g01 Im S) + i (g10 Re S + g11 Im S): least-squares
-// amplitude/phase from the DFT sums S = sum E^n exp(+i w n dt)
-__global__ void k_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11)
+// amplitude/phase from the DFT sums S = sum E^n exp(+i w n dt).  Any
+// non-finite phasor (all-ones exponent bits) sets *bad to 1: one atomic per
+// wave that holds one.
+__global__ void k_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11, int *bad)
 {
+    unsigned int nonfinite = 0u;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         const float2 s = a[i];
-        a[i] = make_float2(fmaf(g00, s.x, g01 * s.y), fmaf(g10, s.x, g11 * s.y));
+        const float2 e = make_float2(fmaf(g00, s.x, g01 * s.y), fmaf(g10, s.x, g11 * s.y));
+        a[i] = e;
+        nonfinite |= (__float_as_uint(e.x) & 0x7f800000u) == 0x7f800000u;
+        nonfinite |= (__float_as_uint(e.y) & 0x7f800000u) == 0x7f800000u;
     }
+    const unsigned long long m = __ballot(nonfinite != 0u);
+    if ((threadIdx.x & 63) == 0 && m) atomicOr(bad, 1);
 }
 
 // alpha = sum w * Ehat over one port plane; one block, fixed-order tree
@@ -606,12 +614,12 @@ hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int
 }
 
 hipError_t yo_launch_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11,
-                              hipStream_t s)
+                              int *bad, hipStream_t s)
 {
     if (!n) return hipSuccess;
     int blocks = nblk(n);
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(BS), 0, s, a, n, g00, g01, g10, g11);
+    hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(BS), 0, s, a, n, g00, g01, g10, g11, bad);
     return hipGetLastError();
 }
 

@@ -169,8 +169,10 @@ hipError_t yo_launch_to_ghost(const float *dense, float *ghost, int ncomp, int c
                               int ny, int nx, int nxp, hipStream_t s);
 hipError_t yo_launch_from_ghost(const float *ghost, float *dense, int ncomp, int c0, int nc, int nz,
                                 int ny, int nx, int nxp, hipStream_t s);
+// in-place phasor fit of n complex sums; sets *bad to 1 if a result is not
+// finite (*bad is left alone otherwise)
 hipError_t yo_launch_finalize(float2 *a, size_t n, float g00, float g01, float g10, float g11,
-                              hipStream_t s);
+                              int *bad, hipStream_t s);
 hipError_t yo_launch_alpha(const float2 *mon_dft, const float2 *weights, int n, float2 *out,
                            hipStream_t s);
 hipError_t yo_launch_chain_forward(const YoChainBufs &c, const float *C, float beta,

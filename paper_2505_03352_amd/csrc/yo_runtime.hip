@@ -139,6 +139,7 @@ struct yo_plan {
     int steps_done = 0;
     int active = 0;              // which right-hand sides the last reset selected
     bool finalized = false;
+    bool unstable = false;        // the last finalize found non-finite phasors
     hipStream_t cap_stream = nullptr;
     // launch timing: the last tm_n steps of each advance run eagerly, with
     // HIP events around part tm_part's launch (pairs in tm_ev)
@@ -1012,6 +1013,7 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     p->design_set = false;
     p->steps_done = 0;
     p->finalized = false;
+    p->unstable = false;
     return YO_OK;
 }
 
@@ -1205,6 +1207,7 @@ yo_status yo_reset(yo_plan *p, int which, yo_stream stream)
     p->steps_done = 0;
     p->active = which;
     p->finalized = false;
+    p->unstable = false;
     return YO_OK;
 }
 
@@ -1438,13 +1441,23 @@ yo_status yo_finalize(yo_plan *p, int which, yo_stream stream)
     int r0, r1;
     set_out_range(p, which, r0, r1);
     const size_t mt = std::max<size_t>(p->mon_total, 1);
+    // watchdog word of the counter region (after the step counter and the
+    // unbinarity counter); zero bits are the float 0
+    int *bad = wsp<int>(p, p->L.ctr) + 32;
+    HIPCHK(yo_launch_fill(reinterpret_cast<float *>(bad), 1, 0.0f, s));
     for (int r = r0; r < r1; ++r) {
         const int f = r < p->n_fwd ? r / std::max(p->n_src, 1) : (r - p->n_fwd) / p->n_ports;
         const float *m = p->fin.data() + 4 * f;
-        HIPCHK(yo_launch_finalize(box_of(p, r), 3 * p->bsz, m[0], m[1], m[2], m[3], s));
-        HIPCHK(yo_launch_finalize(mon_of(p, r), mt, m[0], m[1], m[2], m[3], s));
+        HIPCHK(yo_launch_finalize(box_of(p, r), 3 * p->bsz, m[0], m[1], m[2], m[3], bad, s));
+        HIPCHK(yo_launch_finalize(mon_of(p, r), mt, m[0], m[1], m[2], m[3], bad, s));
     }
+    int host_bad = 0;
+    HIPCHK(hipMemcpyAsync(&host_bad, bad, sizeof host_bad, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     p->finalized = true;
+    p->unstable = host_bad != 0;
+    if (p->unstable)
+        return fail(YO_EUNSTABLE, "non-finite phasors after %d steps: the fields diverged", p->steps_done);
     return YO_OK;
 }
 
@@ -1461,6 +1474,7 @@ yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
 {
     if (!p || !alpha) return fail(YO_EINVAL, "null argument");
     if (!p->finalized || !(p->active & YO_FORWARD)) return fail(YO_ESTATE, "no finished forward run");
+    if (p->unstable) return fail(YO_EUNSTABLE, "the last run diverged (non-finite phasors)");
     hipStream_t s = (hipStream_t)stream;
     const float2 *w = reinterpret_cast<const float2 *>(p->ws + p->L.port_w.off);
     for (int sidx = 0; sidx < p->n_src; ++sidx)
@@ -1481,6 +1495,7 @@ yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
 static yo_status grad_common(yo_plan *p, const float *coef, float *gbox, float *gmap, hipStream_t s)
 {
     if (!p->finalized || p->active != YO_BOTH) return fail(YO_ESTATE, "needs a finished YO_BOTH run");
+    if (p->unstable) return fail(YO_EUNSTABLE, "the last run diverged (non-finite phasors)");
     YoGradArgs a;
     memset(&a, 0, sizeof a);
     for (int f = 0; f < p->n_freq; ++f) {

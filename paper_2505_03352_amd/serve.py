@@ -17,7 +17,9 @@ wavelengths, alpha and the gradient dF/dC.  Requests arrive over time
     boundaries, so requests that arrive while others run overlap with them
     on the GPU;
   * on completion, enqueues finalize, alpha and the gradient, and releases
-    the request's memory once they are done.
+    the request's memory once they are done; a request whose solve fails
+    (e.g. fields that diverged) leaves with its `error` set and no result,
+    and the others go on.
 
 Each request keeps its own fields, counters and results, and a right-hand
 side's update does not depend on what else shares the launch, so a result
@@ -101,6 +103,7 @@ class ServeStats:
     max_active: int
     peak_bytes: int
     cell_updates: float = 0.0
+    n_failed: int = 0
     latencies: List[float] = field(default_factory=list)
 
     def as_dict(self) -> dict:
@@ -141,6 +144,7 @@ class Scheduler:
         cell_updates = 0.0
         done: List[Request] = []
         rejected: List[Request] = []
+        failed: List[Request] = []
         pool = cf.ThreadPoolExecutor(max_workers=max(1, self.prep_workers)) if self.prep_workers else None
         self.ex.begin(self.clock)
 
@@ -159,16 +163,20 @@ class Scheduler:
                 # retire finished work whose results are ready
                 for j in list(retiring):
                     if self.ex.ready(j):
-                        j.req.result = self.ex.collect(j)
+                        try:
+                            j.req.result = self.ex.collect(j)
+                        except Exception as e:      # noqa: BLE001  (a solve that failed)
+                            j.req.result = None
+                            j.req.error = f"solve: {e}"
                         t = self.ex.done_time(j)
                         j.req.t_done = t if t is not None else self.clock.now()
                         self.ex.release(j)
                         used -= j.footprint
                         retiring.remove(j)
-                        done.append(j.req)
+                        (failed if j.req.error else done).append(j.req)
                         if self.on_done is not None:
                             self.on_done(j.req)
-                        self._log("done", j.req.rid)
+                        self._log("fail" if j.req.error else "done", j.req.rid)
                 # admissions, FIFO
                 while queue and len(active) + len(retiring) < self.max_slots:
                     r, fut = queue[0]
@@ -234,7 +242,8 @@ class Scheduler:
             p50_s=percentile(lat, 50), p99_s=percentile(lat, 99),
             mean_s=float(np.mean(lat)) if lat else float("nan"),
             throughput_per_h=3600.0 * len(done) / makespan if makespan > 0 else float("nan"),
-            max_active=max_active, peak_bytes=peak, cell_updates=cell_updates, latencies=lat)
+            max_active=max_active, peak_bytes=peak, cell_updates=cell_updates, n_failed=len(failed),
+            latencies=lat)
 
 
 class _Done:
@@ -366,15 +375,19 @@ class GpuExecutor:
             self._inflight.popleft().synchronize()
 
     def finish(self, job: Job):
+        from ._abi import YeeOptError
         torch = self.torch
         plan = job.state["plan"]
         with torch.cuda.stream(self.compute):
-            plan.finalize(3, self.compute)
-            a = plan.alpha(self.compute)
-            g = plan.gradient(torch.conj(a), self.compute)
+            try:
+                plan.finalize(3, self.compute)
+                a = plan.alpha(self.compute)
+                g = plan.gradient(torch.conj(a), self.compute)
+                job.state["out"] = (a, g)
+            except YeeOptError as e:         # e.g. the watchdog: the fields diverged
+                job.state["error"] = e
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(self.compute)
-        job.state["out"] = (a, g)
         job.handle = ev
 
     def ready(self, job: Job) -> bool:
@@ -387,6 +400,8 @@ class GpuExecutor:
         return self.anchor + self.start_event.elapsed_time(job.handle) / 1e3
 
     def collect(self, job: Job):
+        if job.state.get("error") is not None:
+            raise job.state["error"]
         a, g = job.state["out"]
         return dict(alpha=a.cpu().numpy(), grad=g.cpu().numpy())
 

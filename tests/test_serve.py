@@ -184,3 +184,29 @@ def test_completion_callback_sees_every_finished_request():
     assert st.n_done == 6
     assert sorted(rid for rid, _ in seen) == list(range(6))
     assert all(ok for _, ok in seen)
+
+
+def test_failed_solve_is_reported_and_the_others_finish():
+    """A request whose solve fails (the library's watchdog raises from
+    finalize when the fields diverged) leaves with its error, frees its
+    memory, and does not count as done; the rest complete."""
+    class Failing(FakeExecutor):
+        def collect(self, job):
+            if job.req.rid == 2:
+                raise RuntimeError("YO_EUNSTABLE: non-finite phasors")
+            return job.req.rid
+
+    reqs = make([(0.0, (200_000, 100, 10)) for _ in range(5)])
+    clock = FakeClock()
+    ex = Failing(clock)
+    seen = []
+    sch = Scheduler(ex, max_slots=2, hbm_budget=25, chunk=20, clock=clock, prep_workers=0,
+                    on_done=lambda r: seen.append(r.rid))
+    st = sch.run(reqs)
+    assert st.n_done == 4 and st.n_failed == 1 and st.n_rejected == 0
+    assert "solve" in reqs[2].error and "EUNSTABLE" in reqs[2].error
+    assert reqs[2].result is None
+    assert [r.result for r in reqs if r.rid != 2] == [0, 1, 3, 4]
+    assert sorted(ex.released) == list(range(5))
+    assert sorted(seen) == list(range(5))
+    assert len(st.latencies) == 4
