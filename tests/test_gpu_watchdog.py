@@ -88,3 +88,34 @@ def test_forward_only_run_that_diverged_is_reported():
     p.run(YO_FORWARD)
     assert np.isfinite(p.alpha().cpu().numpy()).all()
     p.close()
+
+
+def test_diverged_plan_in_a_shared_launch_leaves_the_others_alone():
+    """Two plans stepped in the same launches, one from NaN fields: only
+    that plan's finalize reports YO_EUNSTABLE, and the clean plan's alpha
+    and gradient are bitwise those of its run alone."""
+    from paper_2505_03352_amd import YeeOptError
+    from paper_2505_03352_amd.plan import advance_many, plan_for
+    dev = configs.micro(n_steps=500)
+    a = plan_for(dev)
+    b = plan_for(dev)
+    a.run(3)
+    a0 = a.alpha().cpu().numpy()
+    g0 = a.gradient(torch.conj(a.alpha())).cpu().numpy()
+    say("watchdog: clean and diverged plan in shared launches")
+    a.reset(3)
+    b.reset(3)
+    E, H = b.get_fields(0)
+    E.fill_(float("nan"))
+    b.set_fields(0, E, H)
+    advance_many([a, b], [3, 3], dev.n_steps, chunk=100, use_graph=True)
+    a.finalize(3)
+    with pytest.raises(YeeOptError) as e:
+        b.finalize(3)
+    assert e.value.status == YO_EUNSTABLE
+    a1 = a.alpha().cpu().numpy()
+    g1 = a.gradient(torch.conj(a.alpha())).cpu().numpy()
+    a.close()
+    b.close()
+    assert np.array_equal(a0, a1)
+    assert np.array_equal(g0, g1)
