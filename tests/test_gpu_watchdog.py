@@ -119,3 +119,27 @@ def test_diverged_plan_in_a_shared_launch_leaves_the_others_alone():
     b.close()
     assert np.array_equal(a0, a1)
     assert np.array_equal(g0, g1)
+
+
+def test_negative_background_kappa_diverges_and_is_reported():
+    """A block of negative kappa (negative permittivity, no dispersion) next
+    to the source makes the scheme grow without bound (the FP64 oracle's
+    fields on this device reach 1e28 after 100 steps and 1e64 after 200);
+    the run returns YO_EUNSTABLE instead of NaN coefficients."""
+    from paper_2505_03352_amd import YeeOptError
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro(n_steps=600)
+    kb = dev.kappa_bg.copy()
+    x0, y0, z0, bx, by, bz = dev.dft_box()
+    assert 8 <= x0                      # the block [6, 8) lies before the design box in x
+    kb[:, 7:11, 8:13, 6:8] = -0.3
+    dev.kappa_bg = kb
+    p = plan_for(dev)
+    say("watchdog: negative background kappa")
+    with pytest.raises(YeeOptError) as e:
+        p.run(3)
+    assert e.value.status == YO_EUNSTABLE
+    with pytest.raises(YeeOptError) as e:
+        p.alpha()
+    assert e.value.status == YO_EUNSTABLE
+    p.close()
