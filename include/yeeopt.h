@@ -258,13 +258,16 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);
 
 /* Modal coefficients (Appendix A) of the forward right-hand sides:
- * dev_alpha complex64 [n_src][n_ports][n_freq]. */
+ * dev_alpha complex64 [n_src][n_ports][n_freq]; may be null when n_src or
+ * n_ports is 0 (nothing is written). */
 yo_status yo_alpha(const yo_plan *plan, float *dev_alpha, yo_stream stream);
 
 /* Gradient (Eq. (1) and the chain's VJP): dev_coef = dF/dalpha (holomorphic
  * Wirtinger derivative, e.g. conj(alpha) for F = |alpha|^2), complex64
  * [n_src][n_ports][n_freq]; dev_dFdC FP32 [nc][mc] receives
- * sum 2 Re(coef dalpha/dC).  Needs a finished YO_BOTH run and yo_set_design. */
+ * sum 2 Re(coef dalpha/dC).  Needs a finished YO_BOTH run and yo_set_design.
+ * With n_src or n_ports 0 there are no coefficients: dev_coef may be null
+ * and the gradient is zero. */
 yo_status yo_gradient(yo_plan *plan, const float *dev_coef, float *dev_dFdC, yo_stream stream);
 
 /* Same, stopping after Eq. (1): dF/dkappa on the DFT box, FP32 [3][bz][by][bx]

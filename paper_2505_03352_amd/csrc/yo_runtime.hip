@@ -1472,7 +1472,8 @@ yo_status yo_run(yo_plan *p, int which, int chunk, int use_graph, yo_stream stre
 
 yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
 {
-    if (!p || !alpha) return fail(YO_EINVAL, "null argument");
+    // with no sources or no ports the array is empty and may be null
+    if (!p || (!alpha && p->n_src > 0 && p->n_ports > 0)) return fail(YO_EINVAL, "null argument");
     if (!p->finalized || !(p->active & YO_FORWARD)) return fail(YO_ESTATE, "no finished forward run");
     if (p->unstable) return fail(YO_EUNSTABLE, "the last run diverged (non-finite phasors)");
     hipStream_t s = (hipStream_t)stream;
@@ -1524,13 +1525,14 @@ static yo_status grad_common(yo_plan *p, const float *coef, float *gbox, float *
 
 yo_status yo_gradient_kappa(yo_plan *p, const float *coef, float *g, yo_stream stream)
 {
-    if (!p || !coef || !g) return fail(YO_EINVAL, "null argument");
+    if (!p || !g || (!coef && p->n_src > 0 && p->n_ports > 0)) return fail(YO_EINVAL, "null argument");
     return grad_common(p, coef, g, nullptr, (hipStream_t)stream);
 }
 
 yo_status yo_gradient(yo_plan *p, const float *coef, float *dFdC, yo_stream stream)
 {
-    if (!p || !coef || !dFdC) return fail(YO_EINVAL, "null argument");
+    // with no sources or no ports there is no coefficient (the gradient is 0)
+    if (!p || !dFdC || (!coef && p->n_src > 0 && p->n_ports > 0)) return fail(YO_EINVAL, "null argument");
     if (!p->design_set) return fail(YO_ESTATE, "yo_set_design first");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(yo_launch_fill(p->chain.gmap, 4 * (size_t)p->G0 * p->G1, 0.0f, s));
