@@ -38,9 +38,22 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(sha: str, launch_bytes_alg: float):
+# yo_set_tiling flag bits that change the interior launch's work split (the
+# x-shell layouts 1, 128 and 256, 8 waves per block, cooperative interior
+# blocks, no interior prefetch); the shell-only bits 4, 8 and 64 leave it alone
+INTERIOR_SPLIT_BITS = 1 | 2 | 16 | 32 | 128 | 256
+
+
+def interior_split(tiling) -> str:
+    """rows,z-chunk,interior flag bits of a (rows, zchunk, flags) tiling."""
+    rows, zc, flags = tiling
+    return f"{rows},{zc},{flags & INTERIOR_SPLIT_BITS}"
+
+
+def read_traffic(sha: str, split) -> float:
     """HBM bytes per launch from the committed counter summary, or None if
-    the kernel changed since the counters were taken."""
+    the kernel changed since the counters were taken or the interior launch
+    is split differently from the run they were taken on."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -48,7 +61,7 @@ def read_traffic(sha: str, launch_bytes_alg: float):
                 if "=" in line and not line.startswith("#"):
                     k, v = line.strip().split("=", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("kernel_sha") != sha:
+        if kv.get("kernel_sha") != sha or split is None or kv.get("interior_split") != split:
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -204,7 +217,8 @@ def main():
     torch.cuda.synchronize()
     achieved = k_bytes / (k_ms / 1e3) / 1e9
     sha = kernel_sha()
-    traffic = read_traffic(sha, k_bytes)
+    tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else getattr(plan, "tiling", None)
+    traffic = read_traffic(sha, interior_split(tiling) if tiling else None)
     log(f"interior kernel {k_ms:.4f} ms/launch over {k_n} launches, {achieved:.0f} GB/s algorithmic; "
         f"CPML shell {p_ms:.3f} ms/launch ({p_bytes / max(p_ms / 1e3, 1e-12) / 1e9:.0f} GB/s)")
 
