@@ -217,7 +217,8 @@ def main():
     torch.cuda.synchronize()
     achieved = k_bytes / (k_ms / 1e3) / 1e9
     sha = kernel_sha()
-    tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else getattr(plan, "tiling", None)
+    tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else \
+        getattr(plan, "tiling", None)
     traffic = read_traffic(sha, interior_split(tiling) if tiling else None)
     log(f"interior kernel {k_ms:.4f} ms/launch over {k_n} launches, {achieved:.0f} GB/s algorithmic; "
         f"CPML shell {p_ms:.3f} ms/launch ({p_bytes / max(p_ms / 1e3, 1e-12) / 1e9:.0f} GB/s)")
