@@ -280,7 +280,7 @@ def bench_batch(args):
     log("batch: " + ", ".join(f"{d.nx}x{d.ny}x{d.nz}/{d.n_steps}" for d in devs))
     cells = sum(2 * d.cells * d.n_steps for d in devs)
     plans = [plan_for(d, device="cuda:0") for d in devs]
-    batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS, zchunk=16)
+    batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS, zchunk=batch.DEFAULT_ZCHUNK)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.solve(plans, chunk=args.chunk, use_graph=True)
@@ -385,7 +385,7 @@ def bench_batch_fd(args):
         flat = rng.choice(dev.C.size, size=16, replace=False)
         idx = [np.unravel_index(k, dev.C.shape) for k in flat]
         p = plan_for(dev, device="cuda:0")
-        batch.shared_tiling([p], 4, batch.DEFAULT_FLAGS, zchunk=16)
+        batch.shared_tiling([p], 4, batch.DEFAULT_FLAGS, zchunk=batch.DEFAULT_ZCHUNK)
         C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0").requires_grad_(True)
         a = fn.modal_coefficients(C, p, dev.beta, chunk=args.chunk)
         (a.abs() ** 2).sum().backward()
@@ -397,7 +397,7 @@ def bench_batch_fd(args):
                 Cp = dev.C.copy()
                 Cp[k] += sgn * h
                 plans.append(plan_for(dev, device="cuda:0", C=Cp))
-        batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS, zchunk=16)
+        batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS, zchunk=batch.DEFAULT_ZCHUNK)
         batch.solve(plans, which=YO_FORWARD, chunk=args.chunk)
         vals = [float((q.alpha().abs() ** 2).sum()) for q in plans]
         for q in plans:

@@ -27,9 +27,9 @@ from ._abi import YO_BOTH
 ROWS = 4
 # shared settings: (z-planes per tile, flags from {1: full 62-cell x-shell strips,
 # 128: x-shell strips sized so the interior strips are whole, 2: 8 waves per
-# block}).  10 planes cut the 80 interior planes of a 96-plane grid with an
-# 8-cell CPML into whole chunks: 0.950 against 0.969 ms per step for 16 on the
-# 320x240x96 device.  (Flag 256, the x-slab tiles in the interior launch,
+# block}).  10 planes split the 79 planes between the z-slabs of a 96-plane
+# grid with an 8-cell CPML into 8 tiles instead of 5: more, shorter tiles,
+# 0.950 against 0.969 ms per step for 16 on the 320x240x96 device.  (Flag 256, the x-slab tiles in the interior launch,
 # measured 6-10 % slower per step there and is left out of the sweep.)
 SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b) for z in (8, 10, 16, 32) for a in (0, 1, 128)
                                             for b in (0, 2))

@@ -19,10 +19,12 @@ from ._abi import YO_BOTH
 from .plan import Plan, advance_many
 
 
-# x-shell strips that leave whole interior strips, CPML shell with
-# per-class code and no prefetch: the split the autotuner picks on the
-# realistic device
+# Split for shared launches of uneven designs: x-shell strips that leave
+# whole interior strips, CPML shell with per-class code and no prefetch, 10
+# z-planes per tile (8 designs of 128..320 x 96..240 x 64..96 cells: 9.74 s
+# against 9.91 s with 16 planes and 10.02 s with flags 73)
 DEFAULT_FLAGS = 200
+DEFAULT_ZCHUNK = 10
 
 
 def shared_tiling(plans: Sequence[Plan], rows: int = 4, flags: int = DEFAULT_FLAGS,

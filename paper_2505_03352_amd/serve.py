@@ -292,9 +292,10 @@ class GpuExecutor:
     stepping of admitted work on the compute stream; the compute stream
     waits for a job's set-up before its first chunk.  At most two chunks
     are in flight, which keeps admission decisions close to the GPU's
-    progress."""
+    progress.  The default split is the batch executor's (rows 4, 10
+    z-planes per tile, flags 200), since admitted requests share launches."""
 
-    def __init__(self, build: Callable, device="cuda:0", tiling=(4, 16, 200), use_graph=False,
+    def __init__(self, build: Callable, device="cuda:0", tiling=(4, 10, 200), use_graph=False,
                  chunk: int = 100, pulse_multi: bool = False):
         import torch
         from . import _abi  # noqa: F401  (fails loudly without the library)
