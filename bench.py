@@ -1,12 +1,19 @@
 #!/usr/bin/env python
-"""Benchmark: adjoint gradients of the 320x240x96 realistic device on one MI355X.
+"""Benchmark of the adjoint-FDTD hot path on one MI355X.
 
-One step = the whole hot path once: controls -> kappa (filter, projection,
-sub-pixel averaging), forward and adjoint time stepping of all right-hand
-sides (3 wavelengths x (1 forward + 1 adjoint), 10 000 Yee steps each) with
-running DFT, modal coefficients, and the Eq. (1) gradient pulled back to
-dF/dC; then a small descent step on the controls.  Inputs are seeded
-synthetic SOI-like devices, resident on the GPU before timing starts.
+Headline (default, `--workload multiport`): the 600x400x120 1-to-4
+splitter-like device, 5 wavelengths x (1 forward + 4 adjoint port sources) =
+25 right-hand sides batched in the same launches, 20 000 Yee steps each.
+One bench step is a fixed block of `--block` (200) whole Yee steps of all 25
+right-hand sides of that solve (the interior and CPML-shell step launches,
+the source injection, and in the last four periods the running DFT): W
+warm-up blocks, then K timed blocks, all inside one forward+adjoint solve
+that then runs to its end and is finished with the modal coefficients and
+the Eq. (1) gradient pulled back to dF/dC.  That whole gradient, from
+set_design to dF/dC, is timed too (gradients/hour).  The 320x240x96
+realistic device's whole gradients (6 right-hand sides, 10 000 steps) are
+timed after it and reported as extra keys.  Inputs are seeded synthetic
+SOI-like devices, resident on the GPU before timing starts.
 
 Prints ONE JSON line on stdout.  Diagnostics go to stderr.
 """
@@ -23,7 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Gcell-updates/s + % HBM peak; adjoint gradients/hour; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2505_03352_amd/csrc/yo_step.hip", "paper_2505_03352_amd/csrc/yo_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "yee_step_interior_realistic_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+PART_NAMES = ("interior", "shell")
 
 
 def log(*a):
@@ -38,43 +46,80 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-# yo_set_tiling flag bits that change the interior launch's work split (the
-# x-shell layouts 1, 128 and 256, 8 waves per block, cooperative interior
-# blocks, no interior prefetch); the shell-only bits 4, 8 and 64 leave it alone
-INTERIOR_SPLIT_BITS = 1 | 2 | 16 | 32 | 128 | 256
+# yo_set_tiling flag bits that change each launch's work split: the interior
+# (x-shell layouts 1, 128 and 256, 8 waves per block, cooperative interior
+# blocks, no interior prefetch) and the CPML shell (the x-shell layouts, 8
+# waves per block, cooperative shell blocks, per-class code, no shell prefetch)
+SPLIT_BITS = (1 | 2 | 16 | 32 | 128 | 256, 1 | 2 | 4 | 8 | 64 | 128 | 256)
 
 
-def interior_split(tiling) -> str:
-    """rows,z-chunk,interior flag bits of a (rows, zchunk, flags) tiling."""
+def part_split(tiling, part: int) -> str:
+    """rows,z-chunk,flag bits of a (rows, zchunk, flags) tiling that shape
+    launch `part` (0 interior, 1 CPML shell)."""
     rows, zc, flags = tiling
-    return f"{rows},{zc},{flags & INTERIOR_SPLIT_BITS}"
+    return f"{rows},{zc},{flags & SPLIT_BITS[part]}"
 
 
-def read_traffic(sha: str, split) -> float:
-    """HBM bytes per launch from the committed counter summary, or None if
-    the kernel changed since the counters were taken or the interior launch
-    is split differently from the run they were taken on."""
+def traffic_file(part: int, workload: str) -> str:
+    return os.path.join(PROFILES, f"yee_step_{PART_NAMES[part]}_{workload}_traffic.txt")
+
+
+def read_traffic(path: str, sha: str, split) -> float:
+    """HBM bytes per launch from a committed counter summary, or None if the
+    file is missing, the kernel changed since the counters were taken, or the
+    launch is split differently from the run they were taken on."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if "=" in line and not line.startswith("#"):
                     k, v = line.strip().split("=", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("kernel_sha") != sha or split is None or kv.get("interior_split") != split:
+        if kv.get("kernel_sha") != sha or split is None or kv.get("split") != split:
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
 
+def lscpu_summary() -> dict:
+    """Model, sockets and physical cores of this host (lscpu), and the CPUs
+    this process may run on."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+
+    def num(k):
+        try:
+            return int(info.get(k, ""))
+        except ValueError:
+            return None
+    sockets, per = num("Socket(s)"), num("Core(s) per socket")
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"model": info.get("Model name"), "sockets": sockets, "cores_per_socket": per,
+            "threads_per_core": num("Thread(s) per core"),
+            "physical_cores": sockets * per if sockets and per else None,
+            "logical_cpus": num("CPU(s)"), "cpus_allowed": allowed,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(dev, target_s: float):
     """The FP64 oracle on this host's cores: one right-hand side of the same
-    grid, a bounded number of steps."""
-    import numpy as np
+    grid (CPML, source, no DFT window) for a bounded number of steps, at one
+    thread and at all the physical cores this process may use."""
     from oracle import adjoint, chain, fdtd, ports
     kap, _ = chain.kappa(dev)
-    lam = dev.wavelengths[1] if len(dev.wavelengths) > 1 else dev.wavelengths[0]
+    lam = dev.wavelengths[len(dev.wavelengths) // 2]
     src = dev.sources[0]
     J = ports.source_current(src.h)
 
@@ -84,34 +129,52 @@ def cpu_baseline(dev, target_s: float):
         fdtd.run(prm, kap, src_plane=src.plane, src_j=J)
         return time.perf_counter() - t
 
-    # the per-step cost from two short runs (their difference drops the
-    # set-up every run pays), then one run sized to about target_s
-    t10, t30 = run(10), run(30)
-    per_step = max((t30 - t10) / 20.0, 1e-4)
-    n = int(max(30, min(5000, (target_s - t10) / per_step)))
-    t = run(n)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": dev.cells * n / t / 1e9, "unit": "Gcell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{dev.nx}x{dev.ny}x{dev.nz} grid, 1 right-hand side, {n} steps, FP64 "
-                      f"(CPML, source, no DFT window), {t:.1f} s, OMP_NUM_THREADS={threads}"}
+    cpu = lscpu_summary()
+    phys = cpu["physical_cores"] or cpu["cpus_allowed"]
+    # all physical cores, but no more than this process's CPU share
+    cap = int(os.environ.get("OMP_NUM_THREADS") or cpu["cpus_allowed"])
+    full = max(1, min(phys, cpu["cpus_allowed"], cap))
+
+    def measure(threads, budget):
+        used = fdtd.set_threads(threads)
+        # the per-step cost from two short runs (their difference drops the
+        # set-up every run pays), then one run sized to about `budget`
+        t2, t6 = run(2), run(6)
+        per_step = max((t6 - t2) / 4.0, 1e-4)
+        n = int(max(6, min(5000, (budget - t2) / per_step)))
+        t = run(n)
+        return {"value": dev.cells * n / t / 1e9, "unit": "Gcell-updates/s", "cores": used,
+                "kind": "oracle",
+                "sample": f"{dev.nx}x{dev.ny}x{dev.nz} grid, 1 right-hand side, {n} steps, FP64 "
+                          f"(CPML, source, no DFT window), {t:.1f} s on {used} thread(s)"}
+
+    one = measure(1, 0.4 * target_s)
+    out = measure(full, 0.6 * target_s)
+    fdtd.set_threads(cap)
+    out["one_thread"] = one
+    out["host"] = cpu
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--chunk", type=int, default=100)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--block", type=int, default=200,
+                    help="multiport: Yee steps per bench step (an even divisor of 20000)")
+    ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-realistic", action="store_true",
+                    help="multiport: leave out the realistic device's whole gradients")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="plain launches instead of HIP-graph replays (for counter collection)")
-    ap.add_argument("--workload", choices=("realistic", "batch", "serving", "optimize", "broadband",
+    ap.add_argument("--workload", choices=("multiport", "batch", "serving", "optimize", "broadband",
                                            "batch-fd"),
-                    default="realistic",
-                    help="realistic: the headline line; batch / serving: the batched and served "
+                    default="multiport",
+                    help="multiport: the headline line; batch / serving: the batched and served "
                          "forms against one-at-a-time solves (their own JSON line)")
     ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
     ap.add_argument("--no-baseline", action="store_true",
@@ -150,18 +213,12 @@ def main():
     if args.workload == "batch-fd":
         return bench_batch_fd(args)
 
-    import torch
-    from paper_2505_03352_amd import YO_BOTH, autotune
-    from paper_2505_03352_amd.plan import plan_for
-    from workloads import configs
+    return bench_headline(args)
 
-    torch.cuda.set_device(0)
-    dev = configs.realistic()
-    log(f"workload {dev.name}: {dev.nx}x{dev.ny}x{dev.nz}, {len(dev.wavelengths)} wavelengths, "
-        f"{dev.n_steps} steps")
-    plan = plan_for(dev, device="cuda:0")
-    # a plain copy of known size, its source pushed out of the 256 MB
-    # last-level cache first: the reference the HBM counters are scaled by
+
+def calibration_copy(torch):
+    """A plain 1 GiB device copy, its source pushed out of the 256 MB
+    last-level cache first: the reference the HBM counters are scaled by."""
     cal_bytes = 1 << 30
     cal_src = torch.ones(cal_bytes // 4, dtype=torch.float32, device="cuda:0")
     evict = torch.zeros((512 << 20) // 4, dtype=torch.float32, device="cuda:0")
@@ -171,57 +228,176 @@ def main():
     torch.cuda.synchronize()
     log(f"calibration copy: {cal_bytes} bytes read, {cal_bytes} bytes written")
     del cal_src, cal_dst, evict
-    tuned = None
-    if not args.no_autotune:
-        tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
-        log(f"autotune: {tuned}")
-    C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
-    beta = dev.beta
 
-    def step(Cc):
-        plan.set_design(Cc, beta)
+
+def part_rooflines(plan, timed, tiling, workload, sha):
+    """Per launch part: HIP-event duration inside the timed region, the
+    part's algorithmic bytes per launch, and the committed counter figure
+    when it belongs to this kernel and split."""
+    out = []
+    for part in (0, 1):
+        ms, n = timed[part]
+        _, b, cells = plan.time_kernel(part, 1)
+        ach = b / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        out.append({"kernel": f"k_yee_step {PART_NAMES[part]} tiles", "part": PART_NAMES[part],
+                    "ms_per_launch": round(ms, 4), "launches_timed": n,
+                    "bytes_per_launch": b, "cell_updates_per_launch": cells,
+                    "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": read_traffic(traffic_file(part, workload), sha,
+                                            part_split(tiling, part))})
+    return out
+
+
+def roofline_of(parts):
+    """The bench line's roofline object: the launch that takes the most time
+    per step (each part launches once per step), with the other beside it."""
+    dom = max(parts, key=lambda q: q["ms_per_launch"])
+    return {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom["frac"], "traffic": dom["traffic"], "kernel": dom["kernel"],
+            "bytes_per_launch": dom["bytes_per_launch"], "ms_per_launch": dom["ms_per_launch"],
+            "launches_timed": dom["launches_timed"], "parts": parts}
+
+
+def realistic_gradients(args, torch, n_timed=1):
+    """Whole gradients of the 320x240x96 realistic device (6 right-hand
+    sides x 10 000 steps): set_design, forward+adjoint runs, alpha, dF/dC."""
+    from paper_2505_03352_amd import YO_BOTH, autotune
+    from paper_2505_03352_amd.plan import plan_for
+    from workloads import configs
+    dev = configs.realistic()
+    plan = plan_for(dev, device="cuda:0")
+    tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
+    tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"])
+    C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
+
+    def grad():
+        plan.set_design(C, dev.beta)
         plan.run(YO_BOTH, chunk=args.chunk, use_graph=not args.eager)
         a = plan.alpha()
-        g = plan.gradient(torch.conj(a))
-        Cn = torch.clamp(Cc + 1e-3 * g / (g.abs().max() + 1e-30), 0.0, 1.0)
-        return a, g, Cn
+        return plan.gradient(torch.conj(a))
 
-    # HIP events on the solve's stream around the interior-tile launches of
-    # the last 100 steps of each solve (those steps run as plain launches)
-    plan.set_timing(0, 100)
-    for _ in range(args.warmup):
-        _, _, C = step(C)
+    grad()
+    # HIP events around both parts' launches of the last 100 steps of each solve
+    plan.set_timing(2, 100)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a, g, C = step(C)
+    for _ in range(n_timed):
+        grad()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
-    cells_per_step = plan.n_rhs * dev.cells * dev.n_steps
-    value = cells_per_step / (ms / 1e3) / 1e9
-    bytes_model, _ = plan.model_bytes(YO_BOTH)
-    eff_gbs = bytes_model * dev.n_steps / (ms / 1e3) / 1e9
-    log(f"{ms:.1f} ms per gradient, {value:.1f} Gcell-updates/s, |alpha|={a.abs().cpu().numpy().ravel()}")
-
-    # roofline of the dominant kernel (the interior step kernel): its launches
-    # timed inside the timed region, and its algorithmic bytes per launch
-    k_ms, k_n = plan.timing()
+    dt = (time.perf_counter() - t0) / n_timed
+    timed = [plan.timing(0), plan.timing(1)]
     plan.set_timing(0, 0)
     plan.reset(YO_BOTH)
     plan.advance(YO_BOTH, 4)
-    _, k_bytes, k_cells = plan.time_kernel(0, 1)
-    # the CPML shell launch, for the log
-    plan.time_kernel(1, 2)
-    p_ms, p_bytes, _ = plan.time_kernel(1, 30)
+    parts = part_rooflines(plan, timed, tiling, "realistic", kernel_sha())
+    cells = plan.n_rhs * dev.cells * dev.n_steps
+    plan.close()
+    log(f"realistic: {dt:.2f} s per gradient, {cells / dt / 1e9:.1f} Gcell-updates/s; " +
+        "; ".join(f"{q['part']} {q['ms_per_launch']:.4f} ms/launch {q['achieved']:.0f} GB/s"
+                  for q in parts))
+    return {"workload": "realistic: 320x240x96 cells at 20 nm (CPML 8), 100x100 design/controls, "
+                        "r=3, beta=8, 1.50/1.55/1.60 um, 1 forward + 1 adjoint each (6 right-hand "
+                        "sides), 10000 steps; whole gradient (set_design, runs, alpha, dF/dC)",
+            "gcell_updates_per_s": round(cells / dt / 1e9, 3), "s_per_gradient": round(dt, 3),
+            "gradients_per_hour": round(3600.0 / dt, 1), "gradients_timed": n_timed,
+            "tiling": list(tiling), "roofline": roofline_of(parts)}
+
+
+def bench_headline(args):
+    import numpy as np
+    import torch
+    from paper_2505_03352_amd import YO_BOTH, autotune
+    from paper_2505_03352_amd.plan import advance_many, plan_for
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    dev = configs.multiport()
+    block = args.block
+    tail = 8                        # timed plain-launch steps at the end of each block
+    chunk = (block - tail) // 2     # two graph replays per block
+    if block < 2 * tail or (block - tail) % 2 or dev.n_steps % block:
+        raise SystemExit(f"--block must be an even divisor of {dev.n_steps} of at least {2 * tail}")
+    n_blocks = dev.n_steps // block
+    log(f"workload {dev.name}: {dev.nx}x{dev.ny}x{dev.nz}, {dev.n_freq} wavelengths, "
+        f"{len(dev.ports)} ports, {dev.n_steps} steps; bench step = {block} Yee steps of all "
+        f"right-hand sides ({n_blocks} per solve)")
+    plan = plan_for(dev, device="cuda:0")
+    calibration_copy(torch)
+    tuned = None
+    if not args.no_autotune:
+        tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
+        log(f"autotune: rows {tuned['rows']} zchunk {tuned['zchunk']} flags {tuned['flags']} "
+            f"({tuned['ms_per_step']:.3f} ms per step)")
+    tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else (4, 16, 0)
+    C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
+    state = {"block": 0, "grads": []}
+
+    def begin():
+        torch.cuda.synchronize()
+        state["t_grad"] = time.perf_counter()
+        plan.set_design(C, dev.beta)
+        plan.reset(YO_BOTH)
+        state["block"] = 0
+
+    def finish():
+        # the rest of the solve in pieces of 2000 steps, a progress line after each
+        done = state["block"] * block
+        while done < dev.n_steps:
+            k = min(2000, dev.n_steps - done)
+            advance_many([plan], [YO_BOTH], k, chunk=args.chunk, use_graph=not args.eager)
+            done += k
+            torch.cuda.synchronize()
+            log(f"  solve: {done}/{dev.n_steps} steps")
+        plan.finalize(YO_BOTH)
+        a = plan.alpha()
+        g = plan.gradient(torch.conj(a))
+        torch.cuda.synchronize()
+        state["grads"].append(time.perf_counter() - state["t_grad"])
+        state["alpha"] = a
+        state["g"] = g
+
+    def bench_step():
+        if state["block"] == n_blocks:       # past the end of a solve: the next one
+            finish()
+            begin()
+        advance_many([plan], [YO_BOTH], block, chunk=chunk, use_graph=not args.eager)
+        state["block"] += 1
+
+    begin()
+    for _ in range(args.warmup):
+        bench_step()
     torch.cuda.synchronize()
-    achieved = k_bytes / (k_ms / 1e3) / 1e9
+    # HIP events around both parts' launches of the last `tail` steps of each block
+    plan.set_timing(2, tail)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bench_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timed = [plan.timing(0), plan.timing(1)]
+    plan.set_timing(0, 0)
+    ms = (t1 - t0) / args.steps * 1e3
+    cells_per_step = plan.n_rhs * dev.cells * block
+    value = cells_per_step / (ms / 1e3) / 1e9
+    log(f"{ms:.1f} ms per block of {block} steps, {value:.2f} Gcell-updates/s")
+    finish()
+    s_grad = state["grads"][0]
+    alpha = state["alpha"].abs().cpu().numpy()
+    log(f"whole gradient {s_grad:.2f} s ({3600.0 / s_grad:.1f}/h); |alpha| "
+        f"{np.round(alpha.ravel(), 4).tolist()}")
+    bytes_model, _ = plan.model_bytes(YO_BOTH)
+    eff_gbs = bytes_model * block / (ms / 1e3) / 1e9
+    plan.reset(YO_BOTH)
+    plan.advance(YO_BOTH, 4)
     sha = kernel_sha()
-    tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else \
-        getattr(plan, "tiling", None)
-    traffic = read_traffic(sha, interior_split(tiling) if tiling else None)
-    log(f"interior kernel {k_ms:.4f} ms/launch over {k_n} launches, {achieved:.0f} GB/s algorithmic; "
-        f"CPML shell {p_ms:.3f} ms/launch ({p_bytes / max(p_ms / 1e3, 1e-12) / 1e9:.0f} GB/s)")
+    parts = part_rooflines(plan, timed, tiling, "multiport", sha)
+    for q in parts:
+        log(f"{q['part']}: {q['ms_per_launch']:.4f} ms/launch over {q['launches_timed']} launches, "
+            f"{q['bytes_per_launch'] / 1e9:.3f} GB algorithmic, {q['achieved']:.0f} GB/s "
+            f"({q['frac']:.3f} of peak)")
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -236,26 +412,32 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "realistic: 320x240x96 cells at 20 nm (CPML 8), 220 nm Si slab in "
-                               "SiO2, 100x100 design/controls, r=3, beta=8, wavelengths "
-                               "1.50/1.55/1.60 um, 1 forward + 1 adjoint each (6 right-hand "
-                               "sides), 10000 steps, forward+adjoint+gradient per step",
-                   "cells": dev.cells, "rhs": plan.n_rhs, "time_steps": dev.n_steps,
-                   "tiling": [tuned["rows"], tuned["zchunk"], tuned["flags"]] if tuned else None},
-        "gradients_per_hour": round(3.6e6 / ms, 1),
-        "hbm_frac_whole_step": round(eff_gbs / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "k_yee_step interior tiles",
-                     "bytes_per_launch": k_bytes, "ms_per_launch": round(k_ms, 4),
-                     "launches_timed": k_n},
+        "config": {"workload": "multi-port: 600x400x120 cells at 20 nm (CPML 8), 1-to-4 "
+                               "splitter-like SOI device, 250x150 design/controls, r=4, beta=16, "
+                               "5 wavelengths 1.500-1.600 um x (1 forward + 4 adjoint port "
+                               "sources) = 25 right-hand sides in the same launches, 20000 Yee "
+                               f"steps per solve; one bench step = {block} whole Yee steps of all "
+                               "25 right-hand sides (step launches, sources, DFT in the window), "
+                               "inside a forward+adjoint solve that is run to its end and turned "
+                               "into alpha and dF/dC",
+                   "cells": dev.cells, "rhs": int(plan_rhs(dev)), "time_steps_per_solve": dev.n_steps,
+                   "yee_steps_per_bench_step": block, "graph_chunk": chunk,
+                   "tiling": list(tiling)},
+        "gradients_per_hour": round(3600.0 / s_grad, 2),
+        "s_per_gradient": round(s_grad, 2),
+        "hbm_frac_model_bytes_whole_step": round(eff_gbs / HBM_PEAK_GBS, 4),
+        "roofline": roofline_of(parts),
     }
+    if not args.no_realistic:
+        out["realistic"] = realistic_gradients(args, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)...")
         out["cpu_baseline"] = cpu_baseline(dev, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    plan.close()
+
+
+def plan_rhs(dev) -> int:
+    return (len(dev.sources) + len(dev.ports)) * dev.n_freq
 
 
 def _line(metric, value, unit, ms, args, cfg, extra, steps=1, warmup=0):

@@ -215,8 +215,13 @@ yo_status yo_set_design(yo_plan *plan, const float *dev_C, double beta, yo_strea
  * result.  If any value is Inf or NaN (the fields diverged, e.g. from a
  * background kappa <= 0 or non-finite fields set through yo_set_fields) it
  * returns YO_EUNSTABLE, and yo_alpha, yo_gradient and yo_gradient_kappa
- * return YO_EUNSTABLE until the next yo_reset; yo_get_dft still returns the
- * phasors for inspection. */
+ * return YO_EUNSTABLE until the next yo_reset of that side; yo_get_dft still
+ * returns the phasors for inspection.
+ *
+ * The forward and adjoint right-hand sides are independent: YO_BOTH steps
+ * them in the same launches (sharing kappa), while a YO_FORWARD run followed
+ * by a YO_ADJOINT run (or the reverse) gives bitwise the same phasors; a
+ * reset of one side leaves the other side's phasors alone. */
 yo_status yo_run(yo_plan *plan, int which, int chunk, int use_graph, yo_stream stream);
 
 /* Lower-level pieces of yo_run (used by the batch executor and tests). */
@@ -259,15 +264,22 @@ yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);
 
 /* Modal coefficients (Appendix A) of the forward right-hand sides:
  * dev_alpha complex64 [n_src][n_ports][n_freq]; may be null when n_src or
- * n_ports is 0 (nothing is written). */
+ * n_ports is 0 (nothing is written).  YO_ESTATE without a finished run of
+ * the forward right-hand sides (YO_FORWARD or YO_BOTH), or when yo_set_design
+ * or yo_set_background was called after that run's reset (its phasors belong
+ * to another permittivity). */
 yo_status yo_alpha(const yo_plan *plan, float *dev_alpha, yo_stream stream);
 
 /* Gradient (Eq. (1) and the chain's VJP): dev_coef = dF/dalpha (holomorphic
  * Wirtinger derivative, e.g. conj(alpha) for F = |alpha|^2), complex64
  * [n_src][n_ports][n_freq]; dev_dFdC FP32 [nc][mc] receives
- * sum 2 Re(coef dalpha/dC).  Needs a finished YO_BOTH run and yo_set_design.
- * With n_src or n_ports 0 there are no coefficients: dev_coef may be null
- * and the gradient is zero. */
+ * sum 2 Re(coef dalpha/dC).  Needs yo_set_design and finished forward and
+ * adjoint runs: one YO_BOTH run, or a YO_FORWARD run and a YO_ADJOINT run in
+ * either order (each side keeps its phasors until its own next reset);
+ * YO_ESTATE if yo_set_design or yo_set_background was called after either
+ * run's reset (Eq. (1) would pair one design's phasors with another's
+ * permittivity and chain state).  With n_src or n_ports 0 there are no
+ * coefficients: dev_coef may be null and the gradient is zero. */
 yo_status yo_gradient(yo_plan *plan, const float *dev_coef, float *dev_dFdC, yo_stream stream);
 
 /* Same, stopping after Eq. (1): dF/dkappa on the DFT box, FP32 [3][bz][by][bx]
@@ -335,14 +347,18 @@ yo_status yo_adam_step(float *dev_C, const float *dev_G, float *dev_M, float *de
 /* Launch timing inside a solve: with n_last > 0, every later yo_advance,
  * yo_run or yo_advance_many (with this plan first in its list) runs its
  * last n_last steps with plain launches and records a pair of HIP events on
- * its stream around each launch of `part` (0 interior tiles, 1 CPML shell);
- * n_last = 0 turns it off.  n_last <= 4096; events are created here and
- * owned by the plan.  Host only.  YO_EINVAL on a bad part or count. */
+ * its stream around each launch of `part` (0 interior tiles, 1 CPML shell,
+ * 2 both); the pairs accumulate over calls until the next yo_set_timing,
+ * which clears them.  n_last = 0 turns it off.  n_last <= 4096; the events
+ * are created as needed (outside graph capture: the timed steps are never
+ * captured) and owned by the plan.  Host only.  YO_EINVAL on a bad part or
+ * count. */
 yo_status yo_set_timing(yo_plan *plan, int part, int n_last);
 
-/* Mean duration of the launches timed by the last advance (waits for the
- * last of them); count = how many (0: none, avg_ms = 0). */
-yo_status yo_get_timing(yo_plan *plan, float *avg_ms, int *count);
+/* Mean duration of the launches of `part` (0 or 1) timed since the last
+ * yo_set_timing (waits for the last of them); count = how many (0: none,
+ * avg_ms = 0). */
+yo_status yo_get_timing(yo_plan *plan, int part, float *avg_ms, int *count);
 
 const char *yo_last_error(void);
 const char *yo_version(void);

@@ -44,8 +44,12 @@
  * z-planes only.  Built without fast-math.
  */
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int nx, ny, nz;
@@ -143,6 +147,26 @@ static void plane_cell(const orc_plane *pl, int a, int b, int *i, int *j, int *k
     *i = c[0]; *j = c[1]; *k = c[2];
 }
 
+/* thread count of the OpenMP loops (n < 1: leave it); for timing the oracle
+ * at a chosen core count */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int orc_run(const orc_sim *sim, const double *kappa, double *E, double *H,
             const orc_plane *src, const double *src_j,
             const orc_box *box, double *box_acc,
@@ -180,7 +204,14 @@ int orc_run(const orc_sim *sim, const double *kappa, double *E, double *H,
     const size_t box_total = box ? 3 * (size_t)box->bx * box->by * box->bz : 0;
 
     const int pulse = sim->pulse_sigma > 0.0;
+    /* optional progress lines on stderr for long runs (no effect on results) */
+    const char *pe = getenv("ORC_PROGRESS_STEPS");
+    const int progress = pe ? atoi(pe) : 0;
     for (int n = 0; n < sim->n_steps; n++) {
+        if (progress > 0 && n > 0 && n % progress == 0) {
+            fprintf(stderr, "oracle: step %d of %d\n", n, sim->n_steps);
+            fflush(stderr);
+        }
         /* ---- pulse excitation: DFT of E^n at every frequency, every step ---- */
         for (int f = 0; pulse && f < sim->n_dft; f++) {
             int h = (n < sim->win_start) ? 0 : 1;

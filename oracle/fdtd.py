@@ -57,7 +57,17 @@ def lib():
             _build.build()
         _LIB = ct.CDLL(path)
         _LIB.orc_run.restype = ct.c_int
+        _LIB.orc_set_threads.argtypes = [ct.c_int]
+        _LIB.orc_set_threads.restype = None
+        _LIB.orc_max_threads.restype = ct.c_int
     return _LIB
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's OpenMP loops (for timing it at a chosen
+    core count); returns the count now in effect."""
+    lib().orc_set_threads(int(n))
+    return int(lib().orc_max_threads())
 
 
 @dataclass

@@ -83,7 +83,7 @@ _SIGS = {
     "yo_set_timing": [_P, _I, _I],
     "yo_unbinarity": [_P, ct.c_double, ct.c_double, _P, _P],
     "yo_adam_step": [_P, _P, _P, _P, _I, _I, ct.c_double, ct.c_double, ct.c_double, ct.c_double, _P],
-    "yo_get_timing": [_P, ct.POINTER(ct.c_float), ct.POINTER(ct.c_int)],
+    "yo_get_timing": [_P, _I, ct.POINTER(ct.c_float), ct.POINTER(ct.c_int)],
     "yo_alpha": [_P, _P, _S],
     "yo_gradient": [_P, _P, _P, _S],
     "yo_gradient_kappa": [_P, _P, _P, _S],

@@ -138,18 +138,34 @@ struct yo_plan {
     double beta = 0;
     int steps_done = 0;
     int active = 0;              // which right-hand sides the last reset selected
-    bool finalized = false;
-    bool unstable = false;        // the last finalize found non-finite phasors
+    // per side (0 forward, 1 adjoint): phasors fitted by a finalize since
+    // the side's last reset, and non-finite ones among them (watchdog)
+    bool finalized[2] = {false, false};
+    bool unstable[2] = {false, false};
+    // material stamp: bumped by every change of kappa (background, design);
+    // a reset records it, and results of a run whose kappa has changed since
+    // (alpha, the Eq. (1) gradient) are refused
+    int mat_gen = 0, run_mat_gen[2] = {-1, -1};
     hipStream_t cap_stream = nullptr;
     // launch timing: the last tm_n steps of each advance run eagerly, with
-    // HIP events around part tm_part's launch (pairs in tm_ev)
-    int tm_part = 0, tm_n = 0, tm_done = 0;
-    std::vector<hipEvent_t> tm_ev;
+    // HIP events around the launches of part tm_part (0, 1, or 2 for both);
+    // tm_ev[q] holds the event pairs of part q recorded since yo_set_timing
+    // (tm_done[q] of them), created as they are needed
+    int tm_part = 0, tm_n = 0;
+    int tm_done[2] = {0, 0};
+    std::vector<hipEvent_t> tm_ev[2];
 };
 
 namespace {
 
 // ------------------------------------------------------------------ helpers
+// a workspace is bound
+yo_status ws_check(const yo_plan *p)
+{
+    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    return YO_OK;
+}
+
 template <class T>
 T *wsp(yo_plan *p, const Region &r, size_t extra_bytes = 0)
 {
@@ -703,7 +719,8 @@ void yo_plan_destroy(yo_plan *p)
         }
     }
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    for (hipEvent_t e : p->tm_ev) (void)hipEventDestroy(e);
+    for (int q = 0; q < 2; ++q)
+        for (hipEvent_t e : p->tm_ev[q]) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -977,13 +994,8 @@ yo_status yo_set_pulse(yo_plan *p, double omega0, double sigma_steps, double t0_
     return YO_OK;
 }
 
-yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream stream)
+static yo_status bind_ws(yo_plan *p, void *dev, size_t bytes, hipStream_t s)
 {
-    if (!p || !dev) return fail(YO_EINVAL, "null argument");
-    if (((uintptr_t)dev) & 255) return fail(YO_EINVAL, "workspace must be 256-byte aligned");
-    if (bytes < p->L.total)
-        return fail(YO_EWORKSPACE, "workspace of %zu bytes, %zu needed", bytes, p->L.total);
-    hipStream_t s = (hipStream_t)stream;
     p->ws = (char *)dev;
     p->ws_bytes = bytes;
     p->generation++;
@@ -1012,9 +1024,17 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     p->bg_set = false;
     p->design_set = false;
     p->steps_done = 0;
-    p->finalized = false;
-    p->unstable = false;
+    for (int q = 0; q < 2; ++q) p->finalized[q] = p->unstable[q] = false;
     return YO_OK;
+}
+
+yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream stream)
+{
+    if (!p || !dev) return fail(YO_EINVAL, "null argument");
+    if (((uintptr_t)dev) & 255) return fail(YO_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < p->L.total)
+        return fail(YO_EWORKSPACE, "workspace of %zu bytes, %zu needed", bytes, p->L.total);
+    return bind_ws(p, dev, bytes, (hipStream_t)stream);
 }
 
 yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
@@ -1040,13 +1060,14 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
 yo_status yo_set_background(yo_plan *p, const float *kappa, const float *mask, yo_stream stream)
 {
     if (!p || !kappa || !mask) return fail(YO_EINVAL, "null argument");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     hipStream_t s = (hipStream_t)stream;
     const yo_grid &g = p->grid;
     HIPCHK(yo_launch_to_ghost(kappa, wsp<float>(p, p->L.kappa), 3, 0, 3, g.nz, g.ny, g.nx, p->nxp, s));
     HIPCHK(hipMemcpyAsync(p->chain.mask, mask, sizeof(float) * p->U * p->V, hipMemcpyDeviceToDevice, s));
     p->bg_set = true;
     p->design_set = false;
+    p->mat_gen++;
     return YO_OK;
 }
 
@@ -1056,7 +1077,7 @@ yo_status yo_set_source_mode(yo_plan *p, int src, const double *h, yo_stream str
 {
     if (!p || !h) return fail(YO_EINVAL, "null argument");
     if (src < 0 || src >= p->n_src) return fail(YO_EINVAL, "source index out of range");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     const yo_plane &pl = p->src_planes[src];
     const size_t n = (size_t)pl.n0 * pl.n1;
     if (p->src_j_host.size() < p->src_total) p->src_j_host.assign(p->src_total, float2{0, 0});
@@ -1082,7 +1103,7 @@ yo_status yo_set_port_mode(yo_plan *p, int port, const double *e, const double *
 {
     if (!p || !e || !h) return fail(YO_EINVAL, "null argument");
     if (port < 0 || port >= p->n_ports) return fail(YO_EINVAL, "port index out of range");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     const yo_plane &pl = p->port_planes[port];
     const size_t n = (size_t)pl.n0 * pl.n1;
     // N = 1/2 sum (e_t1 conj(h_t2) - e_t2 conj(h_t1)); cell area cancels
@@ -1165,7 +1186,7 @@ yo_status yo_set_port_mode(yo_plan *p, int port, const double *e, const double *
 yo_status yo_set_design(yo_plan *p, const float *C, double beta, yo_stream stream)
 {
     if (!p || !C) return fail(YO_EINVAL, "null argument");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     if (!p->bg_set) return fail(YO_ESTATE, "yo_set_background first");
     if (!(beta > 0)) return fail(YO_EINVAL, "beta must be positive");
     const yo_design &d = p->des;
@@ -1174,13 +1195,14 @@ yo_status yo_set_design(yo_plan *p, const float *C, double beta, yo_stream strea
                                    (hipStream_t)stream));
     p->beta = beta;
     p->design_set = true;
+    p->mat_gen++;
     return YO_OK;
 }
 
 yo_status yo_reset(yo_plan *p, int which, yo_stream stream)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     if (which < 1 || which > 3) return fail(YO_EINVAL, "which must be YO_FORWARD, YO_ADJOINT or YO_BOTH");
     hipStream_t s = (hipStream_t)stream;
     int r0, r1;
@@ -1206,8 +1228,11 @@ yo_status yo_reset(yo_plan *p, int which, yo_stream stream)
     HIPCHK(yo_launch_ctr(ca, 1, s));
     p->steps_done = 0;
     p->active = which;
-    p->finalized = false;
-    p->unstable = false;
+    for (int q = 0; q < 2; ++q)
+        if (which & (1 << q)) {
+            p->finalized[q] = p->unstable[q] = false;
+            p->run_mat_gen[q] = p->mat_gen;
+        }
     return YO_OK;
 }
 
@@ -1307,11 +1332,23 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
             }
             for (int part = 0; part < 2; ++part) {
                 A[part].k_offset = k;
-                const bool tm = timed && base == 0 && part == timed->tm_part && blocks[part] &&
-                                timed->tm_done < timed->tm_n;
-                if (tm) HIPCHK(hipEventRecord(timed->tm_ev[2 * timed->tm_done], s));
-                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
-                if (tm) HIPCHK(hipEventRecord(timed->tm_ev[2 * timed->tm_done++ + 1], s));
+                const bool tm = timed && base == 0 && blocks[part] &&
+                                (timed->tm_part == part || timed->tm_part == 2);
+                if (tm) {
+                    std::vector<hipEvent_t> &ev = timed->tm_ev[part];
+                    const size_t need = 2 * (size_t)timed->tm_done[part] + 2;
+                    while (ev.size() < need) {
+                        hipEvent_t e;
+                        HIPCHK(hipEventCreate(&e));
+                        ev.push_back(e);
+                    }
+                    HIPCHK(hipEventRecord(ev[need - 2], s));
+                    HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
+                    HIPCHK(hipEventRecord(ev[need - 1], s));
+                    timed->tm_done[part]++;
+                } else {
+                    HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
+                }
             }
             as.k_offset = k;
             HIPCHK(yo_launch_source(as, s));
@@ -1348,7 +1385,8 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
     if (n_steps < 0) return fail(YO_EINVAL, "negative step count");
     for (int i = 0; i < n; ++i) {
         yo_plan *p = plans[i];
-        if (!p || !p->ws) return fail(YO_EWORKSPACE, "plan %d has no workspace", i);
+        if (!p) return fail(YO_EINVAL, "plan %d is null", i);
+        if (yo_status st_ = ws_check(p)) return st_;
         if (which[i] != p->active) return fail(YO_ESTATE, "plan %d: which differs from its reset", i);
         // the x-split flags only shape each plan's own tile table; the others
         // pick the kernel variant, which one launch shares
@@ -1364,7 +1402,6 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
     // of this call run eagerly with events around the timed part
     yo_plan *timed = plans[0]->tm_n > 0 ? plans[0] : nullptr;
     const int tail = timed ? std::min(timed->tm_n, n_steps) : 0;
-    if (timed) timed->tm_done = 0;
     // steps_done is advanced per chunk so chunk_needs_dft sees the current steps
     std::vector<int> start(n);
     for (int i = 0; i < n; ++i) start[i] = plans[i]->steps_done;
@@ -1434,7 +1471,7 @@ yo_status yo_advance(yo_plan *p, int which, int n_steps, yo_stream stream)
 yo_status yo_finalize(yo_plan *p, int which, yo_stream stream)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     if (which != p->active) return fail(YO_ESTATE, "finalize: which differs from the reset");
     if (p->steps_done < p->n_steps) return fail(YO_ESTATE, "finalize before all steps ran");
     hipStream_t s = (hipStream_t)stream;
@@ -1454,9 +1491,12 @@ yo_status yo_finalize(yo_plan *p, int which, yo_stream stream)
     int host_bad = 0;
     HIPCHK(hipMemcpyAsync(&host_bad, bad, sizeof host_bad, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    p->finalized = true;
-    p->unstable = host_bad != 0;
-    if (p->unstable)
+    for (int q = 0; q < 2; ++q)
+        if (which & (1 << q)) {
+            p->finalized[q] = true;
+            p->unstable[q] = host_bad != 0;
+        }
+    if (host_bad)
         return fail(YO_EUNSTABLE, "non-finite phasors after %d steps: the fields diverged", p->steps_done);
     return YO_OK;
 }
@@ -1474,8 +1514,11 @@ yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
 {
     // with no sources or no ports the array is empty and may be null
     if (!p || (!alpha && p->n_src > 0 && p->n_ports > 0)) return fail(YO_EINVAL, "null argument");
-    if (!p->finalized || !(p->active & YO_FORWARD)) return fail(YO_ESTATE, "no finished forward run");
-    if (p->unstable) return fail(YO_EUNSTABLE, "the last run diverged (non-finite phasors)");
+    if (yo_status st_ = ws_check(p)) return st_;
+    if (!p->finalized[0]) return fail(YO_ESTATE, "no finished forward run");
+    if (p->run_mat_gen[0] != p->mat_gen)
+        return fail(YO_ESTATE, "the design or background changed after the forward run started");
+    if (p->unstable[0]) return fail(YO_EUNSTABLE, "the forward run diverged (non-finite phasors)");
     hipStream_t s = (hipStream_t)stream;
     const float2 *w = reinterpret_cast<const float2 *>(p->ws + p->L.port_w.off);
     for (int sidx = 0; sidx < p->n_src; ++sidx)
@@ -1495,8 +1538,13 @@ yo_status yo_alpha(const yo_plan *p, float *alpha, yo_stream stream)
 
 static yo_status grad_common(yo_plan *p, const float *coef, float *gbox, float *gmap, hipStream_t s)
 {
-    if (!p->finalized || p->active != YO_BOTH) return fail(YO_ESTATE, "needs a finished YO_BOTH run");
-    if (p->unstable) return fail(YO_EUNSTABLE, "the last run diverged (non-finite phasors)");
+    if (yo_status st_ = ws_check(p)) return st_;
+    if (!p->finalized[0] || !p->finalized[1])
+        return fail(YO_ESTATE, "needs finished forward and adjoint runs (together or one after the other)");
+    if (p->run_mat_gen[0] != p->mat_gen || p->run_mat_gen[1] != p->mat_gen)
+        return fail(YO_ESTATE, "the design or background changed after a run started");
+    if (p->unstable[0] || p->unstable[1])
+        return fail(YO_EUNSTABLE, "a run diverged (non-finite phasors)");
     YoGradArgs a;
     memset(&a, 0, sizeof a);
     for (int f = 0; f < p->n_freq; ++f) {
@@ -1533,6 +1581,7 @@ yo_status yo_gradient(yo_plan *p, const float *coef, float *dFdC, yo_stream stre
 {
     // with no sources or no ports there is no coefficient (the gradient is 0)
     if (!p || !dFdC || (!coef && p->n_src > 0 && p->n_ports > 0)) return fail(YO_EINVAL, "null argument");
+    if (yo_status st_ = ws_check(p)) return st_;
     if (!p->design_set) return fail(YO_ESTATE, "yo_set_design first");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(yo_launch_fill(p->chain.gmap, 4 * (size_t)p->G0 * p->G1, 0.0f, s));
@@ -1545,6 +1594,7 @@ yo_status yo_gradient(yo_plan *p, const float *coef, float *dFdC, yo_stream stre
 yo_status yo_chain_vjp(yo_plan *p, const float *gk, float *dFdC, yo_stream stream)
 {
     if (!p || !gk || !dFdC) return fail(YO_EINVAL, "null argument");
+    if (yo_status st_ = ws_check(p)) return st_;
     if (!p->design_set) return fail(YO_ESTATE, "yo_set_design first");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(yo_launch_fill(p->chain.gmap, 4 * (size_t)p->G0 * p->G1, 0.0f, s));
@@ -1557,7 +1607,7 @@ yo_status yo_unbinarity(yo_plan *p, double lo, double hi, float *dev_u, yo_strea
 {
     if (!p || !dev_u) return fail(YO_EINVAL, "null argument");
     if (!(lo >= 0.0 && lo < hi && hi <= 1.0)) return fail(YO_EINVAL, "need 0 <= lo < hi <= 1");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     if (!p->design_set) return fail(YO_ESTATE, "yo_set_design first");
     // the counter sits after the step counter in the counter region
     int *count = wsp<int>(p, p->L.ctr) + 16;
@@ -1583,33 +1633,30 @@ yo_status yo_adam_step(float *dev_C, const float *dev_G, float *dev_M, float *de
 yo_status yo_set_timing(yo_plan *p, int part, int n_last)
 {
     if (!p) return fail(YO_EINVAL, "null argument");
-    if (part < 0 || part > 1 || n_last < 0 || n_last > 4096) return fail(YO_EINVAL, "bad part or count");
-    const size_t need = 2 * (size_t)n_last;
-    while (p->tm_ev.size() < need) {
-        hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
-        p->tm_ev.push_back(e);
-    }
+    if (part < 0 || part > 2 || n_last < 0 || n_last > 4096) return fail(YO_EINVAL, "bad part or count");
     p->tm_part = part;
     p->tm_n = n_last;
-    p->tm_done = 0;
+    p->tm_done[0] = p->tm_done[1] = 0;
     return YO_OK;
 }
 
-yo_status yo_get_timing(yo_plan *p, float *avg_ms, int *count)
+yo_status yo_get_timing(yo_plan *p, int part, float *avg_ms, int *count)
 {
     if (!p || !avg_ms || !count) return fail(YO_EINVAL, "null argument");
+    if (part < 0 || part > 1) return fail(YO_EINVAL, "part must be 0 or 1");
     *avg_ms = 0.0f;
-    *count = p->tm_done;
-    if (!p->tm_done) return YO_OK;
-    HIPCHK(hipEventSynchronize(p->tm_ev[2 * p->tm_done - 1]));
+    const int n = p->tm_done[part];
+    *count = n;
+    if (!n) return YO_OK;
+    const std::vector<hipEvent_t> &ev = p->tm_ev[part];
+    HIPCHK(hipEventSynchronize(ev[2 * n - 1]));
     double tot = 0.0;
-    for (int i = 0; i < p->tm_done; ++i) {
+    for (int i = 0; i < n; ++i) {
         float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, p->tm_ev[2 * i], p->tm_ev[2 * i + 1]));
+        HIPCHK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
         tot += ms;
     }
-    *avg_ms = (float)(tot / p->tm_done);
+    *avg_ms = (float)(tot / n);
     return YO_OK;
 }
 
@@ -1617,7 +1664,7 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
                          double *cells, yo_stream stream)
 {
     if (!p || !avg_ms || !bytes || !cells) return fail(YO_EINVAL, "null argument");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     if (cls < 0 || cls > 1 || n_launch < 1) return fail(YO_EINVAL, "bad part or count");
     if (!p->active) return fail(YO_ESTATE, "yo_reset first");
     hipStream_t s = (hipStream_t)stream;
@@ -1672,7 +1719,7 @@ yo_status yo_get_dft(const yo_plan *p, int rhs, int region, float *out, yo_strea
     if (!p || !out) return fail(YO_EINVAL, "null argument");
     if (rhs < 0 || rhs >= p->n_rhs) return fail(YO_EINVAL, "rhs out of range");
     if (region < 0 || region > p->n_ports) return fail(YO_EINVAL, "region out of range");
-    if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (yo_status st_ = ws_check(p)) return st_;
     const void *src;
     size_t bytes;
     if (region == 0) {
@@ -1691,6 +1738,7 @@ yo_status yo_set_fields(yo_plan *p, int rhs, const float *E, const float *H, yo_
 {
     if (!p || !E || !H) return fail(YO_EINVAL, "null argument");
     if (rhs < 0 || rhs >= p->n_phys) return fail(YO_EINVAL, "rhs out of range");
+    if (yo_status st_ = ws_check(p)) return st_;
     const yo_grid &g = p->grid;
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
@@ -1704,6 +1752,7 @@ yo_status yo_get_fields(const yo_plan *p, int rhs, float *E, float *H, yo_stream
 {
     if (!p || !E || !H) return fail(YO_EINVAL, "null argument");
     if (rhs < 0 || rhs >= p->n_phys) return fail(YO_EINVAL, "rhs out of range");
+    if (yo_status st_ = ws_check(p)) return st_;
     const yo_grid &g = p->grid;
     const YoRhsD &R = p->hrhs[rhs];
     const int par = p->steps_done & 1;
@@ -1716,6 +1765,7 @@ yo_status yo_get_fields(const yo_plan *p, int rhs, float *E, float *H, yo_stream
 yo_status yo_get_kappa(const yo_plan *p, float *kappa, yo_stream stream)
 {
     if (!p || !kappa) return fail(YO_EINVAL, "null argument");
+    if (yo_status st_ = ws_check(p)) return st_;
     const yo_grid &g = p->grid;
     HIPCHK(yo_launch_from_ghost(reinterpret_cast<const float *>(p->ws + p->L.kappa.off), kappa, 3,
                                 0, 3, g.nz, g.ny, g.nx, p->nxp, (hipStream_t)stream));

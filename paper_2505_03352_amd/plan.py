@@ -276,14 +276,16 @@ class Plan:
         return out
 
     def set_timing(self, part: int = 0, n_last: int = 100):
-        """Time the launches of one part (0 interior, 1 CPML shell) over the
-        last `n_last` steps of every later advance (0: off)."""
+        """Time the launches of one part (0 interior, 1 CPML shell, 2 both)
+        over the last `n_last` steps of every later advance (0: off); clears
+        what was recorded."""
         call("yo_set_timing", self._h, int(part), int(n_last))
 
-    def timing(self):
-        """(mean ms per timed launch, launches timed) of the last advance."""
+    def timing(self, part: int = 0):
+        """(mean ms per timed launch, launches timed) of part 0 or 1 since the
+        last set_timing."""
         ms, n = ct.c_float(), ct.c_int()
-        call("yo_get_timing", self._h, ct.byref(ms), ct.byref(n))
+        call("yo_get_timing", self._h, int(part), ct.byref(ms), ct.byref(n))
         return float(ms.value), int(n.value)
 
     def model_bytes(self, which=YO_BOTH):
