@@ -176,6 +176,24 @@ yo_status yo_workspace_bytes(const yo_plan *plan, size_t *bytes);
  * phases, filter taps) on `stream`.  YO_EWORKSPACE if too small. */
 yo_status yo_bind_workspace(yo_plan *plan, void *dev, size_t bytes, yo_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bind the
+ * library's own static workspace of the current device instead of a
+ * caller-owned buffer; everything else works as after yo_bind_workspace.
+ * Allocates nothing (no hipMalloc, no allocating library call).  The static
+ * workspace holds at most 32 MiB (the tiny 56x56x36 device with one forward
+ * and one adjoint right-hand side needs about 21 MiB): a plan whose
+ * yo_workspace_bytes exceeds that gets YO_EWORKSPACE and stays unbound.  The
+ * device's array is shared by every plan bound to it and keeps the last
+ * binding's contents; this call clears the plan's part of it to zero and
+ * uploads the plan's tables (synchronising `stream`).  Binding another plan
+ * to the same device's static workspace takes the memory over: every later
+ * call on the earlier plan returns YO_EWORKSPACE until it is bound again.
+ * Calls on plans sharing it that overlap in time (other host threads or
+ * streams) race and give undefined results.  Each device holds its own
+ * copy until the process ends. */
+yo_status yo_bind_static_workspace(yo_plan *plan, yo_stream stream);
+
 /* Background: dev_kappa = 1/eps_r per E component, FP32 [3][nz][ny][nx];
  * dev_mask = background fill of the design canvas, FP32 [S(nd+4)][S(md+4)]
  * (only its margin is used).  Both are copied into the workspace. */

@@ -69,6 +69,7 @@ _SIGS = {
     "yo_set_alpha_terms": [_P, _I],
     "yo_workspace_bytes": [_P, ct.POINTER(ct.c_size_t)],
     "yo_bind_workspace": [_P, _P, ct.c_size_t, _S],
+    "yo_bind_static_workspace": [_P, _S],
     "yo_set_background": [_P, _P, _P, _S],
     "yo_set_source_mode": [_P, _I, _P, _S],
     "yo_set_port_mode": [_P, _I, _P, _P, _S],

@@ -68,6 +68,17 @@ std::mutex g_graph_mu;
 std::map<std::string, GraphEntry> g_graphs;
 int g_next_plan_id = 1;
 
+// Static workspace for callers that cannot allocate (yo_bind_static_workspace).
+// Each device the library runs on holds its own copy until the process
+// ends.  Host code never uses the array's name as an address: its device
+// address is looked up per device with hipGetSymbolAddress.
+#define YO_STATIC_WS_BYTES ((size_t)32 << 20)
+#define YO_MAX_DEVICES 64
+static __device__ __align__(256) char scratch[YO_STATIC_WS_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[YO_MAX_DEVICES];
+unsigned g_scratch_epoch[YO_MAX_DEVICES];
+
 }  // namespace
 
 // Tiling flags (yo_set_tiling)
@@ -146,6 +157,11 @@ struct yo_plan {
     // a reset records it, and results of a run whose kappa has changed since
     // (alpha, the Eq. (1) gradient) are refused
     int mat_gen = 0, run_mat_gen[2] = {-1, -1};
+    // bound to the device's static workspace (yo_bind_static_workspace): the
+    // device and the binding's epoch there; a later static binding on the
+    // same device takes the memory over and this plan is refused
+    int static_dev = -1;
+    unsigned static_epoch = 0;
     hipStream_t cap_stream = nullptr;
     // launch timing: the last tm_n steps of each advance run eagerly, with
     // HIP events around the launches of part tm_part (0, 1, or 2 for both);
@@ -159,10 +175,16 @@ struct yo_plan {
 namespace {
 
 // ------------------------------------------------------------------ helpers
-// a workspace is bound
+// a workspace is bound and, for the static workspace, still this plan's
 yo_status ws_check(const yo_plan *p)
 {
     if (!p->ws) return fail(YO_EWORKSPACE, "no workspace bound");
+    if (p->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch_epoch[p->static_dev] != p->static_epoch)
+            return fail(YO_EWORKSPACE, "another plan was bound to the static workspace of device %d "
+                                       "since this one; bind again", p->static_dev);
+    }
     return YO_OK;
 }
 
@@ -1034,7 +1056,39 @@ yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream strea
     if (((uintptr_t)dev) & 255) return fail(YO_EINVAL, "workspace must be 256-byte aligned");
     if (bytes < p->L.total)
         return fail(YO_EWORKSPACE, "workspace of %zu bytes, %zu needed", bytes, p->L.total);
+    p->static_dev = -1;
     return bind_ws(p, dev, bytes, (hipStream_t)stream);
+}
+
+yo_status yo_bind_static_workspace(yo_plan *p, yo_stream stream)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (p->L.total > YO_STATIC_WS_BYTES)
+        return fail(YO_EWORKSPACE, "the plan needs %zu workspace bytes; the static workspace holds %zu",
+                    p->L.total, (size_t)YO_STATIC_WS_BYTES);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= YO_MAX_DEVICES) return fail(YO_EUNSUPPORTED, "device index %d", dev);
+    void *ptr = nullptr;
+    unsigned epoch = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            // once per device, with that device current: the array's address there
+            void *q = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !q)
+                return fail(YO_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            g_scratch_ptr[dev] = q;
+        }
+        ptr = g_scratch_ptr[dev];
+        epoch = ++g_scratch_epoch[dev];
+    }
+    p->static_dev = dev;
+    p->static_epoch = epoch;
+    // bind_ws clears the whole region the plan uses (the last binding's
+    // contents stay in the array) and uploads the tables
+    return bind_ws(p, ptr, YO_STATIC_WS_BYTES, (hipStream_t)stream);
 }
 
 yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)

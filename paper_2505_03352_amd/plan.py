@@ -134,6 +134,14 @@ class Plan:
              ct.c_size_t(view.numel()), _stream(stream))
         return self
 
+    def bind_static(self, stream=None):
+        """Bind the library's static per-device workspace (no allocation;
+        at most 32 MiB, shared by every plan bound this way on the device:
+        the last one bound owns it)."""
+        call("yo_bind_static_workspace", self._h, _stream(stream))
+        self.workspace = None
+        return self
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _abi.lib().yo_plan_destroy(self._h)
@@ -342,14 +350,19 @@ def freqs_of(dev) -> List[FreqSpec]:
 
 
 def plan_for(dev, device="cuda", stream=None, C=None, beta=None, set_design=True,
-             workspace: Optional[torch.Tensor] = None, pulse=None, two_term: bool = False) -> Plan:
+             workspace: Optional[torch.Tensor] = None, pulse=None, two_term: bool = False,
+             static_workspace: bool = False) -> Plan:
     """Create, bind and fill a plan for a device description.  pulse:
     (omega0 rad/s, sigma steps, t0 steps) for pulse excitation; two_term:
-    the two-term modal coefficient."""
+    the two-term modal coefficient; static_workspace: bind the library's
+    static workspace instead of allocating one."""
     grid, design = grid_design_of(dev)
     p = Plan(grid, design, dev.n_steps, freqs_of(dev), [m.plane for m in dev.sources],
              [m.plane for m in dev.ports], device=device, pulse=pulse, two_term=two_term)
-    p.bind(workspace, stream)
+    if static_workspace:
+        p.bind_static(stream)
+    else:
+        p.bind(workspace, stream)
     p.set_background(torch.as_tensor(dev.kappa_bg, dtype=torch.float32),
                      torch.as_tensor(dev.mask_hr, dtype=torch.float32), stream)
     for s, m in enumerate(dev.sources):

@@ -219,3 +219,16 @@ def test_two_term_coefficient_arguments_and_workspace():
     q = _create(dev, ports=[edge, dev.ports[1].plane])
     assert _abi.lib().yo_set_alpha_terms(q.handle, 2) == _abi.YO_EINVAL
     q.close()
+
+
+def test_static_workspace_rejects_a_plan_beyond_its_size():
+    """The allocation-free binding refuses, before touching any device, a plan
+    whose workspace exceeds the static array (32 MiB)."""
+    dev = configs.realistic()
+    p = _create(dev)
+    assert p.workspace_bytes > 32 << 20
+    with pytest.raises(_abi.YeeOptError) as e:
+        _abi.call("yo_bind_static_workspace", p.handle, None)
+    assert e.value.status == _abi.YO_EWORKSPACE
+    assert "static workspace" in str(e.value)
+    p.close()
