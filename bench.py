@@ -177,8 +177,10 @@ def main():
                     help="multiport: the headline line; batch / serving: the batched and served "
                          "forms against one-at-a-time solves (their own JSON line)")
     ap.add_argument("--requests", type=int, default=12, help="serving: first N requests of the trace")
-    ap.add_argument("--no-baseline", action="store_true",
-                    help="serving: skip the one-request-at-a-time baseline")
+    ap.add_argument("--sides", default="served,plain",
+                    help="serving: which of served (continuous batching), plain (one request at "
+                         "a time, plain forward-then-adjoint solves per wavelength) and same (the "
+                         "served executor with one slot) to run, comma-separated")
     ap.add_argument("--iters", type=int, default=5, help="optimize: optimizer iterations")
     ap.add_argument("--pulse", action="store_true",
                     help="optimize: gradients from pulse runs; serving: pulse runs for "
@@ -191,6 +193,9 @@ def main():
     ap.add_argument("--pulse-k", type=float, default=None,
                     help="band edges in spectral widths of the pulse (broadband: 0.4, "
                          "optimize: 1.0)")
+    ap.add_argument("--dft-stride", type=int, default=4,
+                    help="pulse runs: the DFT samples every n-th step (the library checks that "
+                         "the pulse spectrum vanishes at the aliases)")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--rate", type=float, default=4.0, help="serving: arrival rate, requests/s")
     ap.add_argument("--max-cells", type=float, default=4.5e7,
@@ -451,8 +456,12 @@ def _line(metric, value, unit, ms, args, cfg, extra, steps=1, warmup=0):
 
 def bench_batch(args):
     """8 designs of uneven size (1 wavelength, forward + adjoint each):
-    shared launches with graph replays against one design at a time with
-    plain launches, equal steps and windows."""
+    shared launches with graph replays against one design at a time, (a)
+    with the same graph replays and chunk (the gain of shared launches
+    alone) and (b) as plain solves: the forward run, then the adjoint run,
+    plain launches, no graph (no right-hand-side sharing); equal steps and
+    windows, so equal accuracy."""
+    import numpy as np
     import torch
     from paper_2505_03352_amd import batch
     from paper_2505_03352_amd.plan import plan_for
@@ -470,33 +479,107 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     log(f"batched: {t_batch:.2f} s")
-    t0 = time.perf_counter()
-    same = True
-    for p, (a0, g0) in zip(plans, res_b):
-        p.run(3, chunk=args.chunk, use_graph=False)
-        a = p.alpha()
-        g = p.gradient(torch.conj(a))
-        same &= bool((a.cpu().numpy() == a0).all() and (g.cpu().numpy() == g0).all())
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    log(f"one at a time: {t_seq:.2f} s, identical results: {same}")
+
+    def one_at_a_time(plain):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        same, worst = True, 0.0
+        for p, (a0, g0) in zip(plans, res_b):
+            if plain:
+                p.run(1, chunk=args.chunk, use_graph=False)
+                p.run(2, chunk=args.chunk, use_graph=False)
+            else:
+                p.run(3, chunk=args.chunk, use_graph=True)
+            a = p.alpha()
+            g = p.gradient(torch.conj(a)).cpu().numpy()
+            a = a.cpu().numpy()
+            same &= bool((a == a0).all() and (g == g0).all())
+            worst = max(worst, float(np.abs(g - g0).max() / np.abs(g0).max()))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, same, worst
+
+    t_seq, same, _ = one_at_a_time(False)
+    log(f"one at a time, graph replays: {t_seq:.2f} s, identical results: {same}")
+    t_plain, same_plain, worst_plain = one_at_a_time(True)
+    log(f"one at a time, plain forward then adjoint runs: {t_plain:.2f} s, identical results: "
+        f"{same_plain} (largest gradient difference {worst_plain:.1e} of its maximum)")
     for p in plans:
         p.close()
+
+    def rec(t):
+        return {"designs_per_h": round(3600 * len(devs) / t, 1),
+                "gcell_updates_per_s": round(cells / t / 1e9, 3), "seconds": round(t, 3)}
     _line("designs/hour (batched, 8 uneven designs)", 3600 * len(devs) / t_batch, "designs/h",
           t_batch * 1e3, args,
           {"workload": "batch: 8 designs, axes uniform in 128..320 x 96..240 x 64..96 at 20 nm, "
                        "1 wavelength, forward + adjoint + gradient each, seeds 100..107"},
           {"gcell_updates_per_s": round(cells / t_batch / 1e9, 3),
-           "one_at_a_time": {"designs_per_h": round(3600 * len(devs) / t_seq, 1),
-                             "gcell_updates_per_s": round(cells / t_seq / 1e9, 3),
-                             "seconds": round(t_seq, 3)},
-           "speedup": round(t_seq / t_batch, 3), "identical_results": same})
+           "one_at_a_time_graph": dict(rec(t_seq), identical_results=same),
+           "one_at_a_time_plain": dict(rec(t_plain), identical_results=same_plain,
+                                       max_gradient_diff_over_max=worst_plain,
+                                       how="forward run then adjoint run per design, plain "
+                                           "launches, no graph"),
+           "speedup_vs_graph": round(t_seq / t_batch, 3),
+           "speedup_vs_plain": round(t_plain / t_batch, 3)})
+
+
+class PlainOneAtATime:
+    """The serving baseline of plain solves: requests in arrival order, one
+    at a time; each wavelength of a request is its own plan (one forward and
+    one adjoint right-hand side, the request's steps and windows), run as a
+    forward solve and then an adjoint solve with plain launches and no graph;
+    the request's gradient is the sum over its wavelengths."""
+
+    def __init__(self, torch, chunk):
+        self.torch = torch
+        self.chunk = chunk
+
+    def run(self, trace, on_done=None):
+        from paper_2505_03352_amd.plan import plan_for
+        from paper_2505_03352_amd.serve import ServeStats, percentile
+        from workloads import configs
+        torch = self.torch
+        t0 = time.perf_counter()
+        lat, results, cu = [], [], 0.0
+        for i, (arr, cls, lams) in enumerate(trace):
+            now = time.perf_counter() - t0
+            if now < arr:
+                time.sleep(arr - now)
+            n_steps = configs.serving_request(i, cls, lams).n_steps
+            alphas, g_sum = [], None
+            for lam in lams:
+                dev = configs.serving_request(i, cls, [lam], n_steps=n_steps)
+                p = plan_for(dev, device="cuda:0")
+                p.run(1, chunk=self.chunk, use_graph=False)
+                p.run(2, chunk=self.chunk, use_graph=False)
+                a = p.alpha()
+                g = p.gradient(torch.conj(a))
+                alphas.append(a.cpu().numpy())
+                g_sum = g if g_sum is None else g_sum + g
+                cu += 2 * dev.cells * dev.n_steps
+                p.close()
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            lat.append(t - arr)
+            results.append((alphas, g_sum.cpu().numpy()))
+            if on_done is not None:
+                on_done(i, t)
+        makespan = (time.perf_counter() - t0) - min(t for t, _, _ in trace)
+        import numpy as np
+        st = ServeStats(n_done=len(lat), n_rejected=0, makespan_s=makespan, p50_s=percentile(lat, 50),
+                        p99_s=percentile(lat, 99), mean_s=float(np.mean(lat)),
+                        throughput_per_h=3600.0 * len(lat) / makespan, max_active=1, peak_bytes=0,
+                        cell_updates=cu, latencies=lat)
+        return st, results
 
 
 def bench_serving(args):
-    """The first N requests of the Poisson trace (4 req/s): continuous
-    batching with `--slots` concurrent requests against one request at a
-    time on the same trace."""
+    """The first N requests of the Poisson trace: continuous batching with
+    `--slots` concurrent requests against (plain) one request at a time with
+    plain forward-then-adjoint solves per wavelength, and (same) the served
+    loop's own executor with one slot and the same route; `--sides` picks
+    which of the three run."""
+    import numpy as np
     import torch
     from paper_2505_03352_amd.serve import GpuExecutor, Request, Scheduler
     from workloads import configs
@@ -510,42 +593,62 @@ def bench_serving(args):
 
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
-    out = {}
-    runs = (("served", args.slots),) if args.no_baseline else (("served", args.slots), ("one_at_a_time", 1))
-    for name, slots in runs:
-        # --pulse: the served loop evaluates multi-wavelength requests from
-        # pulse runs where that is cheaper; the one-at-a-time baseline stays
-        # time-harmonic
-        ex = GpuExecutor(build, device="cuda:0", chunk=args.chunk, pulse_multi=args.pulse and slots > 1)
-        reqs = [Request(i, t, (i, cls, lams)) for i, (t, cls, lams) in enumerate(trace)]
-        cap = args.max_cells if slots > 1 else None
+    sides = [x for x in args.sides.split(",") if x]
+    out, res = {}, {}
+    for name in sides:
         t_start = time.perf_counter()
 
-        def done(r, name=name):
-            if r.rid % 10 == 9:
-                log(f"{name}: request {r.rid} done at {time.perf_counter() - t_start:.1f} s")
+        def done(rid, t=None, name=name):
+            if rid % 10 == 9:
+                log(f"{name}: request {rid} done at {time.perf_counter() - t_start:.1f} s")
 
-        st = Scheduler(ex, max_slots=slots, hbm_budget=budget, chunk=args.chunk,
-                       max_active_cells=cap, on_done=done).run(reqs)
+        if name == "plain":
+            st, res[name] = PlainOneAtATime(torch, args.chunk).run(trace, on_done=done)
+        else:
+            slots = args.slots if name == "served" else 1
+            # --pulse: multi-wavelength requests from pulse runs where cheaper
+            ex = GpuExecutor(build, device="cuda:0", chunk=args.chunk, pulse_multi=args.pulse,
+                             dft_stride=args.dft_stride)
+            reqs = [Request(i, t, (i, cls, lams)) for i, (t, cls, lams) in enumerate(trace)]
+            cap = args.max_cells if slots > 1 else None
+            st = Scheduler(ex, max_slots=slots, hbm_budget=budget, chunk=args.chunk,
+                           max_active_cells=cap, on_done=lambda r: done(r.rid)).run(reqs)
+            res[name] = [(None, r.result["grad"]) for r in sorted(reqs, key=lambda r: r.rid)]
         torch.cuda.synchronize()
         out[name] = st
         log(f"{name}: {st.as_dict()}")
-    s, b = out["served"], out.get("one_at_a_time")
-    _line("p50/p99 request latency and designs/hour (continuous batching)", s.throughput_per_h,
-          "designs/h", s.makespan_s * 1e3, args,
+    diffs = {}
+    if len(res) > 1:
+        names = list(res)
+        for other in names[1:]:
+            d = max(float(np.abs(a[1] - b[1]).max() / np.abs(b[1]).max())
+                    for a, b in zip(res[names[0]], res[other]))
+            diffs[f"{names[0]}_vs_{other}_max_gradient_diff"] = d
+            log(f"gradients {names[0]} vs {other}: largest difference {d:.1e} of the maximum")
+
+    def rec(st):
+        return {"designs_per_h": round(st.throughput_per_h, 1), "p50_s": round(st.p50_s, 3),
+                "p99_s": round(st.p99_s, 3), "mean_s": round(st.mean_s, 3),
+                "makespan_s": round(st.makespan_s, 2),
+                "gcell_updates_per_s": round(st.cell_updates / st.makespan_s / 1e9, 3)}
+    head = out.get("served") or next(iter(out.values()))
+    extra = {k: rec(v) for k, v in out.items()}
+    if "served" in out:
+        for k in out:
+            if k != "served":
+                extra[f"speedup_vs_{k}"] = round(out["served"].throughput_per_h / out[k].throughput_per_h, 3)
+    extra.update(diffs)
+    _line("p50/p99 request latency and designs/hour (continuous batching)", head.throughput_per_h,
+          "designs/h", head.makespan_s * 1e3, args,
           {"workload": f"serving: first {args.requests} of 200 Poisson arrivals at {args.rate:g} req/s, "
                        "sizes 96^3+-8 / 200x160x80 / 320x240x96, 1-3 wavelengths, forward + "
                        "adjoint + gradient, seed 200" + (
-                           "; served: multi-wavelength requests from pulse runs where cheaper"
-                           if args.pulse else ""), "slots": args.slots,
+                           "; multi-wavelength requests from pulse runs where cheaper (served "
+                           "and same)" if args.pulse else "; time-harmonic runs"),
+           "sides": sides, "slots": args.slots,
            "max_active_cell_updates_per_step": args.max_cells,
            "hbm_budget_bytes": budget},
-          {"p50_s": round(s.p50_s, 3), "p99_s": round(s.p99_s, 3),
-           "gcell_updates_per_s": round(s.cell_updates / s.makespan_s / 1e9, 3),
-           "one_at_a_time": None if b is None else {
-               "designs_per_h": round(b.throughput_per_h, 1), "p50_s": round(b.p50_s, 3),
-               "p99_s": round(b.p99_s, 3),
-               "gcell_updates_per_s": round(b.cell_updates / b.makespan_s / 1e9, 3)}})
+          extra)
 
 
 def bench_batch_fd(args):
@@ -658,7 +761,7 @@ def bench_broadband(args):
     n_h = ph.n_rhs
     dp = make(n_steps=args.pulse_steps or (7000 if args.device == "realistic" else 12000))
     w0, sig, t0 = dp.pulse(k=0.4 if args.pulse_k is None else args.pulse_k)
-    pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0))
+    pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0, args.dft_stride))
     tp = autotune.tune(pp, YO_BOTH, use_cache=False)
     s_p, a_p, g_p = timed(pp, args.steps)
     ea = float(np.abs(a_p - a_h).max() / np.abs(a_h).max())
@@ -726,7 +829,7 @@ def bench_optimize(args):
         plan.close()
         run_dev = configs.demux(n_steps=args.pulse_steps or 12000)
         w0, sig, t0 = run_dev.pulse(k=1.0 if args.pulse_k is None else args.pulse_k)
-        plan = plan_for(run_dev, device="cuda:0", pulse=(w0 / run_dev.dt(), sig, t0))
+        plan = plan_for(run_dev, device="cuda:0", pulse=(w0 / run_dev.dt(), sig, t0, args.dft_stride))
         tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
         s_p, a_p, g_p = one(plan)
         ea = float(np.abs(a_p - a_h).max() / np.abs(a_h).max())

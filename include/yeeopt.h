@@ -168,6 +168,19 @@ yo_status yo_set_alpha_terms(yo_plan *plan, int terms);
  * carrier outside (0, pi/dt) or t0 < 0.  Changes yo_workspace_bytes. */
 yo_status yo_set_pulse(yo_plan *plan, double omega0, double sigma_steps, double t0_steps);
 
+/* Under a pulse (yo_set_pulse first), host only, before yo_bind_workspace
+ * (YO_ESTATE after): the DFT adds E^n only on the steps n divisible by
+ * `stride` (1..64; 1, the default, is every step), and the phasors become
+ * 2 stride DFT(w) / S(w).  The sampled sum is (1/stride) times the sum of
+ * the full DFT at w + 2 pi q / stride, q = 0..stride-1, so the phasors stay
+ * those of the full DFT when the pulse's spectrum vanishes at every alias
+ * q != 0: YO_EINVAL unless it is below 1e-6 of its value at w there (and for
+ * the pulse's conjugate part) at every wavelength; the FP32 rounding of the
+ * stored samples alone leaves about 1e-8.  The DFT's memory traffic
+ * drops by the stride.  YO_EINVAL without a pulse or for a stride outside
+ * [1, 64]; turning the pulse off resets it to 1. */
+yo_status yo_set_dft_stride(yo_plan *plan, int stride);
+
 /* Device bytes the plan needs (host only). */
 yo_status yo_workspace_bytes(const yo_plan *plan, size_t *bytes);
 

@@ -63,6 +63,7 @@ struct YoPlanD {
     int box[6];              // x0 y0 z0 bx by bz
     int n_ports;
     int n_steps;
+    int dft_stride;          // the DFT adds E^n of the steps n divisible by it (1: every step)
     YoPlaneD ports[YO_MAX_PORTS];
     int mon_off[YO_MAX_PORTS];
     int mon_total;

@@ -106,6 +106,7 @@ struct yo_plan {
     int n_phys = 0, n_pfwd = 0;
     bool pulse = false;
     double pulse_w = 0, pulse_sigma = 0, pulse_t0 = 0;
+    int dft_stride = 1;          // under a pulse: the DFT samples every dft_stride-th step
     std::vector<float> fin;      // [n_freq][4] phasor matrices applied at finalize
     int mon_nc = 2;              // component planes per port (5: two-term coefficient)
     std::vector<yo_freq> freqs;
@@ -366,7 +367,9 @@ void build_steptab(yo_plan *p)
             const std::complex<double> sm((double)row[n].x, -(double)row[n].y);
             S += sm * std::polar(1.0, p->omega_dt[f] * (n + 0.5));
         }
-        const std::complex<double> c = 2.0 / S;
+        // sampling every m-th step divides the sum by m (its aliases, at
+        // w + 2 pi q / m, carry no pulse spectrum: yo_set_dft_stride checks)
+        const std::complex<double> c = 2.0 * p->dft_stride / S;
         p->fin[4 * f + 0] = (float)c.real();
         p->fin[4 * f + 1] = (float)(-c.imag());
         p->fin[4 * f + 2] = (float)c.imag();
@@ -789,6 +792,7 @@ static yo_status rebuild_descriptors(yo_plan *p)
     P.n_ports = p->n_ports;
     P.mon_nc = p->mon_nc;
     P.n_steps = p->n_steps;
+    P.dft_stride = p->pulse ? p->dft_stride : 1;
     P.mon_total = (int)p->mon_total;
     for (int q = 0; q < p->n_ports; ++q) {
         const yo_plane &pl = p->port_planes[q];
@@ -995,6 +999,7 @@ yo_status yo_set_pulse(yo_plan *p, double omega0, double sigma_steps, double t0_
     if (p->ws) return fail(YO_ESTATE, "set the pulse before binding a workspace");
     if (!(sigma_steps > 0)) {
         p->pulse = false;
+        p->dft_stride = 1;
         p->n_phys = p->n_rhs;
         p->n_pfwd = p->n_fwd;
     } else {
@@ -1047,6 +1052,40 @@ static yo_status bind_ws(yo_plan *p, void *dev, size_t bytes, hipStream_t s)
     p->design_set = false;
     p->steps_done = 0;
     for (int q = 0; q < 2; ++q) p->finalized[q] = p->unstable[q] = false;
+    return YO_OK;
+}
+
+yo_status yo_set_dft_stride(yo_plan *p, int stride)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (p->ws) return fail(YO_ESTATE, "set the DFT stride before binding a workspace");
+    if (!p->pulse) return fail(YO_EINVAL, "a DFT stride needs pulse excitation (yo_set_pulse)");
+    if (stride < 1 || stride > 64) return fail(YO_EINVAL, "stride must be in [1, 64]");
+    // the sampled sum equals (1/m) sum_q DFT(w + 2 pi q / m); the pulse's own
+    // spectrum S at every alias q != 0 (and that of its conjugate part, at
+    // -w0) must be negligible against S(w) for the phasor to stay exact
+    const float4 *row = p->steptab.data() + (size_t)p->n_freq * p->n_steps;
+    auto spec = [&](double w, bool conj) {
+        std::complex<double> S = 0.0;
+        for (int n = 0; n < p->n_steps; ++n) {
+            const std::complex<double> sm((double)row[n].x, (conj ? 1.0 : -1.0) * (double)row[n].y);
+            S += sm * std::polar(1.0, w * (n + 0.5));
+        }
+        return std::abs(S);
+    };
+    for (int f = 0; f < p->n_freq && stride > 1; ++f) {
+        const double w = p->omega_dt[f];
+        const double s0 = spec(w, false);
+        for (int q = 1; q < stride; ++q) {
+            const double wa = w + 2.0 * M_PI * q / stride;
+            const double leak = std::max(spec(wa, false), spec(wa, true));
+            if (!(leak <= 1e-6 * s0))
+                return fail(YO_EINVAL, "DFT stride %d: the pulse spectrum at the alias %d of wavelength %d "
+                                       "is %.2e of its value there", stride, q, f, leak / s0);
+        }
+    }
+    p->dft_stride = stride;
+    build_steptab(p);
     return YO_OK;
 }
 
@@ -1367,8 +1406,11 @@ static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, 
 // n_launch to every plan's counter.  Per step: DFT of E^n (when `with_dft`),
 // the step launches (interior, CPML shell), the source.  Plans must share
 // every tiling flag but the x-split ones.
+// DFT launches: at the steps k of the call with k % dft_every == 0 (the
+// kernel itself skips steps its plan does not sample).
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
-                              bool with_dft, hipStream_t s, yo_plan *timed = nullptr)
+                              bool with_dft, hipStream_t s, yo_plan *timed = nullptr,
+                              int dft_every = 1)
 {
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
@@ -1380,7 +1422,7 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
         aux_args(plans + base, which + base, cnt, true, ad);
         aux_args(plans + base, which + base, cnt, false, as);
         for (int k = 0; k < n_launch; ++k) {
-            if (with_dft) {
+            if (with_dft && k % dft_every == 0) {
                 ad.k_offset = k;
                 HIPCHK(yo_launch_dft(ad, s));
             }
@@ -1414,6 +1456,18 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
         HIPCHK(yo_launch_ctr(ca, 0, s));
     }
     return YO_OK;
+}
+
+// The DFT stride every plan of the list samples, when they share one and all
+// stand at a step it divides (then the DFT kernel need only be launched on
+// every stride-th step of a call); else 1.
+static int dft_every(yo_plan *const *plans, int n)
+{
+    const int st = plans[0]->pulse ? plans[0]->dft_stride : 1;
+    if (st <= 1) return 1;
+    for (int i = 0; i < n; ++i)
+        if (!plans[i]->pulse || plans[i]->dft_stride != st || plans[i]->steps_done % st) return 1;
+    return st;
 }
 
 // does any plan's DFT window meet the steps [steps_done, steps_done + count)?
@@ -1469,6 +1523,11 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
             key += "#" + std::to_string(plans[i]->id) + ":" + std::to_string(plans[i]->generation) +
                    "w" + std::to_string(which[i]) + "k" + std::to_string(plans[i]->kc) + "f" +
                    std::to_string(plans[i]->tflags);
+        // a graph launching the DFT only on every stride-th step is replayed
+        // only at steps the stride divides: its chunk must be a multiple
+        int every = dft_every(plans, n);
+        if (chunk % every) every = 1;
+        key += "e" + std::to_string(every);
         GraphEntry ge[2];
         while (n_steps - tail - done >= chunk) {
             const int variant = chunk_needs_dft(plans, which, n, chunk) ? 1 : 0;
@@ -1482,7 +1541,8 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
                 yo_plan *p0 = plans[0];
                 if (!p0->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p0->cap_stream, hipStreamNonBlocking));
                 HIPCHK(hipStreamBeginCapture(p0->cap_stream, hipStreamCaptureModeThreadLocal));
-                yo_status st = launch_steps(plans, which, n, chunk, variant == 1, p0->cap_stream);
+                yo_status st = launch_steps(plans, which, n, chunk, variant == 1, p0->cap_stream, nullptr,
+                                            every);
                 hipGraph_t graph = nullptr;
                 hipError_t e = hipStreamEndCapture(p0->cap_stream, &graph);
                 if (st) {
@@ -1507,7 +1567,7 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         const int lim = in_tail ? n_steps - done : n_steps - tail - done;
         const int k = std::min(chunk, lim);
         yo_status st = launch_steps(plans, which, n, k, chunk_needs_dft(plans, which, n, k), s,
-                                    in_tail ? timed : nullptr);
+                                    in_tail ? timed : nullptr, dft_every(plans, n));
         if (st) return st;
         done += k;
         bump(k);

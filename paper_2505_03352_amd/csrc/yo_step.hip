@@ -653,8 +653,9 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
     } else {
         // A block's waves take consecutive tiles (neighbouring x-strips of
         // the same rows) of one right-hand side, so together they stream
-        // contiguous row segments; consecutive blocks take the same tiles
-        // for the next right-hand sides.
+        // contiguous row segments and share the cache lines at the strips'
+        // edges; consecutive blocks take the same tiles for the next
+        // right-hand sides, which share kappa.
         const int grp = local / (wpb * sl.nrhs);
         const int in_grp = local - grp * (wpb * sl.nrhs);
         const int r = sl.rhs0 + in_grp / wpb;
@@ -690,7 +691,8 @@ __device__ __forceinline__ void plane_component(int axis, int index, int tt, int
 
 // Running DFT of E^n (called before step n): S += E^n exp(+i w n dt) on the
 // design box (3 components) and the port planes (2 tangential components),
-// for each frequency the right-hand side accumulates.
+// for each frequency the right-hand side accumulates; under a pulse with a
+// DFT stride m > 1 only the steps divisible by m add.
 __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
 {
     int s, r, q;
@@ -701,6 +703,7 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
     const YoRhsD &R = P.rhs[r];
     const int w = step - R.win_start;
     if (w < 0 || w >= R.win_len) return;
+    if (P.dft_stride > 1 && step % P.dft_stride) return;
     const float *F = R.F[step & 1];
     const int bx = P.box[3], by = P.box[4], bz = P.box[5];
     const int bsz = bx * by * bz;

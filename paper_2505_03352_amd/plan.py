@@ -58,8 +58,9 @@ class Plan:
     def __init__(self, grid: dict, design: dict, n_steps: int, freqs: Sequence[FreqSpec],
                  src_planes: Sequence, port_planes: Sequence, device="cuda", pulse=None,
                  two_term: bool = False):
-        """pulse: None, or (omega0 rad/s, sigma steps, t0 steps) for pulse
-        excitation (one run per source and per port for all wavelengths).
+        """pulse: None, or (omega0 rad/s, sigma steps, t0 steps[, DFT stride])
+        for pulse excitation (one run per source and per port for all
+        wavelengths; the DFT samples every stride-th step, default 1).
         two_term: the modal coefficient with both of its terms (App. A)."""
         self.device = torch.device(device)
         self.grid = dict(grid)
@@ -100,6 +101,8 @@ class Plan:
         self.pulse = tuple(pulse) if pulse is not None else None
         if self.pulse is not None:
             call("yo_set_pulse", self._h, float(pulse[0]), float(pulse[1]), float(pulse[2]))
+            if len(self.pulse) > 3 and int(self.pulse[3]) != 1:
+                call("yo_set_dft_stride", self._h, int(self.pulse[3]))
         nb = ct.c_size_t()
         call("yo_workspace_bytes", self._h, ct.byref(nb))
         self.workspace_bytes = int(nb.value)

@@ -296,7 +296,7 @@ class GpuExecutor:
     z-planes per tile, flags 200), since admitted requests share launches."""
 
     def __init__(self, build: Callable, device="cuda:0", tiling=(4, 10, 200), use_graph=False,
-                 chunk: int = 100, pulse_multi: bool = False):
+                 chunk: int = 100, pulse_multi: bool = False, dft_stride: int = 4):
         import torch
         from . import _abi  # noqa: F401  (fails loudly without the library)
         self.torch = torch
@@ -306,6 +306,7 @@ class GpuExecutor:
         self.use_graph = use_graph
         self.chunk = chunk
         self.pulse_multi = pulse_multi
+        self.dft_stride = dft_stride       # pulse runs: the DFT samples every dft_stride-th step
         self.compute = torch.cuda.Stream(self.device)
         self.setup = torch.cuda.Stream(self.device)
         self._inflight = collections.deque()
@@ -330,7 +331,7 @@ class GpuExecutor:
         grid, design = grid_design_of(dev)
         plan = Plan(grid, design, dev.n_steps, freqs_of(dev), [m.plane for m in dev.sources],
                     [m.plane for m in dev.ports], device=self.device,
-                    pulse=None if pulse is None else pulse[:3])
+                    pulse=None if pulse is None else tuple(pulse[:3]) + (self.dft_stride,))
         plan.set_tiling(*self.tiling)
         host = dict(kappa=self.torch.as_tensor(dev.kappa_bg, dtype=self.torch.float32),
                     mask=self.torch.as_tensor(dev.mask_hr, dtype=self.torch.float32),

@@ -232,3 +232,22 @@ def test_static_workspace_rejects_a_plan_beyond_its_size():
     assert e.value.status == _abi.YO_EWORKSPACE
     assert "static workspace" in str(e.value)
     p.close()
+
+
+def test_dft_stride_arguments():
+    """yo_set_dft_stride needs a pulse, a stride in [1, 64], a pulse whose
+    spectrum vanishes at the aliases, and no workspace yet."""
+    dev = configs.tiny()
+    p = _create(dev)
+    L = _abi.lib()
+    assert L.yo_set_dft_stride(p.handle, 4) == _abi.YO_EINVAL          # no pulse
+    w0 = 2 * np.pi * 299792458.0 / 1.55e-6
+    assert L.yo_set_pulse(p.handle, w0, 80.0, 400.0) == _abi.YO_OK
+    assert L.yo_set_dft_stride(p.handle, 0) == _abi.YO_EINVAL
+    assert L.yo_set_dft_stride(p.handle, 65) == _abi.YO_EINVAL
+    assert L.yo_set_dft_stride(p.handle, 4) == _abi.YO_OK
+    # a pulse a few steps long has a spectrum wide enough to alias
+    assert L.yo_set_pulse(p.handle, w0, 1.5, 10.0) == _abi.YO_OK
+    assert L.yo_set_dft_stride(p.handle, 8) == _abi.YO_EINVAL
+    assert b"alias" in L.yo_last_error()
+    p.close()
