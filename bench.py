@@ -31,7 +31,7 @@ METRIC = "Gcell-updates/s + % HBM peak; adjoint gradients/hour; p50/p99 solve la
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2505_03352_amd/csrc/yo_step.hip", "paper_2505_03352_amd/csrc/yo_internal.h"]
 PROFILES = os.path.join(ROOT, "profiles")
-PART_NAMES = ("interior", "shell")
+PART_NAMES = ("interior", "shell", "two_step", "frame")
 
 
 def log(*a):
@@ -48,9 +48,12 @@ def kernel_sha() -> str:
 
 # yo_set_tiling flag bits that change each launch's work split: the interior
 # (x-shell layouts 1, 128 and 256, 8 waves per block, cooperative interior
-# blocks, no interior prefetch) and the CPML shell (the x-shell layouts, 8
-# waves per block, cooperative shell blocks, per-class code, no shell prefetch)
-SPLIT_BITS = (1 | 2 | 16 | 32 | 128 | 256, 1 | 2 | 4 | 8 | 64 | 128 | 256)
+# blocks, no interior prefetch), the CPML shell (the x-shell layouts, 8 waves
+# per block, cooperative shell blocks, per-class code, no shell prefetch),
+# the two-step launch (x-shell layouts, 8 waves per block) and the interior
+# around it (the same and no prefetch); 512 (two steps per launch) in all
+SPLIT_BITS = (1 | 2 | 16 | 32 | 128 | 256 | 512, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512,
+              1 | 2 | 128 | 256 | 512, 1 | 2 | 32 | 128 | 256 | 512)
 
 
 def part_split(tiling, part: int) -> str:
@@ -235,17 +238,26 @@ def calibration_copy(torch):
     del cal_src, cal_dst, evict
 
 
+KERNEL_OF_PART = ("k_yee_step interior tiles", "k_yee_step CPML shell tiles",
+                  "k_yee_step2 two-step region (two steps per launch)",
+                  "k_yee_step interior tiles around the two-step region")
+
+
 def part_rooflines(plan, timed, tiling, workload, sha):
-    """Per launch part: HIP-event duration inside the timed region, the
-    part's algorithmic bytes per launch, and the committed counter figure
-    when it belongs to this kernel and split."""
+    """Per launch part that ran in the timed region: HIP-event duration, the
+    part's algorithmic bytes per launch (the two-step launch counts both of
+    its steps), the share of the timed kernels' time, and the committed
+    counter figure when it belongs to this kernel and split."""
     out = []
-    for part in (0, 1):
-        ms, n = timed[part]
+    total = sum(ms * n for ms, n in timed)
+    for part, (ms, n) in enumerate(timed):
+        if n == 0:
+            continue
         _, b, cells = plan.time_kernel(part, 1)
         ach = b / (ms / 1e3) / 1e9 if ms > 0 else 0.0
-        out.append({"kernel": f"k_yee_step {PART_NAMES[part]} tiles", "part": PART_NAMES[part],
+        out.append({"kernel": KERNEL_OF_PART[part], "part": PART_NAMES[part],
                     "ms_per_launch": round(ms, 4), "launches_timed": n,
+                    "time_share": round(ms * n / total, 4) if total > 0 else None,
                     "bytes_per_launch": b, "cell_updates_per_launch": cells,
                     "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": read_traffic(traffic_file(part, workload), sha,
@@ -254,9 +266,10 @@ def part_rooflines(plan, timed, tiling, workload, sha):
 
 
 def roofline_of(parts):
-    """The bench line's roofline object: the launch that takes the most time
-    per step (each part launches once per step), with the other beside it."""
-    dom = max(parts, key=lambda q: q["ms_per_launch"])
+    """The bench line's roofline object: the launch part that takes the most
+    of the timed kernel time (launches times mean duration), with the others
+    beside it."""
+    dom = max(parts, key=lambda q: q["ms_per_launch"] * q["launches_timed"])
     return {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["frac"], "traffic": dom["traffic"], "kernel": dom["kernel"],
             "bytes_per_launch": dom["bytes_per_launch"], "ms_per_launch": dom["ms_per_launch"],
@@ -270,27 +283,40 @@ def realistic_gradients(args, torch, n_timed=1):
     from paper_2505_03352_amd.plan import plan_for
     from workloads import configs
     dev = configs.realistic()
-    plan = plan_for(dev, device="cuda:0")
+    plan = plan_for(dev, device="cuda:0", time_blocking=2)
     tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
     tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"])
     C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
 
-    def grad():
+    from paper_2505_03352_amd.plan import advance_many
+    mid = dev.n_steps // 2
+
+    def grad(timing):
+        # one solve as yo_run does it (reset, chunked steps, finalize), its
+        # middle 100 steps, before the DFT window, in a call of their own with
+        # HIP events around every launch part (those steps run as plain
+        # launches)
         plan.set_design(C, dev.beta)
-        plan.run(YO_BOTH, chunk=args.chunk, use_graph=not args.eager)
+        plan.reset(YO_BOTH)
+        g = not args.eager
+        advance_many([plan], [YO_BOTH], mid, chunk=args.chunk, use_graph=g)
+        if timing:
+            plan.set_timing(2, 100)
+        advance_many([plan], [YO_BOTH], 100, chunk=args.chunk, use_graph=g)
+        plan.set_timing(2, 0)          # off; what was recorded stays
+        advance_many([plan], [YO_BOTH], dev.n_steps - mid - 100, chunk=args.chunk, use_graph=g)
+        plan.finalize(YO_BOTH)
         a = plan.alpha()
         return plan.gradient(torch.conj(a))
 
-    grad()
-    # HIP events around both parts' launches of the last 100 steps of each solve
-    plan.set_timing(2, 100)
+    grad(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(n_timed):
-        grad()
+        grad(True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / n_timed
-    timed = [plan.timing(0), plan.timing(1)]
+    timed = [plan.timing(q) for q in range(4)]
     plan.set_timing(0, 0)
     plan.reset(YO_BOTH)
     plan.advance(YO_BOTH, 4)
@@ -326,7 +352,7 @@ def bench_headline(args):
     log(f"workload {dev.name}: {dev.nx}x{dev.ny}x{dev.nz}, {dev.n_freq} wavelengths, "
         f"{len(dev.ports)} ports, {dev.n_steps} steps; bench step = {block} Yee steps of all "
         f"right-hand sides ({n_blocks} per solve)")
-    plan = plan_for(dev, device="cuda:0")
+    plan = plan_for(dev, device="cuda:0", time_blocking=2)
     calibration_copy(torch)
     tuned = None
     if not args.no_autotune:
@@ -372,14 +398,14 @@ def bench_headline(args):
     for _ in range(args.warmup):
         bench_step()
     torch.cuda.synchronize()
-    # HIP events around both parts' launches of the last `tail` steps of each block
+    # HIP events around every launch part's launches of the last `tail` steps of each block
     plan.set_timing(2, tail)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         bench_step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    timed = [plan.timing(0), plan.timing(1)]
+    timed = [plan.timing(q) for q in range(4)]
     plan.set_timing(0, 0)
     ms = (t1 - t0) / args.steps * 1e3
     cells_per_step = plan.n_rhs * dev.cells * block

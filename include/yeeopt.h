@@ -181,6 +181,20 @@ yo_status yo_set_pulse(yo_plan *plan, double omega0, double sigma_steps, double 
  * [1, 64]; turning the pulse off resets it to 1. */
 yo_status yo_set_dft_stride(yo_plan *plan, int stride);
 
+/* Temporal blocking (Sec. 2: the diamond / wavefront tilings of x-y-z-t that
+ * fdtd-z shares with DiamondTorre, advancing several steps per pass over
+ * memory), host only, before yo_bind_workspace (YO_ESTATE after).  steps = 2
+ * gives every right-hand side a third state buffer (the state after step s
+ * lives in buffer s % 3), so that the interior cells two clear of every
+ * absorbing slab and of every source and port plane (the two-step region)
+ * can be advanced two steps in one launch that reads each of their planes
+ * once; tiling flag 512 (yo_set_tiling) then turns the pairs on.  Steps
+ * whose DFT the plan needs (the time-harmonic window) and a run's odd last
+ * step go one at a time.  Results are bitwise those of single steps.
+ * steps = 1 (the default) removes the buffer.  Changes yo_workspace_bytes.
+ * YO_EINVAL for other values. */
+yo_status yo_set_time_blocking(yo_plan *plan, int steps);
+
 /* Device bytes the plan needs (host only). */
 yo_status yo_workspace_bytes(const yo_plan *plan, size_t *bytes);
 
@@ -289,6 +303,11 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
  *       interior is cut into whole 62-cell strips (overrides 1)
  *  256  tiles that meet only the x-slabs run in the interior launch, which
  *       then carries the x-axis CPML code
+ *  512  two steps per launch over the two-step region where the run
+ *       allows (needs yo_set_time_blocking(plan, 2); not with 16): its
+ *       tiles are strips of at most 60 cells, 4 rows and zchunk planes, and
+ *       the rest of the interior runs as single-step tiles around it (with
+ *       256, together with the tiles that meet only the x-slabs)
  * Other bits: YO_EINVAL.  Results do not depend on the split (bitwise).
  * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);
@@ -348,8 +367,11 @@ yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
                          double *cell_updates_per_step);
 
 /* Measurement: time `n_launch` launches of one part of the time-stepping
- * kernel (cls 0: interior tiles, 1: CPML shell; other values YO_EINVAL; an
- * empty part reports zeros and launches nothing) over the
+ * kernel (cls 0: interior tiles, 1: CPML shell, 2: the two-step region's
+ * launch, which advances its cells two steps (its bytes and cell-updates
+ * count both; YO_ESTATE unless two steps remain in the run), 3: the interior
+ * around it; other values YO_EINVAL; an empty part reports zeros and
+ * launches nothing) over the
  * right-hand sides selected by the last yo_reset, at the current step, with
  * HIP events on `stream`; blocks until done.  The launches re-run the same
  * step (they read the current buffers and do not advance the counter), so
@@ -379,14 +401,17 @@ yo_status yo_adam_step(float *dev_C, const float *dev_G, float *dev_M, float *de
  * yo_run or yo_advance_many (with this plan first in its list) runs its
  * last n_last steps with plain launches and records a pair of HIP events on
  * its stream around each launch of `part` (0 interior tiles, 1 CPML shell,
- * 2 both); the pairs accumulate over calls until the next yo_set_timing,
- * which clears them.  n_last = 0 turns it off.  n_last <= 4096; the events
+ * 2 every part, including the two-step region's launches and the interior
+ * around it under tiling flag 512); the pairs accumulate over calls until
+ * the next yo_set_timing with n_last > 0, which clears them.  n_last = 0
+ * turns it off and keeps what was recorded.  n_last <= 4096; the events
  * are created as needed (outside graph capture: the timed steps are never
  * captured) and owned by the plan.  Host only.  YO_EINVAL on a bad part or
  * count. */
 yo_status yo_set_timing(yo_plan *plan, int part, int n_last);
 
-/* Mean duration of the launches of `part` (0 or 1) timed since the last
+/* Mean duration of the launches of `part` (0 interior, 1 CPML shell, 2 the
+ * two-step region, 3 the interior around it) timed since the last
  * yo_set_timing (waits for the last of them); count = how many (0: none,
  * avg_ms = 0). */
 yo_status yo_get_timing(yo_plan *plan, int part, float *avg_ms, int *count);

@@ -67,6 +67,7 @@ _SIGS = {
     "yo_set_morphology": [_P, ct.c_char_p, ct.c_double, ct.c_double],
     "yo_set_pulse": [_P, ct.c_double, ct.c_double, ct.c_double],
     "yo_set_dft_stride": [_P, _I],
+    "yo_set_time_blocking": [_P, _I],
     "yo_set_alpha_terms": [_P, _I],
     "yo_workspace_bytes": [_P, ct.POINTER(ct.c_size_t)],
     "yo_bind_workspace": [_P, _P, ct.c_size_t, _S],

@@ -9,8 +9,11 @@ shell choice (cooperative, per-class code, prefetch) with the shell launch
 alone, on the real grid with HIP events (the kernel-timing entry point
 re-runs one step without advancing), and keeps the fastest sum.  Results are
 cached in a JSON file keyed by the shape class (architecture, padded x
-extent, ny, nz, number of right-hand sides, CPML width), so plans of the
-same class reuse the choice.  Every split gives bitwise the same fields, so
+extent, ny, nz, number of right-hand sides, CPML width, time blocking), so
+plans of the same class reuse the choice.  For a plan with time blocking it
+also times two steps per launch (the two-step region's launch, the interior
+around it and the shell, each with its own best choice) and keeps that when
+it is faster per step.  Every split gives bitwise the same fields, so
 tuning only changes speed.
 """
 from __future__ import annotations
@@ -34,6 +37,14 @@ ROWS = 4
 SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b) for z in (8, 10, 16, 32) for a in (0, 1, 128)
                                             for b in (0, 2))
 INTERIOR_FLAGS = (0, 16, 32, 16 | 32)          # cooperative, no prefetch
+# settings swept for two steps per launch (plans with time blocking): z-planes
+# per tile and flags from {1, 128: x-shell cuts as above; 2: 8 waves per
+# block; 256: tiles that meet only the x-slabs run with the single-step
+# interior around the two-step region, with the x-axis CPML code}.  The
+# two-step launch itself barely depends on the z-chunk (its wavefront
+# recomputes two planes below each tile); the shell does.
+PAIR_SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b | c) for z in (8, 10, 16) for a in (0, 1, 128)
+                                                 for b in (0, 2) for c in (0, 256))
 SHELL_FLAGS = tuple(a | b | c for a in (0, 4) for b in (0, 8) for c in (0, 64))
 _lock = threading.Lock()
 
@@ -45,6 +56,7 @@ def cache_path() -> str:
 
 def shape_key(plan, which: int) -> str:
     g = plan.grid
+    tb = getattr(plan, "time_blocking", 1)
     nxp = (g["nx"] + 31) // 32 * 32
     nf, nr = plan.n_stepped_fwd, plan.n_stepped
     r = nf if which == 1 else (nr - nf if which == 2 else nr)
@@ -53,7 +65,7 @@ def shape_key(plan, which: int) -> str:
         arch = torch.cuda.get_device_properties(plan.device).gcnArchName.split(":")[0]
     except Exception:
         pass
-    return f"{arch}|nx{nxp}|ny{g['ny']}|nz{g['nz']}|R{r}|pml{max(g['npml'])}"
+    return f"{arch}|nx{nxp}|ny{g['ny']}|nz{g['nz']}|R{r}|pml{max(g['npml'])}" + ("|tb2" if tb == 2 else "")
 
 
 def _load() -> dict:
@@ -85,7 +97,7 @@ def _time(plan, zc, flags, part, which, n_launch, stream) -> float:
 
 
 def tune(plan, which: int = YO_BOTH, shared: Optional[Iterable] = None, n_launch: int = 5,
-         use_cache: bool = True, stream=None) -> dict:
+         use_cache: bool = True, stream=None, pair_shared: Optional[Iterable] = None) -> dict:
     """Pick and apply the fastest split for `plan`; returns the record.
 
     Leaves the plan reset (fields zero) for `which`."""
@@ -115,6 +127,30 @@ def tune(plan, which: int = YO_BOTH, shared: Optional[Iterable] = None, n_launch
         if best is None or total < best[0]:
             best = (total, zc, flags)
     total, zc, flags = best
+    if getattr(plan, "time_blocking", 1) == 2 and plan.n_steps >= 2:
+        # two steps per launch over the two-step region: per step, half the
+        # two-step launch, the interior around it and the shell (one launch
+        # each per step), each with its own best choice; kept when it beats
+        # the best single-step split
+        for zc2, base in (pair_shared or PAIR_SHARED):
+            if zc2 > nz and zc2 != 8:
+                continue
+            fl0 = base | 512
+            t2 = _time(plan, zc2, fl0, 2, which, n_launch, stream)
+            if t2 <= 0.0:
+                break               # no two-step region on this grid
+            tf = {f: _time(plan, zc2, fl0 | f, 3, which, n_launch, stream) for f in (0, 32)}
+            ts = {f: _time(plan, zc2, fl0 | f, 1, which, n_launch, stream) for f in SHELL_FLAGS}
+            ff = min(tf, key=tf.get)
+            fs = min(ts, key=ts.get)
+            per_step = 0.5 * t2 + tf[ff] + ts[fs]
+            fl = fl0 | ff | fs
+            timings[f"pairs_z{zc2}f{base}"] = dict(two_step=round(t2, 4),
+                                                   frame={str(k): round(v, 4) for k, v in tf.items()},
+                                                   shell={str(k): round(v, 4) for k, v in ts.items()},
+                                                   best=fl, ms=round(per_step, 4))
+            if per_step < total:
+                total, zc, flags = per_step, zc2, fl
     plan.set_tiling(ROWS, zc, flags)
     plan.reset(which, stream)
     rec = dict(rows=ROWS, zchunk=zc, flags=flags, ms_per_step=total, timings=timings)

@@ -29,7 +29,10 @@ struct YoPlaneD {
 // One right-hand side: its own field state, absorbing-layer memories, DFT
 // sums, source plane and per-step phase table.
 struct YoRhsD {
-    float *F[2];             // double-buffered state, ghost layout, nc = 6 (E then Ht)
+    // state buffers, ghost layout, nc = 6 (E then Ht): the state after step
+    // s is in F[s % nbuf]; nbuf = 3 (a third buffer) when the plan may
+    // advance its interior two steps per sweep, else 2 (F[2] null)
+    float *F[3];
     // CPML memories: per axis a, at float offset psi_off[a] of the plan, six
     // arrays of psi_n[a] floats: E (2 components), Ht step parity 0 (2),
     // Ht parity 1 (2); each [2 comps] of the axis' slab layout
@@ -64,6 +67,8 @@ struct YoPlanD {
     int n_ports;
     int n_steps;
     int dft_stride;          // the DFT adds E^n of the steps n divisible by it (1: every step)
+    int nbuf;                // state buffers per right-hand side (2 or 3)
+    int r2[6];               // two-step region [x0, x1) x [y0, y1) x [z0, z1) (empty: x1 <= x0)
     YoPlaneD ports[YO_MAX_PORTS];
     int mon_off[YO_MAX_PORTS];
     int mon_total;
@@ -160,6 +165,8 @@ struct YoChainBufs {
 // rows); prefetch: operands of the next plane loaded during this one
 hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &args, int blocks,
                           hipStream_t s);
+// two steps per sweep over the tiles of the two-step region (independent waves)
+hipError_t yo_launch_step2(const YoStepArgs &args, int blocks, hipStream_t s);
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);

@@ -92,7 +92,8 @@ enum {
     YO_TILE_NOPF_SHELL = 64,  // CPML shell: no prefetch of the next plane
     YO_TILE_XFULL = 128,      // x-shell strips as narrow as whole 62-cell interior strips allow
     YO_TILE_XINT = 256,       // tiles inside the x-slabs only run in the interior launch (x CPML code)
-    YO_TILE_ALL = 511
+    YO_TILE_PAIRS = 512,      // the two-step region advances two steps per sweep (yo_set_time_blocking)
+    YO_TILE_ALL = 1023
 };
 
 struct yo_plan {
@@ -146,6 +147,13 @@ struct yo_plan {
     std::vector<char> src_set, port_set;
     int kc = 16, tflags = 0;     // z-planes per tile; tiling flags (YO_TILE_* below)
     int n_int = 0, n_tiles = 0;  // tile table: interior tiles [0, n_int), CPML shell [n_int, n_tiles)
+    // temporal blocking (yo_set_time_blocking): steps per sweep the interior
+    // may take, state buffers per right-hand side, the two-step region and
+    // its tiles (after the shell: [n_tiles, n_tiles + n2)) and the single-step
+    // tiles of the interior around it ([n_tiles + n2, n_tiles + n2 + nfr))
+    int tsteps = 1, nbuf = 2;
+    int r2[6] = {0, 0, 0, 0, 0, 0};
+    int n2 = 0, nfr = 0;
     bool bg_set = false, design_set = false;
     double beta = 0;
     int steps_done = 0;
@@ -165,12 +173,12 @@ struct yo_plan {
     unsigned static_epoch = 0;
     hipStream_t cap_stream = nullptr;
     // launch timing: the last tm_n steps of each advance run eagerly, with
-    // HIP events around the launches of part tm_part (0, 1, or 2 for both);
-    // tm_ev[q] holds the event pairs of part q recorded since yo_set_timing
-    // (tm_done[q] of them), created as they are needed
+    // HIP events around the launches of part tm_part (0 or 1, or 2 for
+    // every part); tm_ev[q] holds the event pairs of part q (see part_range)
+    // recorded since yo_set_timing (tm_done[q] of them), created as needed
     int tm_part = 0, tm_n = 0;
-    int tm_done[2] = {0, 0};
-    std::vector<hipEvent_t> tm_ev[2];
+    int tm_done[4] = {0, 0, 0, 0};
+    std::vector<hipEvent_t> tm_ev[4];
 };
 
 namespace {
@@ -437,6 +445,98 @@ void split_axis(int n, int lo, int hi, int w, std::vector<std::pair<int, int>> &
     }
 }
 
+// Two-step region R2 inside the interior region [lo, hi) and its tiles.
+// Along each axis R2 keeps two cells clear of the absorbing slabs (the
+// two-step kernel recomputes step n+1's Ht two cells below and its E one
+// cell on either side of its cells, all without CPML code) and clear of every
+// source and port plane (whose currents enter E between the steps): the
+// component planes a source writes, and one more on either side, stay
+// outside the cells where the kernel computes step n+1's E.  Then the
+// two-step tiles cover R2 (strips of at most 60 cells, YO_TY rows, kc
+// planes), and single-step tiles cover the rest of the interior (the
+// "frame"), cut at R2's faces.
+void build_pair_tiles(yo_plan *p, const int lo[3], const int hi[3])
+{
+    const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    int r[6];
+    for (int a = 0; a < 3; ++a) {
+        r[2 * a] = std::max(lo[a], p->plo[a] + 2);
+        r[2 * a + 1] = std::min(hi[a], n[a] - p->phi[a] - 1);
+    }
+    auto cut = [&](const yo_plane &pl, int ncomp) {
+        // step n+1's E is computed on [r0 - 1, r1] along the plane's normal;
+        // the plane's currents touch indices i .. i + (ncomp == 5)
+        const int a = pl.axis, i = pl.index, i_end = pl.index + (ncomp == 5 ? 1 : 0);
+        int &r0 = r[2 * a], &r1 = r[2 * a + 1];
+        if (r1 <= r0 || i_end < r0 - 1 || i > r1) return;
+        const int below = (i - 1) - r0, above = r1 - (i_end + 2);
+        if (below >= above) r1 = i - 1;
+        else r0 = i_end + 2;
+    };
+    for (const yo_plane &pl : p->src_planes) cut(pl, 2);
+    for (const yo_plane &pl : p->port_planes) cut(pl, p->mon_nc);
+    for (int a = 0; a < 3; ++a)
+        if (r[2 * a + 1] - r[2 * a] < 4) return;   // too thin: no two-step region
+    for (int i = 0; i < 6; ++i) p->r2[i] = r[i];
+    // two-step tiles
+    std::vector<std::pair<int, int>> ax, ay, az;
+    std::vector<char> ix, iy, iz;
+    split_axis(n[0], r[0], r[1], 60, ax, ix);
+    split_axis(n[1], r[2], r[3], YO_TY, ay, iy);
+    split_axis(n[2], r[4], r[5], p->kc, az, iz);
+    for (size_t k = 0; k < az.size(); ++k)
+        for (size_t j = 0; j < ay.size(); ++j)
+            for (size_t i = 0; i < ax.size(); ++i) {
+                if (!(ix[i] && iy[j] && iz[k])) continue;
+                int4 t;
+                t.x = ax[i].first | (ax[i].second << 16);
+                t.y = ay[j].first | (ay[j].second << 16);
+                t.z = az[k].first | ((az[k].first + az[k].second) << 16);
+                t.w = 0;
+                p->tiles_host.push_back(t);
+            }
+    p->n2 = (int)p->tiles_host.size() - p->n_tiles;
+    // frame: the interior minus R2, single-step tiles cut at R2's faces
+    auto pieces = [&](int a, int w, std::vector<std::pair<int, int>> &out, std::vector<char> &in_r2) {
+        out.clear();
+        in_r2.clear();
+        const int cuts[4] = {lo[a], r[2 * a], r[2 * a + 1], hi[a]};
+        for (int seg = 0; seg < 3; ++seg) {
+            const int len = cuts[seg + 1] - cuts[seg];
+            if (len <= 0) continue;
+            const int np = (len + w - 1) / w;
+            int st = cuts[seg];
+            for (int q = 0; q < np; ++q) {
+                const int sz = len / np + (q < len % np ? 1 : 0);
+                out.emplace_back(st, sz);
+                in_r2.push_back(seg == 1);
+                st += sz;
+            }
+        }
+    };
+    pieces(0, YO_TX, ax, ix);
+    pieces(1, YO_TY, ay, iy);
+    pieces(2, p->kc, az, iz);
+    for (size_t k = 0; k < az.size(); ++k)
+        for (size_t j = 0; j < ay.size(); ++j)
+            for (size_t i = 0; i < ax.size(); ++i) {
+                if (ix[i] && iy[j] && iz[k]) continue;
+                int4 t;
+                t.x = ax[i].first | (ax[i].second << 16);
+                t.y = ay[j].first | (ay[j].second << 16);
+                t.z = az[k].first | ((az[k].first + az[k].second) << 16);
+                t.w = 0;
+                p->tiles_host.push_back(t);
+            }
+    // with YO_TILE_XINT the interior list also holds the tiles that meet
+    // only the x-slabs (class 1); they join the frame, which then runs the
+    // x-axis CPML code
+    if (p->tflags & YO_TILE_XINT)
+        for (int t = 0; t < p->n_int; ++t)
+            if (p->tiles_host[t].w == 1) p->tiles_host.push_back(p->tiles_host[t]);
+    p->nfr = (int)p->tiles_host.size() - p->n_tiles - p->n2;
+}
+
 // Tile table: the interior tiles, then the CPML shell, each in space order
 // (z, y, x fastest).  Along each axis the region clear of the absorbing
 // slabs is [lo + 1, n - hi) for a CPML of lo/hi cells (no owned site and no
@@ -499,6 +599,9 @@ void build_tiles(yo_plan *p)
     p->n_int = (int)p->tiles_host.size();
     emit(true, (p->tflags & YO_TILE_COOP_SHELL) ? YO_TY * wpb : YO_TY, p->tiles_host);
     p->n_tiles = (int)p->tiles_host.size();
+    p->n2 = p->nfr = 0;
+    for (int i = 0; i < 6; ++i) p->r2[i] = 0;
+    if (p->tsteps == 2 && (p->tflags & YO_TILE_PAIRS)) build_pair_tiles(p, lo, hi);
 }
 
 size_t tiles_capacity(const yo_grid &g, int ty_min, int kc_min)
@@ -551,7 +654,7 @@ void set_out_range(const yo_plan *p, int which, int &r0, int &r1)
     r1 = (which & YO_ADJOINT) ? p->n_rhs : p->n_fwd;
 }
 
-size_t fields_per_rhs(const yo_plan *p) { return 12 * p->cells_p; }   // 2 buffers x (E, H) x 3
+size_t fields_per_rhs(const yo_plan *p) { return 6 * (size_t)p->nbuf * p->cells_p; }   // buffers x (E, H) x 3
 
 // DFT results of output right-hand side r (numbering of yo_rhs_count)
 float2 *box_of(const yo_plan *p, int r)
@@ -744,7 +847,7 @@ void yo_plan_destroy(yo_plan *p)
         }
     }
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < 4; ++q)
         for (hipEvent_t e : p->tm_ev[q]) (void)hipEventDestroy(e);
     delete p;
 }
@@ -793,6 +896,8 @@ static yo_status rebuild_descriptors(yo_plan *p)
     P.mon_nc = p->mon_nc;
     P.n_steps = p->n_steps;
     P.dft_stride = p->pulse ? p->dft_stride : 1;
+    P.nbuf = p->nbuf;
+    for (int i = 0; i < 6; ++i) P.r2[i] = p->r2[i];
     P.mon_total = (int)p->mon_total;
     for (int q = 0; q < p->n_ports; ++q) {
         const yo_plane &pl = p->port_planes[q];
@@ -816,6 +921,7 @@ static yo_status rebuild_descriptors(yo_plan *p)
         float *f = fields + fields_per_rhs(p) * r;
         R.F[0] = f;
         R.F[1] = f + 6 * p->cells_p;
+        R.F[2] = p->nbuf == 3 ? f + 12 * p->cells_p : nullptr;
         R.psi = psi + p->psi_per_rhs * r;
         // under a pulse, stepped right-hand side r stands for the output
         // right-hand sides of its source or port at every frequency; its
@@ -1089,6 +1195,21 @@ yo_status yo_set_dft_stride(yo_plan *p, int stride)
     return YO_OK;
 }
 
+yo_status yo_set_time_blocking(yo_plan *p, int steps)
+{
+    if (!p) return fail(YO_EINVAL, "null argument");
+    if (p->ws) return fail(YO_ESTATE, "set the time blocking before binding a workspace");
+    if (steps != 1 && steps != 2) return fail(YO_EINVAL, "steps per sweep must be 1 or 2");
+    p->tsteps = steps;
+    p->nbuf = steps == 2 ? 3 : 2;
+    if (steps == 1) p->tflags &= ~YO_TILE_PAIRS;
+    // the two-step and frame tiles can add up to twice the single-step count
+    p->tiles_cap = tiles_capacity(p->grid, 4, 4) * (steps == 2 ? 3 : 1);
+    build_tiles(p);
+    build_layout(p);
+    return YO_OK;
+}
+
 yo_status yo_bind_workspace(yo_plan *p, void *dev, size_t bytes, yo_stream stream)
 {
     if (!p || !dev) return fail(YO_EINVAL, "null argument");
@@ -1137,6 +1258,10 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
     // a tile's planes and the halo plane below are at most one per lane
     if (zchunk < 4 || zchunk > 63) return fail(YO_EINVAL, "zchunk must be in [4, 63]");
     if (flags & ~YO_TILE_ALL) return fail(YO_EINVAL, "unknown tiling flags");
+    if ((flags & YO_TILE_PAIRS) && p->tsteps != 2)
+        return fail(YO_EINVAL, "flag 512 needs yo_set_time_blocking(plan, 2) before binding");
+    if ((flags & YO_TILE_PAIRS) && (flags & YO_TILE_COOP_INT))
+        return fail(YO_EINVAL, "flag 512 does not combine with flag 16");
     p->kc = zchunk;
     p->tflags = flags;
     build_tiles(p);
@@ -1146,6 +1271,10 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipMemcpy(p->ws + p->L.tiles.off, p->tiles_host.data(), p->tiles_host.size() * sizeof(int4),
                          hipMemcpyHostToDevice));
+        // the plan descriptor carries the two-step region, which the split sets
+        rebuild_descriptors(p);
+        if (yo_status st = upload_desc(p, nullptr)) return st;
+        HIPCHK(hipDeviceSynchronize());
     }
     return YO_OK;
 }
@@ -1359,21 +1488,35 @@ static void aux_args(yo_plan *const *plans, const int *which, int cnt, bool dft,
 
 // Fill the step-kernel arguments of tile class `cls` for a plan list;
 // returns the number of blocks (0: no plan has tiles of that class).
-// Step-kernel arguments of one part (0 interior, 1 CPML shell) for a plan
-// list; returns the number of blocks (0: no plan has tiles there).
+// tiles of launch part `part`: 0 interior, 1 CPML shell, 2 two-step region,
+// 3 the interior around it (single steps)
+static void part_range(const yo_plan *p, int part, int &t0, int &t1)
+{
+    switch (part) {
+    case 0: t0 = 0; t1 = p->n_int; break;
+    case 1: t0 = p->n_int; t1 = p->n_tiles; break;
+    case 2: t0 = p->n_tiles; t1 = p->n_tiles + p->n2; break;
+    default: t0 = p->n_tiles + p->n2; t1 = t0 + p->nfr; break;
+    }
+}
+
+// Step-kernel arguments of one part (see part_range) for a plan list;
+// returns the number of blocks (0: no plan has tiles there).
 static int step_args(yo_plan *const *plans, const int *which, int cnt, int part, YoStepArgs &a)
 {
     memset(&a, 0, sizeof(YoStepArgs));
     a.n_slots = cnt;
     const int wpb = (plans[0]->tflags & YO_TILE_WPB8) ? 8 : 4;
-    const bool coop = (plans[0]->tflags & (part ? YO_TILE_COOP_SHELL : YO_TILE_COOP_INT)) != 0;
+    const bool coop = part < 2 &&
+                      (plans[0]->tflags & (part ? YO_TILE_COOP_SHELL : YO_TILE_COOP_INT)) != 0;
     int tot = 0;
     for (int i = 0; i < cnt; ++i) {
         yo_plan *p = plans[i];
         int r0, r1;
         set_rhs_range(p, which[i], r0, r1);
         YoSlot &sl = a.slot[i];
-        const int t0 = part ? p->n_int : 0, t1 = part ? p->n_tiles : p->n_int;
+        int t0, t1;
+        part_range(p, part, t0, t1);
         sl.plan = wsp<YoPlanD>(p, p->L.desc_plan);
         sl.tiles = wsp<int4>(p, p->L.tiles) + t0;
         sl.rhs0 = r0;
@@ -1395,6 +1538,9 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int part,
 static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, int blocks, hipStream_t s)
 {
     const int f = p0->tflags;
+    if (part == 2) return yo_launch_step2(a, blocks, s);
+    if (part == 3)
+        return yo_launch_step((f & YO_TILE_XINT) ? 1 : 0, false, !(f & YO_TILE_NOPF_INT), a, blocks, s);
     if (part == 0)
         return yo_launch_step((f & YO_TILE_XINT) ? 1 : 0, (f & YO_TILE_COOP_INT) != 0,
                               !(f & YO_TILE_NOPF_INT), a, blocks, s);
@@ -1407,47 +1553,67 @@ static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, 
 // the step launches (interior, CPML shell), the source.  Plans must share
 // every tiling flag but the x-split ones.
 // DFT launches: at the steps k of the call with k % dft_every == 0 (the
-// kernel itself skips steps its plan does not sample).
+// kernel itself skips steps its plan does not sample).  pairs: the steps go
+// two at a time where two remain (the two-step region in one launch for
+// both, the interior around it and the CPML shell one step at a time, the
+// source after each step); the caller guarantees no DFT at the second step
+// of a pair.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
                               bool with_dft, hipStream_t s, yo_plan *timed = nullptr,
-                              int dft_every = 1)
+                              int dft_every = 1, bool pairs = false)
 {
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
-        static thread_local YoStepArgs A[2];
-        int blocks[2];
-        for (int part = 0; part < 2; ++part)
+        static thread_local YoStepArgs A[4];
+        int blocks[4] = {0, 0, 0, 0};
+        for (int part = 0; part < (pairs ? 4 : 2); ++part)
             blocks[part] = step_args(plans + base, which + base, cnt, part, A[part]);
         YoAuxArgs ad, as;
         aux_args(plans + base, which + base, cnt, true, ad);
         aux_args(plans + base, which + base, cnt, false, as);
-        for (int k = 0; k < n_launch; ++k) {
+        auto launch = [&](int part, int k) -> yo_status {
+            A[part].k_offset = k;
+            const bool tm = timed && base == 0 && blocks[part] &&
+                            (timed->tm_part == part || timed->tm_part == 2);
+            if (tm) {
+                std::vector<hipEvent_t> &ev = timed->tm_ev[part];
+                const size_t need = 2 * (size_t)timed->tm_done[part] + 2;
+                while (ev.size() < need) {
+                    hipEvent_t e;
+                    HIPCHK(hipEventCreate(&e));
+                    ev.push_back(e);
+                }
+                HIPCHK(hipEventRecord(ev[need - 2], s));
+                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
+                HIPCHK(hipEventRecord(ev[need - 1], s));
+                timed->tm_done[part]++;
+            } else {
+                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
+            }
+            return YO_OK;
+        };
+        yo_status st;
+        for (int k = 0; k < n_launch;) {
             if (with_dft && k % dft_every == 0) {
                 ad.k_offset = k;
                 HIPCHK(yo_launch_dft(ad, s));
             }
-            for (int part = 0; part < 2; ++part) {
-                A[part].k_offset = k;
-                const bool tm = timed && base == 0 && blocks[part] &&
-                                (timed->tm_part == part || timed->tm_part == 2);
-                if (tm) {
-                    std::vector<hipEvent_t> &ev = timed->tm_ev[part];
-                    const size_t need = 2 * (size_t)timed->tm_done[part] + 2;
-                    while (ev.size() < need) {
-                        hipEvent_t e;
-                        HIPCHK(hipEventCreate(&e));
-                        ev.push_back(e);
-                    }
-                    HIPCHK(hipEventRecord(ev[need - 2], s));
-                    HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
-                    HIPCHK(hipEventRecord(ev[need - 1], s));
-                    timed->tm_done[part]++;
-                } else {
-                    HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
+            if (pairs && k + 1 < n_launch) {
+                if ((st = launch(2, k))) return st;
+                for (int q = 0; q < 2; ++q) {
+                    if ((st = launch(3, k + q))) return st;
+                    if ((st = launch(1, k + q))) return st;
+                    as.k_offset = k + q;
+                    HIPCHK(yo_launch_source(as, s));
                 }
+                k += 2;
+            } else {
+                for (int part = 0; part < 2; ++part)
+                    if ((st = launch(part, k))) return st;
+                as.k_offset = k;
+                HIPCHK(yo_launch_source(as, s));
+                k += 1;
             }
-            as.k_offset = k;
-            HIPCHK(yo_launch_source(as, s));
         }
         YoCtrArgs ca{};
         ca.n = cnt;
@@ -1456,6 +1622,25 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
         HIPCHK(yo_launch_ctr(ca, 0, s));
     }
     return YO_OK;
+}
+
+// Steps of a call may go two at a time when every plan has the two-step
+// layout and the count left in its run, and no DFT falls on a pair's second
+// step (no DFT in the call, or pulse DFTs on even steps only).
+static bool pairs_ok(yo_plan *const *plans, int n, int n_launch, bool with_dft, int every)
+{
+    for (int i = 0; i < n; ++i) {
+        const yo_plan *p = plans[i];
+        // (a plan whose two-step region came out empty has no frame tiles either)
+        if (!(p->tflags & YO_TILE_PAIRS) || p->tsteps != 2 || p->n2 == 0) return false;
+        if (p->steps_done + n_launch > p->n_steps) return false;
+    }
+    if (with_dft) {
+        if (every % 2) return false;
+        for (int i = 0; i < n; ++i)
+            if (!plans[i]->pulse) return false;
+    }
+    return true;
 }
 
 // The DFT stride every plan of the list samples, when they share one and all
@@ -1528,10 +1713,12 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         int every = dft_every(plans, n);
         if (chunk % every) every = 1;
         key += "e" + std::to_string(every);
-        GraphEntry ge[2];
+        GraphEntry ge[4];
         while (n_steps - tail - done >= chunk) {
-            const int variant = chunk_needs_dft(plans, which, n, chunk) ? 1 : 0;
-            const std::string kv = key + (variant ? "|dft" : "|nodft");
+            const bool need_dft = chunk_needs_dft(plans, which, n, chunk);
+            const bool pairs = pairs_ok(plans, n, chunk, need_dft, every) && chunk % 2 == 0;
+            const int variant = (need_dft ? 1 : 0) | (pairs ? 2 : 0);
+            const std::string kv = key + (need_dft ? "|dft" : "|nodft") + (pairs ? "|pairs" : "");
             if (!ge[variant].exec) {
                 std::lock_guard<std::mutex> lk(g_graph_mu);
                 auto it = g_graphs.find(kv);
@@ -1541,8 +1728,8 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
                 yo_plan *p0 = plans[0];
                 if (!p0->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p0->cap_stream, hipStreamNonBlocking));
                 HIPCHK(hipStreamBeginCapture(p0->cap_stream, hipStreamCaptureModeThreadLocal));
-                yo_status st = launch_steps(plans, which, n, chunk, variant == 1, p0->cap_stream, nullptr,
-                                            every);
+                yo_status st = launch_steps(plans, which, n, chunk, need_dft, p0->cap_stream, nullptr,
+                                            every, pairs);
                 hipGraph_t graph = nullptr;
                 hipError_t e = hipStreamEndCapture(p0->cap_stream, &graph);
                 if (st) {
@@ -1566,8 +1753,10 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
         const bool in_tail = done >= n_steps - tail;
         const int lim = in_tail ? n_steps - done : n_steps - tail - done;
         const int k = std::min(chunk, lim);
-        yo_status st = launch_steps(plans, which, n, k, chunk_needs_dft(plans, which, n, k), s,
-                                    in_tail ? timed : nullptr, dft_every(plans, n));
+        const bool need_dft = chunk_needs_dft(plans, which, n, k);
+        const int every = dft_every(plans, n);
+        yo_status st = launch_steps(plans, which, n, k, need_dft, s, in_tail ? timed : nullptr, every,
+                                    pairs_ok(plans, n, k, need_dft, every));
         if (st) return st;
         done += k;
         bump(k);
@@ -1750,14 +1939,17 @@ yo_status yo_set_timing(yo_plan *p, int part, int n_last)
     if (part < 0 || part > 2 || n_last < 0 || n_last > 4096) return fail(YO_EINVAL, "bad part or count");
     p->tm_part = part;
     p->tm_n = n_last;
-    p->tm_done[0] = p->tm_done[1] = 0;
+    // starting clears what was recorded; stopping (n_last = 0) keeps it for
+    // yo_get_timing
+    if (n_last > 0)
+        for (int q = 0; q < 4; ++q) p->tm_done[q] = 0;
     return YO_OK;
 }
 
 yo_status yo_get_timing(yo_plan *p, int part, float *avg_ms, int *count)
 {
     if (!p || !avg_ms || !count) return fail(YO_EINVAL, "null argument");
-    if (part < 0 || part > 1) return fail(YO_EINVAL, "part must be 0 or 1");
+    if (part < 0 || part > 3) return fail(YO_EINVAL, "part must be 0, 1, 2 or 3");
     *avg_ms = 0.0f;
     const int n = p->tm_done[part];
     *count = n;
@@ -1779,8 +1971,10 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
 {
     if (!p || !avg_ms || !bytes || !cells) return fail(YO_EINVAL, "null argument");
     if (yo_status st_ = ws_check(p)) return st_;
-    if (cls < 0 || cls > 1 || n_launch < 1) return fail(YO_EINVAL, "bad part or count");
+    if (cls < 0 || cls > 3 || n_launch < 1) return fail(YO_EINVAL, "bad part or count");
     if (!p->active) return fail(YO_ESTATE, "yo_reset first");
+    if (cls == 2 && p->steps_done + 2 > p->n_steps)
+        return fail(YO_ESTATE, "the two-step launch needs two steps left in the run");
     hipStream_t s = (hipStream_t)stream;
     int r0, r1;
     set_rhs_range(p, p->active, r0, r1);
@@ -1789,7 +1983,9 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     // owned cells of the part and (cell, axis) pairs inside an absorbing slab
     const yo_grid &g = p->grid;
     double own = 0.0, in_pml = 0.0;
-    for (int t = cls ? p->n_int : 0; t < (cls ? p->n_tiles : p->n_int); ++t) {
+    int ta, tb;
+    part_range(p, cls, ta, tb);
+    for (int t = ta; t < tb; ++t) {
         const int4 tt = p->tiles_host[t];
         const int x0 = tt.x & 0xffff, x1 = x0 + (tt.x >> 16);
         const int y0 = tt.y & 0xffff, y1 = y0 + (tt.y >> 16);
@@ -1806,8 +2002,11 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
         }
     }
     const double R = r1 - r0;
-    *bytes = own * (48.0 * R + 12.0) + 32.0 * R * in_pml;
-    *cells = own * R;
+    // the two-step launch advances its cells two steps: twice the bytes
+    // two one-step sweeps must move
+    const double steps = cls == 2 ? 2.0 : 1.0;
+    *bytes = steps * (own * (48.0 * R + 12.0) + 32.0 * R * in_pml);
+    *cells = steps * own * R;
     if (!blocks || r1 <= r0) {
         *avg_ms = 0.0f;
         *bytes = *cells = 0.0;
@@ -1855,7 +2054,7 @@ yo_status yo_set_fields(yo_plan *p, int rhs, const float *E, const float *H, yo_
     if (yo_status st_ = ws_check(p)) return st_;
     const yo_grid &g = p->grid;
     const YoRhsD &R = p->hrhs[rhs];
-    const int par = p->steps_done & 1;
+    const int par = p->steps_done % p->nbuf;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(yo_launch_to_ghost(E, R.F[par], 3, 0, 6, g.nz, g.ny, g.nx, p->nxp, s));
     HIPCHK(yo_launch_to_ghost(H, R.F[par], 3, 3, 6, g.nz, g.ny, g.nx, p->nxp, s));
@@ -1869,7 +2068,7 @@ yo_status yo_get_fields(const yo_plan *p, int rhs, float *E, float *H, yo_stream
     if (yo_status st_ = ws_check(p)) return st_;
     const yo_grid &g = p->grid;
     const YoRhsD &R = p->hrhs[rhs];
-    const int par = p->steps_done & 1;
+    const int par = p->steps_done % p->nbuf;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(yo_launch_from_ghost(R.F[par], E, 3, 0, 6, g.nz, g.ny, g.nx, p->nxp, s));
     HIPCHK(yo_launch_from_ghost(R.F[par], H, 3, 3, 6, g.nz, g.ny, g.nx, p->nxp, s));

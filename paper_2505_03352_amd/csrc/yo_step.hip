@@ -21,7 +21,9 @@
 //   * a wave marches z-planes k0..k1-1, carrying E of the next plane and the
 //     Ht of the previous plane in registers; it starts one plane early to
 //     recompute Ht(k0-1).
-// E, Ht and the Ht CPML memories are double-buffered by step parity, so a
+// A step reads the state buffer of step n and writes that of step n+1 (two
+// buffers, or three in rotation when the plan's interior may take two steps
+// per sweep); the Ht CPML memories are double-buffered by step parity, so a
 // halo recompute reads old values no other wave overwrites in this launch,
 // and every recomputed halo value is bitwise equal to the one its owner
 // stores (same expression, same inputs, no contraction).  Field arrays carry
@@ -319,8 +321,8 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     const int rowb = nxp * (int)sizeof(float);                // one component row, bytes
     const int par = step & 1;
     // state: 6 component rows per group (E then Ht); kappa: 3
-    const Rsrc Fo = rsrc_of(R.F[par], 6 * groups * nxp);
-    const Rsrc Fn = rsrc_of(R.F[par ^ 1], 6 * groups * nxp);
+    const Rsrc Fo = rsrc_of(R.F[step % P.nbuf], 6 * groups * nxp);
+    const Rsrc Fn = rsrc_of(R.F[(step + 1) % P.nbuf], 6 * groups * nxp);
     const Rsrc K = rsrc_of(P.kappa, 3 * groups * nxp);
     const int eb = 0, hb = 3 * rowb;                          // E and Ht within a state group
     const float sx = P.sx, sy = P.sy, sz = P.sz;
@@ -665,6 +667,243 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two steps per sweep (temporal blocking) for the tiles of the two-step region
+// R2 (YoPlanD::r2), which lies two cells clear of every absorbing slab and of
+// every source plane, so neither step needs CPML code or a source term there.
+// A wave owns x in [x0, x0+xn) (xn <= 60; lane l holds x = x0 - 2 + l), rows
+// j0..j0+jn-1 (jn <= TY) and planes k0..k1-1, reads the state after step n
+// (buffer n % 3) and writes the state after step n+2 (buffer (n+2) % 3),
+// recomputing from step n's values everything the second step needs around
+// its cells: step n+1 on lanes 1..62, rows j0-1..j0+TY and planes k0-1..k1,
+// step n+1's Ht on one more lane, row and plane below.  Marching up z, it
+// takes step n+1 at plane k and step n+2 at plane k-1 in the same pass (a
+// wavefront in z-t), so each plane's state is read once for both steps.
+// The cells of R2's outermost layer also get their step-n+1 state written
+// (buffer (n+1) % 3): the single steps of the tiles around R2 read it.
+// Every value is computed with the expression and the operand order of the
+// single-step kernel, so the two paths give bitwise the same fields.
+template <int TY>
+__device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, const int step,
+                                           const int4 t, const int lane)
+{
+    const int nx = P.nx, ny = P.ny, nxp = P.nxp;
+    const int rows = ny + 2;
+    const size_t groups = (size_t)(P.nz + 2) * rows;
+    const int rowb = nxp * (int)sizeof(float);
+    const int nb = P.nbuf;
+    const Rsrc FA = rsrc_of(R.F[step % nb], 6 * groups * nxp);          // after step n
+    const Rsrc FB = rsrc_of(R.F[(step + 1) % nb], 6 * groups * nxp);    // after n+1 (rim)
+    const Rsrc FC = rsrc_of(R.F[(step + 2) % nb], 6 * groups * nxp);    // after n+2
+    const Rsrc K = rsrc_of(P.kappa, 3 * groups * nxp);
+    const int eb = 0, hb = 3 * rowb;
+    const float sx = P.sx, sy = P.sy, sz = P.sz;
+
+    const int x0 = t.x & 0xffff, xn = t.x >> 16;
+    const int j0 = t.y & 0xffff, jn = t.y >> 16;
+    const int k0 = t.z & 0xffff, k1 = t.z >> 16;
+    const int x = x0 - 2 + lane;
+    const int xo = (clampi(x, -1, nx) + 1) * (int)sizeof(float);
+    const bool own_x = (lane >= 2) && (lane < 2 + xn);
+    // R2's outermost layer, whose step-n+1 state the tiles around R2 read
+    const int ra0 = P.r2[0], ra1 = P.r2[1], rb0 = P.r2[2], rb1 = P.r2[3], rc0 = P.r2[4], rc1 = P.r2[5];
+    const bool rim_x = own_x && (x == ra0 || x == ra1 - 1);
+    auto ro = [&](int j, int k) -> int {
+        return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 6 * rowb;
+    };
+    auto rk = [&](int j, int k) -> int {
+        return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 3 * rowb;
+    };
+    // row index r: j = j0 - 2 + r
+    constexpr int NE = TY + 4;     // E^n rows 0..TY+3 (the last: Ex and Ez only)
+    constexpr int NH = TY + 3;     // Ht^{n-1/2} and Ht^{n+1/2} rows 0..TY+2
+    float Ec[3][NE], Enx[3][NE];   // E^n at planes k and k+1
+    float Ho[3][NH];               // Ht^{n-1/2} at plane k
+    float Hh[3][NH], Hhp[3][NH];   // Ht^{n+1/2} at planes k and k-1
+    float Kc[3][NH], Kp[3][NH];    // kappa at planes k and k-1 (rows 1..TY+2)
+    float E1c[3][NH], E1p[3][NH];  // E^{n+1} at planes k and k-1 (rows 1..TY+2)
+    float H2[3][NH], H2p[2][NH];   // Ht^{n+3/2} at planes k-1 and k-2 (rows 1..TY+1)
+
+    auto load_e = [&](int k, float (&e)[3][NE]) {
+#pragma unroll
+        for (int r = 0; r < NE; ++r) {
+            const int o = ro(j0 - 2 + r, k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (r == NE - 1 && c == 1) { e[c][r] = 0.0f; continue; }
+                e[c][r] = bload(FA, xo, eb + c * rowb + o);
+            }
+        }
+    };
+    load_e(k0 - 2, Ec);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < NH; ++r) Hhp[c][r] = E1p[c][r] = Kp[c][r] = H2[c][r] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < NH; ++r) H2p[0][r] = H2p[1][r] = 0.0f;
+
+    for (int k = k0 - 2; k <= k1; ++k) {
+        load_e(k + 1, Enx);
+#pragma unroll
+        for (int r = 0; r < NH; ++r) {
+            const int o = ro(j0 - 2 + r, k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Ho[c][r] = bload(FA, xo, hb + c * rowb + o);
+        }
+        const bool do_e1 = k >= k0 - 1;
+        if (do_e1) {
+#pragma unroll
+            for (int r = 1; r < NH; ++r) {
+                const int o = rk(j0 - 2 + r, k);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Kc[c][r] = bload(K, xo, c * rowb + o);
+            }
+        }
+        // ---- step n+1's Ht at plane k, rows 0..TY+2 ----
+#pragma unroll
+        for (int r = 0; r < NH; ++r) {
+            const float ez_i1 = shfl_next(Ec[2][r]);
+            const float ey_i1 = shfl_next(Ec[1][r]);
+            const float dyEz = Ec[2][r + 1] - Ec[2][r];
+            const float dzEy = Enx[1][r] - Ec[1][r];
+            const float dzEx = Enx[0][r] - Ec[0][r];
+            const float dxEz = ez_i1 - Ec[2][r];
+            const float dxEy = ey_i1 - Ec[1][r];
+            const float dyEx = Ec[0][r + 1] - Ec[0][r];
+            Hh[0][r] = Ho[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
+            Hh[1][r] = Ho[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
+            Hh[2][r] = Ho[2][r] - fmaf(sx, dxEy, -(sy * dyEx));
+        }
+        if (do_e1) {
+            // ---- step n+1's E at plane k, rows 1..TY+2 ----
+            const bool own_k = k >= k0 && k < k1;
+            const bool rim_k = k == rc0 || k == rc1 - 1;
+#pragma unroll
+            for (int r = 1; r < NH; ++r) {
+                const int j = j0 - 2 + r;
+                const float hz_im = shfl_prev(Hh[2][r]);
+                const float hy_im = shfl_prev(Hh[1][r]);
+                const float dyHz = Hh[2][r] - Hh[2][r - 1];
+                const float dzHy = Hh[1][r] - Hhp[1][r];
+                const float dzHx = Hh[0][r] - Hhp[0][r];
+                const float dxHz = Hh[2][r] - hz_im;
+                const float dxHy = Hh[1][r] - hy_im;
+                const float dyHx = Hh[0][r] - Hh[0][r - 1];
+                float ex = fmaf(Kc[0][r], fmaf(sy, dyHz, -(sz * dzHy)), Ec[0][r]);
+                float ey = fmaf(Kc[1][r], fmaf(sz, dzHx, -(sx * dxHz)), Ec[1][r]);
+                float ez = fmaf(Kc[2][r], fmaf(sx, dxHy, -(sy * dyHx)), Ec[2][r]);
+                ex = (j == 0 || k == 0) ? 0.0f : ex;
+                ey = (x == 0 || k == 0) ? 0.0f : ey;
+                ez = (x == 0 || j == 0) ? 0.0f : ez;
+                E1c[0][r] = ex;
+                E1c[1][r] = ey;
+                E1c[2][r] = ez;
+                // the step-n+1 state of R2's outermost layer
+                const bool own_r = r >= 2 && r - 2 < jn;
+                if (own_k && own_r && own_x && (rim_k || rim_x || j == rb0 || j == rb1 - 1)) {
+                    const int o = ro(j, k);
+                    bstore_nt(ex, FB, xo, eb + o);
+                    bstore_nt(ey, FB, xo, eb + rowb + o);
+                    bstore_nt(ez, FB, xo, eb + 2 * rowb + o);
+                    bstore_nt(Hh[0][r], FB, xo, hb + o);
+                    bstore_nt(Hh[1][r], FB, xo, hb + rowb + o);
+                    bstore_nt(Hh[2][r], FB, xo, hb + 2 * rowb + o);
+                }
+            }
+        }
+        if (k >= k0) {
+            // ---- step n+2 at plane km = k-1: Ht rows 1..TY+1, E rows 2..TY+1 ----
+            const int km = k - 1;
+#pragma unroll
+            for (int r = 1; r <= TY + 1; ++r) {
+                const float ez_i1 = shfl_next(E1p[2][r]);
+                const float ey_i1 = shfl_next(E1p[1][r]);
+                const float dyEz = E1p[2][r + 1] - E1p[2][r];
+                const float dzEy = E1c[1][r] - E1p[1][r];
+                const float dzEx = E1c[0][r] - E1p[0][r];
+                const float dxEz = ez_i1 - E1p[2][r];
+                const float dxEy = ey_i1 - E1p[1][r];
+                const float dyEx = E1p[0][r + 1] - E1p[0][r];
+                H2[0][r] = Hhp[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
+                H2[1][r] = Hhp[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
+                H2[2][r] = Hhp[2][r] - fmaf(sx, dxEy, -(sy * dyEx));
+            }
+            if (km >= k0) {
+#pragma unroll
+                for (int r = 2; r <= TY + 1; ++r) {
+                    const int j = j0 - 2 + r;
+                    const float hz_im = shfl_prev(H2[2][r]);
+                    const float hy_im = shfl_prev(H2[1][r]);
+                    if (r - 2 >= jn) continue;
+                    const float dyHz = H2[2][r] - H2[2][r - 1];
+                    const float dzHy = H2[1][r] - H2p[1][r];
+                    const float dzHx = H2[0][r] - H2p[0][r];
+                    const float dxHz = H2[2][r] - hz_im;
+                    const float dxHy = H2[1][r] - hy_im;
+                    const float dyHx = H2[0][r] - H2[0][r - 1];
+                    float ex = fmaf(Kp[0][r], fmaf(sy, dyHz, -(sz * dzHy)), E1p[0][r]);
+                    float ey = fmaf(Kp[1][r], fmaf(sz, dzHx, -(sx * dxHz)), E1p[1][r]);
+                    float ez = fmaf(Kp[2][r], fmaf(sx, dxHy, -(sy * dyHx)), E1p[2][r]);
+                    ex = (j == 0 || km == 0) ? 0.0f : ex;
+                    ey = (x == 0 || km == 0) ? 0.0f : ey;
+                    ez = (x == 0 || j == 0) ? 0.0f : ez;
+                    if (own_x) {
+                        const int o = ro(j, km);
+                        bstore_nt(ex, FC, xo, eb + o);
+                        bstore_nt(ey, FC, xo, eb + rowb + o);
+                        bstore_nt(ez, FC, xo, eb + 2 * rowb + o);
+                        bstore_nt(H2[0][r], FC, xo, hb + o);
+                        bstore_nt(H2[1][r], FC, xo, hb + rowb + o);
+                        bstore_nt(H2[2][r], FC, xo, hb + 2 * rowb + o);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 1; r <= TY + 1; ++r) {
+                H2p[0][r] = H2[0][r];
+                H2p[1][r] = H2[1][r];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int r = 0; r < NE; ++r) Ec[c][r] = Enx[c][r];
+#pragma unroll
+            for (int r = 0; r < NH; ++r) {
+                Hhp[c][r] = Hh[c][r];
+                E1p[c][r] = E1c[c][r];
+                Kp[c][r] = Kc[c][r];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step2(const YoStepArgs a)
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, rem = nb & 7, xcd = b & 7, pos = b >> 3;
+    const int lb = (xcd < rem) ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
+    const int wpb = a.wpb;
+    const int wave = __builtin_amdgcn_readfirstlane(lb * wpb + (int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (wave >= a.total_waves) return;
+    int s = 0;
+    while (s + 1 < a.n_slots && wave >= a.prefix[s + 1]) ++s;
+    const YoSlot sl = a.slot[s];
+    const YoPlanD &P = *sl.plan;
+    const int step = *P.step_ctr + a.k_offset;
+    // the host schedules a pair only where both steps remain
+    if (step + 1 >= P.n_steps) return;
+    const int local = wave - a.prefix[s];
+    const int grp = local / (wpb * sl.nrhs);
+    const int in_grp = local - grp * (wpb * sl.nrhs);
+    const int r = sl.rhs0 + in_grp / wpb;
+    const int ti = grp * wpb + in_grp % wpb;
+    if (ti >= sl.ntile) return;
+    wave_step2<YO_TY>(P, P.rhs[r], step, sl.tiles[ti], lane);
+}
+
 // locate point q of slot s in the aux work list
 __device__ __forceinline__ bool aux_point(const YoAuxArgs &a, int &s, int &r, int &q)
 {
@@ -704,7 +943,7 @@ __global__ __launch_bounds__(256) void k_dft(const YoAuxArgs a)
     const int w = step - R.win_start;
     if (w < 0 || w >= R.win_len) return;
     if (P.dft_stride > 1 && step % P.dft_stride) return;
-    const float *F = R.F[step & 1];
+    const float *F = R.F[step % P.nbuf];
     const int bx = P.box[3], by = P.box[4], bz = P.box[5];
     const int bsz = bx * by * bz;
     float e;
@@ -769,7 +1008,7 @@ __global__ __launch_bounds__(256) void k_source(const YoAuxArgs a)
     const size_t o = yo_off(c, cx, cy, cz, P.ny, P.nxp, 6);
     const float2 jv = R.src_j[q];
     const float j = fmaf(jv.x, st.x, jv.y * st.y);
-    float *F = R.F[(step + 1) & 1];
+    float *F = R.F[(step + 1) % P.nbuf];
     F[o] = fmaf(-P.kappa[yo_off(c, cx, cy, cz, P.ny, P.nxp, 3)], j, F[o]);
 }
 
@@ -816,6 +1055,14 @@ hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &ar
     case YO_PM_ANY: launch_pm<YO_PM_ANY>(coop, prefetch, args, blocks, s); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t yo_launch_step2(const YoStepArgs &args, int blocks, hipStream_t s)
+{
+    if (blocks <= 0) return hipSuccess;
+    if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_yee_step2, dim3(blocks), dim3(64 * args.wpb), 0, s, args);
     return hipGetLastError();
 }
 

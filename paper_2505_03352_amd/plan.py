@@ -57,11 +57,13 @@ class Plan:
 
     def __init__(self, grid: dict, design: dict, n_steps: int, freqs: Sequence[FreqSpec],
                  src_planes: Sequence, port_planes: Sequence, device="cuda", pulse=None,
-                 two_term: bool = False):
+                 two_term: bool = False, time_blocking: int = 1):
         """pulse: None, or (omega0 rad/s, sigma steps, t0 steps[, DFT stride])
         for pulse excitation (one run per source and per port for all
         wavelengths; the DFT samples every stride-th step, default 1).
-        two_term: the modal coefficient with both of its terms (App. A)."""
+        two_term: the modal coefficient with both of its terms (App. A).
+        time_blocking: 2 gives the plan a third state buffer so that tiling
+        flag 512 can advance its interior two steps per launch."""
         self.device = torch.device(device)
         self.grid = dict(grid)
         self.design = dict(design)
@@ -103,6 +105,9 @@ class Plan:
             call("yo_set_pulse", self._h, float(pulse[0]), float(pulse[1]), float(pulse[2]))
             if len(self.pulse) > 3 and int(self.pulse[3]) != 1:
                 call("yo_set_dft_stride", self._h, int(self.pulse[3]))
+        self.time_blocking = int(time_blocking)
+        if self.time_blocking != 1:
+            call("yo_set_time_blocking", self._h, self.time_blocking)
         nb = ct.c_size_t()
         call("yo_workspace_bytes", self._h, ct.byref(nb))
         self.workspace_bytes = int(nb.value)
@@ -354,14 +359,16 @@ def freqs_of(dev) -> List[FreqSpec]:
 
 def plan_for(dev, device="cuda", stream=None, C=None, beta=None, set_design=True,
              workspace: Optional[torch.Tensor] = None, pulse=None, two_term: bool = False,
-             static_workspace: bool = False) -> Plan:
+             static_workspace: bool = False, time_blocking: int = 1) -> Plan:
     """Create, bind and fill a plan for a device description.  pulse:
-    (omega0 rad/s, sigma steps, t0 steps) for pulse excitation; two_term:
-    the two-term modal coefficient; static_workspace: bind the library's
-    static workspace instead of allocating one."""
+    (omega0 rad/s, sigma steps, t0 steps[, DFT stride]) for pulse excitation;
+    two_term: the two-term modal coefficient; static_workspace: bind the
+    library's static workspace instead of allocating one; time_blocking: 2
+    for a plan that may take two steps per launch (tiling flag 512)."""
     grid, design = grid_design_of(dev)
     p = Plan(grid, design, dev.n_steps, freqs_of(dev), [m.plane for m in dev.sources],
-             [m.plane for m in dev.ports], device=device, pulse=pulse, two_term=two_term)
+             [m.plane for m in dev.ports], device=device, pulse=pulse, two_term=two_term,
+             time_blocking=time_blocking)
     if static_workspace:
         p.bind_static(stream)
     else:

@@ -251,3 +251,26 @@ def test_dft_stride_arguments():
     assert L.yo_set_dft_stride(p.handle, 8) == _abi.YO_EINVAL
     assert b"alias" in L.yo_last_error()
     p.close()
+
+
+def test_time_blocking_arguments_and_workspace():
+    """yo_set_time_blocking adds one state buffer per right-hand side; tiling
+    flag 512 needs it and does not combine with flag 16."""
+    dev = configs.tiny()
+    p = _create(dev)
+    L = _abi.lib()
+    b1 = p.workspace_bytes
+    assert L.yo_set_tiling(p.handle, 4, 16, 512) == _abi.YO_EINVAL
+    assert L.yo_set_time_blocking(p.handle, 3) == _abi.YO_EINVAL
+    assert L.yo_set_time_blocking(p.handle, 2) == _abi.YO_OK
+    nb = ct.c_size_t()
+    assert L.yo_workspace_bytes(p.handle, ct.byref(nb)) == _abi.YO_OK
+    nxp = (dev.nx + 2 + 31) // 32 * 32
+    one_buffer = 6 * 4 * (dev.nz + 2) * (dev.ny + 2) * nxp
+    assert nb.value - b1 >= 2 * one_buffer          # forward + adjoint right-hand side
+    assert L.yo_set_tiling(p.handle, 4, 16, 512) == _abi.YO_OK
+    assert L.yo_set_tiling(p.handle, 4, 16, 512 | 16) == _abi.YO_EINVAL
+    assert L.yo_set_tiling(p.handle, 4, 16, 512 | 256) == _abi.YO_OK
+    assert L.yo_set_time_blocking(p.handle, 1) == _abi.YO_OK
+    assert L.yo_workspace_bytes(p.handle, ct.byref(nb)) == _abi.YO_OK and nb.value == b1
+    p.close()
