@@ -308,6 +308,12 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
  *       tiles are strips of at most 60 cells, 4 rows and zchunk planes, and
  *       the rest of the interior runs as single-step tiles around it (with
  *       256, together with the tiles that meet only the x-slabs)
+ * 1024  with 512 (else YO_EINVAL): the two-step launch of a pair of steps
+ *       runs on a second stream of the plan (created at its first advance,
+ *       default priority), concurrently with the first step's other
+ *       launches, and is joined back before the second step; advance calls
+ *       on the caller's stream still complete in stream order, captured
+ *       into a graph as well
  * Other bits: YO_EINVAL.  Results do not depend on the split (bitwise).
  * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);

@@ -13,8 +13,11 @@ extent, ny, nz, number of right-hand sides, CPML width, time blocking), so
 plans of the same class reuse the choice.  For a plan with time blocking it
 also times two steps per launch (the two-step region's launch, the interior
 around it and the shell, each with its own best choice) and keeps that when
-it is faster per step.  Every split gives bitwise the same fields, so
-tuning only changes speed.
+it is faster per step; with two steps per launch chosen, it then times whole
+steps with the two-step launch on a second stream beside the first step's
+other launches (flag 1024) against the same launches in one stream, and keeps
+the faster.  Every split gives bitwise the same fields, so tuning only
+changes speed.
 """
 from __future__ import annotations
 
@@ -96,6 +99,22 @@ def _time(plan, zc, flags, part, which, n_launch, stream) -> float:
     return ms
 
 
+def _time_steps(plan, zc, flags, which, n_steps, stream) -> float:
+    """ms per step of `n_steps` whole steps as plain launches (HIP events
+    on the plan's stream)."""
+    from .plan import advance_many
+    plan.set_tiling(ROWS, zc, flags)
+    plan.reset(which, stream)
+    advance_many([plan], [which], 2, chunk=2, use_graph=False, stream=stream)   # warm-up
+    s = torch.cuda.current_stream() if stream is None else stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    advance_many([plan], [which], n_steps, chunk=n_steps, use_graph=False, stream=stream)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / n_steps
+
+
 def tune(plan, which: int = YO_BOTH, shared: Optional[Iterable] = None, n_launch: int = 5,
          use_cache: bool = True, stream=None, pair_shared: Optional[Iterable] = None) -> dict:
     """Pick and apply the fastest split for `plan`; returns the record.
@@ -151,9 +170,22 @@ def tune(plan, which: int = YO_BOTH, shared: Optional[Iterable] = None, n_launch
                                                    best=fl, ms=round(per_step, 4))
             if per_step < total:
                 total, zc, flags = per_step, zc2, fl
+    overlap = None
+    n_ov = 4 * n_launch
+    if flags & 512 and plan.n_steps >= n_ov + 2:
+        # the two-step launch beside the first step's frame and shell: the
+        # parts' separate timings cannot tell, so whole steps are timed
+        t_one = _time_steps(plan, zc, flags, which, n_ov, stream)
+        t_two = _time_steps(plan, zc, flags | 1024, which, n_ov, stream)
+        overlap = dict(one_stream=round(t_one, 4), two_streams=round(t_two, 4))
+        if t_two < 0.99 * t_one:
+            flags |= 1024
+            total *= t_two / t_one
     plan.set_tiling(ROWS, zc, flags)
     plan.reset(which, stream)
     rec = dict(rows=ROWS, zchunk=zc, flags=flags, ms_per_step=total, timings=timings)
+    if overlap:
+        rec["overlap"] = overlap
     if use_cache:
         with _lock:
             d = _load()

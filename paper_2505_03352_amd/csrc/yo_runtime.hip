@@ -93,7 +93,8 @@ enum {
     YO_TILE_XFULL = 128,      // x-shell strips as narrow as whole 62-cell interior strips allow
     YO_TILE_XINT = 256,       // tiles inside the x-slabs only run in the interior launch (x CPML code)
     YO_TILE_PAIRS = 512,      // the two-step region advances two steps per sweep (yo_set_time_blocking)
-    YO_TILE_ALL = 1023
+    YO_TILE_OVERLAP = 1024,   // with 512: the two-step launch runs beside the first step's frame and shell
+    YO_TILE_ALL = 2047
 };
 
 struct yo_plan {
@@ -172,6 +173,10 @@ struct yo_plan {
     int static_dev = -1;
     unsigned static_epoch = 0;
     hipStream_t cap_stream = nullptr;
+    // YO_TILE_OVERLAP: the stream the two-step launch runs on, and the
+    // events that fork it from the caller's stream and join it back
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ov_fork = nullptr, ov_join = nullptr;
     // launch timing: the last tm_n steps of each advance run eagerly, with
     // HIP events around the launches of part tm_part (0 or 1, or 2 for
     // every part); tm_ev[q] holds the event pairs of part q (see part_range)
@@ -455,6 +460,23 @@ void split_axis(int n, int lo, int hi, int w, std::vector<std::pair<int, int>> &
 // two-step tiles cover R2 (strips of at most 60 cells, YO_TY rows, kc
 // planes), and single-step tiles cover the rest of the interior (the
 // "frame"), cut at R2's faces.
+// Keep the source and port planes normal to axis `a` out of [r0, r1) along
+// it: step n+1's E is computed on [r0 - 1, r1] along the plane's normal and
+// a plane's currents touch indices i .. i + (ncomp == 5); the range keeps
+// the larger side of each plane that meets it.
+static void cut_planes(const yo_plan *p, int a, int &r0, int &r1)
+{
+    auto cut = [&](const yo_plane &pl, int ncomp) {
+        const int i = pl.index, i_end = pl.index + (ncomp == 5 ? 1 : 0);
+        if (pl.axis != a || r1 <= r0 || i_end < r0 - 1 || i > r1) return;
+        const int below = (i - 1) - r0, above = r1 - (i_end + 2);
+        if (below >= above) r1 = i - 1;
+        else r0 = i_end + 2;
+    };
+    for (const yo_plane &pl : p->src_planes) cut(pl, 2);
+    for (const yo_plane &pl : p->port_planes) cut(pl, p->mon_nc);
+}
+
 void build_pair_tiles(yo_plan *p, const int lo[3], const int hi[3])
 {
     const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
@@ -462,19 +484,8 @@ void build_pair_tiles(yo_plan *p, const int lo[3], const int hi[3])
     for (int a = 0; a < 3; ++a) {
         r[2 * a] = std::max(lo[a], p->plo[a] + 2);
         r[2 * a + 1] = std::min(hi[a], n[a] - p->phi[a] - 1);
+        cut_planes(p, a, r[2 * a], r[2 * a + 1]);
     }
-    auto cut = [&](const yo_plane &pl, int ncomp) {
-        // step n+1's E is computed on [r0 - 1, r1] along the plane's normal;
-        // the plane's currents touch indices i .. i + (ncomp == 5)
-        const int a = pl.axis, i = pl.index, i_end = pl.index + (ncomp == 5 ? 1 : 0);
-        int &r0 = r[2 * a], &r1 = r[2 * a + 1];
-        if (r1 <= r0 || i_end < r0 - 1 || i > r1) return;
-        const int below = (i - 1) - r0, above = r1 - (i_end + 2);
-        if (below >= above) r1 = i - 1;
-        else r0 = i_end + 2;
-    };
-    for (const yo_plane &pl : p->src_planes) cut(pl, 2);
-    for (const yo_plane &pl : p->port_planes) cut(pl, p->mon_nc);
     for (int a = 0; a < 3; ++a)
         if (r[2 * a + 1] - r[2 * a] < 4) return;   // too thin: no two-step region
     for (int i = 0; i < 6; ++i) p->r2[i] = r[i];
@@ -547,15 +558,31 @@ void build_pair_tiles(yo_plan *p, const int lo[3], const int hi[3])
 // class (int4 .w) has bit a set when it is not clear along axis a.  The two
 // parts may use different row counts (cooperative blocks take YO_TY rows per
 // wave of the block).
+// With two steps per launch (YO_TILE_PAIRS) the region clear of the slabs is
+// [lo + 2, n - hi - 1), the two-step region's own margin, so that no
+// single-step interior layer one cell thick lies between that region and
+// the shell (the shell runs the layer, its CPML code idle there); and
+// YO_TILE_XFULL then cuts whole 60-cell strips of the two-step launch out
+// of the row between the x-normal source and port planes.
 void build_tiles(yo_plan *p)
 {
     const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
     const int wpb = (p->tflags & YO_TILE_WPB8) ? 8 : 4;
+    const bool pr = p->tsteps == 2 && (p->tflags & YO_TILE_PAIRS);
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-        lo[a] = p->plo[a] > 0 ? p->plo[a] + 1 : 0;
-        hi[a] = n[a] - p->phi[a];
-        if (a == 0 && (p->tflags & YO_TILE_XFULL) && hi[0] - lo[0] >= YO_TX) {
+        lo[a] = p->plo[a] > 0 ? p->plo[a] + (pr ? 2 : 1) : 0;
+        hi[a] = n[a] - p->phi[a] - (pr && p->phi[a] > 0 ? 1 : 0);
+        int a0 = lo[a], a1 = hi[a];
+        if (a == 0 && pr) cut_planes(p, 0, a0, a1);
+        if (a == 0 && pr && (p->tflags & YO_TILE_XFULL) && a1 - a0 >= 60) {
+            // whole 60-cell two-step strips, centred in the row where the
+            // planes allow; the shell strips take the rest
+            const int whole = (a1 - a0) / 60 * 60;
+            const int wlo = std::min(std::max((n[0] - whole) / 2, a0), a1 - whole);
+            lo[0] = wlo;
+            hi[0] = wlo + whole;
+        } else if (a == 0 && (p->tflags & YO_TILE_XFULL) && hi[0] - lo[0] >= YO_TX) {
             // the interior takes as many whole strips as fit; the rest of the
             // row goes to the two shell strips (which then also carry
             // interior columns)
@@ -847,6 +874,9 @@ void yo_plan_destroy(yo_plan *p)
         }
     }
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+    if (p->ov_fork) (void)hipEventDestroy(p->ov_fork);
+    if (p->ov_join) (void)hipEventDestroy(p->ov_join);
     for (int q = 0; q < 4; ++q)
         for (hipEvent_t e : p->tm_ev[q]) (void)hipEventDestroy(e);
     delete p;
@@ -1092,6 +1122,8 @@ yo_status yo_set_alpha_terms(yo_plan *p, int terms)
         }
     }
     p->mon_nc = terms == 2 ? 5 : 2;
+    // the two-step region keeps clear of every plane a port's currents touch
+    build_tiles(p);
     build_port_tables(p);
     p->port_w_host.clear();
     std::fill(p->port_set.begin(), p->port_set.end(), 0);
@@ -1202,7 +1234,7 @@ yo_status yo_set_time_blocking(yo_plan *p, int steps)
     if (steps != 1 && steps != 2) return fail(YO_EINVAL, "steps per sweep must be 1 or 2");
     p->tsteps = steps;
     p->nbuf = steps == 2 ? 3 : 2;
-    if (steps == 1) p->tflags &= ~YO_TILE_PAIRS;
+    if (steps == 1) p->tflags &= ~(YO_TILE_PAIRS | YO_TILE_OVERLAP);
     // the two-step and frame tiles can add up to twice the single-step count
     p->tiles_cap = tiles_capacity(p->grid, 4, 4) * (steps == 2 ? 3 : 1);
     build_tiles(p);
@@ -1262,6 +1294,8 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
         return fail(YO_EINVAL, "flag 512 needs yo_set_time_blocking(plan, 2) before binding");
     if ((flags & YO_TILE_PAIRS) && (flags & YO_TILE_COOP_INT))
         return fail(YO_EINVAL, "flag 512 does not combine with flag 16");
+    if ((flags & YO_TILE_OVERLAP) && !(flags & YO_TILE_PAIRS))
+        return fail(YO_EINVAL, "flag 1024 needs flag 512");
     p->kc = zchunk;
     p->tflags = flags;
     build_tiles(p);
@@ -1557,11 +1591,18 @@ static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, 
 // two at a time where two remain (the two-step region in one launch for
 // both, the interior around it and the CPML shell one step at a time, the
 // source after each step); the caller guarantees no DFT at the second step
-// of a pair.
+// of a pair.  With YO_TILE_OVERLAP the two-step launch of a pair goes on
+// the first plan's side stream, forked after the launches before it and
+// joined before the pair's second step: the first step's frame, shell and
+// source read only step n's buffer and write cells of step n+1's buffer that
+// the two-step launch does not (it reads step n's and writes R2's rim of
+// step n+1's and R2 of step n+2's), so the two may run at once.
 static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, int n_launch,
                               bool with_dft, hipStream_t s, yo_plan *timed = nullptr,
                               int dft_every = 1, bool pairs = false)
 {
+    yo_plan *const p0 = plans[0];
+    const bool overlap = pairs && (p0->tflags & YO_TILE_OVERLAP) && p0->side_stream;
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
         static thread_local YoStepArgs A[4];
@@ -1571,7 +1612,7 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
         YoAuxArgs ad, as;
         aux_args(plans + base, which + base, cnt, true, ad);
         aux_args(plans + base, which + base, cnt, false, as);
-        auto launch = [&](int part, int k) -> yo_status {
+        auto launch = [&](int part, int k, hipStream_t on) -> yo_status {
             A[part].k_offset = k;
             const bool tm = timed && base == 0 && blocks[part] &&
                             (timed->tm_part == part || timed->tm_part == 2);
@@ -1583,12 +1624,12 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
                     HIPCHK(hipEventCreate(&e));
                     ev.push_back(e);
                 }
-                HIPCHK(hipEventRecord(ev[need - 2], s));
-                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
-                HIPCHK(hipEventRecord(ev[need - 1], s));
+                HIPCHK(hipEventRecord(ev[need - 2], on));
+                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], on));
+                HIPCHK(hipEventRecord(ev[need - 1], on));
                 timed->tm_done[part]++;
             } else {
-                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], s));
+                HIPCHK(launch_part(plans[base], part, A[part], blocks[part], on));
             }
             return YO_OK;
         };
@@ -1599,17 +1640,25 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
                 HIPCHK(yo_launch_dft(ad, s));
             }
             if (pairs && k + 1 < n_launch) {
-                if ((st = launch(2, k))) return st;
+                if (overlap) {
+                    HIPCHK(hipEventRecord(p0->ov_fork, s));
+                    HIPCHK(hipStreamWaitEvent(p0->side_stream, p0->ov_fork, 0));
+                    if ((st = launch(2, k, p0->side_stream))) return st;
+                    HIPCHK(hipEventRecord(p0->ov_join, p0->side_stream));
+                } else if ((st = launch(2, k, s))) {
+                    return st;
+                }
                 for (int q = 0; q < 2; ++q) {
-                    if ((st = launch(3, k + q))) return st;
-                    if ((st = launch(1, k + q))) return st;
+                    if (q == 1 && overlap) HIPCHK(hipStreamWaitEvent(s, p0->ov_join, 0));
+                    if ((st = launch(3, k + q, s))) return st;
+                    if ((st = launch(1, k + q, s))) return st;
                     as.k_offset = k + q;
                     HIPCHK(yo_launch_source(as, s));
                 }
                 k += 2;
             } else {
                 for (int part = 0; part < 2; ++part)
-                    if ((st = launch(part, k))) return st;
+                    if ((st = launch(part, k, s))) return st;
                 as.k_offset = k;
                 HIPCHK(yo_launch_source(as, s));
                 k += 1;
@@ -1691,6 +1740,12 @@ yo_status yo_advance_many(yo_plan *const *plans, const int *which, int n, int n_
     }
     hipStream_t s = (hipStream_t)stream;
     if (chunk < 1) chunk = 1;
+    if ((plans[0]->tflags & YO_TILE_OVERLAP) && !plans[0]->side_stream) {
+        yo_plan *p0 = plans[0];
+        HIPCHK(hipEventCreateWithFlags(&p0->ov_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&p0->ov_join, hipEventDisableTiming));
+        HIPCHK(hipStreamCreateWithFlags(&p0->side_stream, hipStreamNonBlocking));
+    }
     // launch timing (yo_set_timing on the first plan): the last tm_n steps
     // of this call run eagerly with events around the timed part
     yo_plan *timed = plans[0]->tm_n > 0 ? plans[0] : nullptr;

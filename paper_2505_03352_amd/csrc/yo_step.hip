@@ -345,7 +345,11 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
         return xme[(pp * YO_MAX_WPB + dw) * 4 * 64 + c * 64];
     };
     const int x = x0 - 1 + lane;
-    const int xo = (clampi(x, -1, nx) + 1) * (int)sizeof(float);   // column byte offset (ghost clamped)
+    // lanes past the halo lane after the last owned one take no part: their
+    // column offset lies past every buffer, so their loads move no data (a
+    // narrow strip costs only its own columns)
+    const bool lane_used = lane <= xn + 1;
+    const int xo = lane_used ? (clampi(x, -1, nx) + 1) * (int)sizeof(float) : 0x40000000;
     const bool own_x = (lane >= 1) && (lane <= xn);
     // wave-uniform byte offsets of row group (j, k) in the state and kappa arrays
     auto ro = [&](int j, int k) -> int {
@@ -389,7 +393,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
                 C.czH = cpml_at(P.prof[2], nz, 3, kk);
             }
         }
-        if ((PM & 1) && xin) {
+        if ((PM & 1) && xin && lane_used) {
             pxs = slab_index(x, nx, P.plo[0], P.phi[0]);
             if (pxs >= 0) {
                 cxE = cpml_at(P.prof[0], nx, 0, x);
@@ -482,7 +486,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 #pragma unroll
             for (int r = 0; r <= TY; ++r) {
                 const int j = j0 - 1 + r;
-                const bool use = (r > 0 || bottom) && xin && kin && j >= 0 && j < ny;
+                const bool use = (r > 0 || bottom) && xin && lane_used && kin && j >= 0 && j < ny;
                 psi_preload<PM>(C, 2 + 2 * par, x, j, k, pxs, use, qH[r]);
             }
 #pragma unroll
@@ -513,8 +517,8 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             float dyEx = Ec[0][r + 1] - Ec[0][r];
             const bool own = own_x && own_k && (r >= 1) && (r <= jn);
             if (PM)
-                h_cpml<PM, PRE>(C, par, x, j, k, pxs, cxH, own, qH[r], dxEz, dxEy, dyEz, dyEx, dzEy,
-                                dzEx);
+                h_cpml<PM, PRE>(C, par, lane_used ? x : -1, j, k, pxs, cxH, own, qH[r], dxEz, dxEy,
+                                dyEz, dyEx, dzEy, dzEx);
             const float hx = Ho_[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
             const float hy = Ho_[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
             const float hz = Ho_[2][r] - fmaf(sx, dxEy, -(sy * dyEx));

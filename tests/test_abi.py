@@ -255,7 +255,7 @@ def test_dft_stride_arguments():
 
 def test_time_blocking_arguments_and_workspace():
     """yo_set_time_blocking adds one state buffer per right-hand side; tiling
-    flag 512 needs it and does not combine with flag 16."""
+    flag 512 needs it and does not combine with flag 16; flag 1024 needs 512."""
     dev = configs.tiny()
     p = _create(dev)
     L = _abi.lib()
@@ -271,6 +271,9 @@ def test_time_blocking_arguments_and_workspace():
     assert L.yo_set_tiling(p.handle, 4, 16, 512) == _abi.YO_OK
     assert L.yo_set_tiling(p.handle, 4, 16, 512 | 16) == _abi.YO_EINVAL
     assert L.yo_set_tiling(p.handle, 4, 16, 512 | 256) == _abi.YO_OK
+    assert L.yo_set_tiling(p.handle, 4, 16, 512 | 1024) == _abi.YO_OK
+    assert L.yo_set_tiling(p.handle, 4, 16, 1024) == _abi.YO_EINVAL         # needs 512
+    assert L.yo_set_tiling(p.handle, 4, 16, 2048) == _abi.YO_EINVAL
     assert L.yo_set_time_blocking(p.handle, 1) == _abi.YO_OK
     assert L.yo_workspace_bytes(p.handle, ct.byref(nb)) == _abi.YO_OK and nb.value == b1
     p.close()

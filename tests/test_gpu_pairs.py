@@ -4,7 +4,9 @@ the C ABI: every field value, phasor, alpha and gradient bitwise equal, with
 CPML and a source plane, with several right-hand sides and wavelengths (the
 DFT window runs single steps), under a pulse whose DFT samples every fourth
 step, for plans stepped together in shared launches, and with odd step
-counts (a run's last step alone)."""
+counts (a run's last step alone); also with the two-step launch on a second
+stream beside the first step's other launches (flag 1024), eager and in
+graphs."""
 import sys
 
 import numpy as np
@@ -55,7 +57,8 @@ def test_pairs_bitwise_equal_single_steps_with_cpml_and_source(steps):
     for tb, zc, fl, graph in [(1, 16, 0, False), (2, 16, 512, False), (2, 8, 512 | 2, True),
                               (2, 10, 512 | 1 | 64 | 8, True), (2, 10, 512 | 128, False),
                               (2, 4, 512 | 32, True), (2, 10, 512 | 256 | 1 | 64, True),
-                              (2, 8, 512 | 256 | 128 | 2, False)]:
+                              (2, 8, 512 | 256 | 128 | 2, False), (2, 10, 512 | 1024 | 1 | 8, True),
+                              (2, 8, 512 | 1024 | 128, False)]:
         say(f"pairs box steps={steps} tb={tb} tiling=(4,{zc},{fl}) graph={graph}")
         p = _box_plan(steps, tb)
         p.set_tiling(4, zc, fl)
@@ -92,7 +95,7 @@ def test_pairs_bitwise_equal_with_window_and_several_wavelengths():
     dev = configs.micro(n_steps=400, nx=150, ny=40, nz=30, md=10, nd=10, mc=5, nc=5,
                         wavelengths=[0.78e-6, 0.8e-6, 0.82e-6])
     res = {}
-    for tb, fl in [(1, 0), (2, 512), (2, 512 | 73)]:
+    for tb, fl in [(1, 0), (2, 512), (2, 512 | 73), (2, 512 | 1024 | 73)]:
         say(f"pairs micro tb={tb} flags={fl}")
         p = plan_for(dev, time_blocking=tb)
         p.set_tiling(4, 10, fl)
@@ -115,13 +118,13 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
     from paper_2505_03352_amd.plan import advance_many, plan_for
     devs = [configs.micro_demux(n_steps=2600), configs.micro(n_steps=1300, nx=90, ny=34, nz=24)]
     res = {}
-    for tb in (1, 2):
-        say(f"pairs pulse + shared launches tb={tb}")
+    for tb, fl in ((1, 0), (2, 512), (2, 512 | 1024)):
+        say(f"pairs pulse + shared launches tb={tb} flags={fl}")
         plans = []
         for d in devs:
             w0, sig, t0 = d.pulse()
             p = plan_for(d, pulse=(w0 / d.dt(), sig, t0, 4), time_blocking=tb)
-            p.set_tiling(4, 8, 512 if tb == 2 else 0)
+            p.set_tiling(4, 8, fl)
             plans.append(p)
         for p in plans:
             p.reset(3)
@@ -132,9 +135,10 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
             a = p.alpha()
             out += [p.get_dft(r, 0).cpu().numpy() for r in range(p.n_rhs)] + [a.cpu().numpy()]
             p.close()
-        res[tb] = out
-    for x, y in zip(res[2], res[1]):
-        assert np.array_equal(x, y)
+        res[fl] = out
+    for fl in (512, 512 | 1024):
+        for x, y in zip(res[fl], res[0]):
+            assert np.array_equal(x, y), fl
 
 
 def test_autotuner_times_pairs_and_keeps_results():
@@ -158,8 +162,41 @@ def test_autotuner_times_pairs_and_keeps_results():
         t = rec["timings"][k]
         assert t["two_step"] > 0 and min(t["shell"].values()) > 0
     best = min(rec["timings"].values(), key=lambda t: t["ms"])
-    assert rec["flags"] == best["best"] and rec["ms_per_step"] == pytest.approx(best["ms"], abs=1e-4)
+    # flag 1024 (the two-step launch on a second stream) is decided on whole
+    # steps after the split, when the split has two steps per launch
+    assert rec["flags"] & ~1024 == best["best"]
+    if rec["flags"] & 512:
+        ov = rec["overlap"]
+        assert ov["one_stream"] > 0 and ov["two_streams"] > 0
+        assert bool(rec["flags"] & 1024) == (ov["two_streams"] < 0.99 * ov["one_stream"])
+    else:
+        assert rec["ms_per_step"] == pytest.approx(best["ms"], abs=1e-4)
     advance_many([p], [1], 120, chunk=40, use_graph=True)
     E, H = (x.cpu().numpy() for x in p.get_fields(0))
     assert np.array_equal(E, E0) and np.array_equal(H, H0)
     p.close()
+
+
+def test_pairs_bitwise_equal_with_two_term_ports():
+    """The two-term coefficient's adjoint currents touch each port plane and
+    the plane after it; the two-step region keeps clear of both, also in the
+    split of whole 60-cell two-step strips (flag 128), so alpha and the
+    gradient are bitwise those of single steps."""
+    from paper_2505_03352_amd.plan import plan_for
+    dev = configs.micro(n_steps=400, nx=150, ny=40, nz=30, md=10, nd=10, mc=5, nc=5)
+    res = {}
+    for tb, fl in [(1, 0), (2, 512 | 128), (2, 512 | 73), (2, 512 | 1024 | 128 | 8)]:
+        say(f"pairs two-term tb={tb} flags={fl}")
+        p = plan_for(dev, two_term=True, time_blocking=tb)
+        p.set_tiling(4, 10, fl)
+        p.run(3, chunk=50, use_graph=True)
+        a = p.alpha()
+        g = p.gradient(torch.conj(a).resolve_conj().contiguous())
+        res[(tb, fl)] = [p.get_dft(r, 0).cpu().numpy() for r in range(p.n_rhs)] + \
+                        [a.cpu().numpy(), g.cpu().numpy()]
+        p.close()
+    ref = res[(1, 0)]
+    assert np.abs(ref[-1]).max() > 0
+    for k, v in res.items():
+        for x, y in zip(v, ref):
+            assert np.array_equal(x, y), k
