@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--no-realistic", action="store_true",
                     help="multiport: leave out the realistic device's whole gradients")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tiling", default=None,
+                    help="multi-port: rows,zchunk,flags of the step launches instead of the autotuner's")
     ap.add_argument("--eager", action="store_true",
                     help="plain launches instead of HIP-graph replays (for counter collection)")
     ap.add_argument("--workload", choices=("multiport", "batch", "serving", "optimize", "broadband",
@@ -355,11 +357,16 @@ def bench_headline(args):
     plan = plan_for(dev, device="cuda:0", time_blocking=2)
     calibration_copy(torch)
     tuned = None
-    if not args.no_autotune:
-        tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
-        log(f"autotune: rows {tuned['rows']} zchunk {tuned['zchunk']} flags {tuned['flags']} "
-            f"({tuned['ms_per_step']:.3f} ms per step)")
-    tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else (4, 16, 0)
+    if args.tiling:
+        tiling = tuple(int(v) for v in args.tiling.split(","))
+        plan.set_tiling(*tiling)
+        log(f"tiling (given): rows {tiling[0]} zchunk {tiling[1]} flags {tiling[2]}")
+    else:
+        if not args.no_autotune:
+            tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
+            log(f"autotune: rows {tuned['rows']} zchunk {tuned['zchunk']} flags {tuned['flags']} "
+                f"({tuned['ms_per_step']:.3f} ms per step)")
+        tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else (4, 16, 0)
     C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
     state = {"block": 0, "grads": []}
 
