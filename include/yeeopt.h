@@ -314,6 +314,11 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
  *       launches, and is joined back before the second step; advance calls
  *       on the caller's stream still complete in stream order, captured
  *       into a graph as well
+ * 2048  with 512 (else YO_EINVAL): where the two-step region is the whole
+ *       interior (no source or port plane cuts it, as with 128 when the
+ *       planes lie in the shell strips), the z-slabs under it also go two
+ *       steps per launch, with the z-axis CPML code; the shell launch of
+ *       those steps then covers the x- and y-slabs only
  * Other bits: YO_EINVAL.  Results do not depend on the split (bitwise).
  * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);
@@ -376,8 +381,10 @@ yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
  * kernel (cls 0: interior tiles, 1: CPML shell, 2: the two-step region's
  * launch, which advances its cells two steps (its bytes and cell-updates
  * count both; YO_ESTATE unless two steps remain in the run), 3: the interior
- * around it; other values YO_EINVAL; an empty part reports zeros and
- * launches nothing) over the
+ * around it, 4: the two-step launch of the z-slabs under it (tiling flag
+ * 2048; two steps like 2), 5: the CPML shell of the steps that go in pairs
+ * (without the tiles of 4); other values YO_EINVAL; an empty part reports
+ * zeros and launches nothing) over the
  * right-hand sides selected by the last yo_reset, at the current step, with
  * HIP events on `stream`; blocks until done.  The launches re-run the same
  * step (they read the current buffers and do not advance the counter), so
@@ -407,8 +414,8 @@ yo_status yo_adam_step(float *dev_C, const float *dev_G, float *dev_M, float *de
  * yo_run or yo_advance_many (with this plan first in its list) runs its
  * last n_last steps with plain launches and records a pair of HIP events on
  * its stream around each launch of `part` (0 interior tiles, 1 CPML shell,
- * 2 every part, including the two-step region's launches and the interior
- * around it under tiling flag 512); the pairs accumulate over calls until
+ * 2 every part, including the launches of the steps that go in pairs under
+ * tiling flag 512: parts 2 to 5 of yo_time_kernel); the pairs accumulate over calls until
  * the next yo_set_timing with n_last > 0, which clears them.  n_last = 0
  * turns it off and keeps what was recorded.  n_last <= 4096; the events
  * are created as needed (outside graph capture: the timed steps are never
@@ -417,7 +424,8 @@ yo_status yo_adam_step(float *dev_C, const float *dev_G, float *dev_M, float *de
 yo_status yo_set_timing(yo_plan *plan, int part, int n_last);
 
 /* Mean duration of the launches of `part` (0 interior, 1 CPML shell, 2 the
- * two-step region, 3 the interior around it) timed since the last
+ * two-step region, 3 the interior around it, 4 the z-slabs under it, 5 the
+ * CPML shell of steps that go in pairs; see yo_time_kernel) timed since the last
  * yo_set_timing (waits for the last of them); count = how many (0: none,
  * avg_ms = 0). */
 yo_status yo_get_timing(yo_plan *plan, int part, float *avg_ms, int *count);

@@ -11,9 +11,10 @@ re-runs one step without advancing), and keeps the fastest sum.  Results are
 cached in a JSON file keyed by the shape class (architecture, padded x
 extent, ny, nz, number of right-hand sides, CPML width, time blocking), so
 plans of the same class reuse the choice.  For a plan with time blocking it
-also times two steps per launch (the two-step region's launch, the interior
-around it and the shell, each with its own best choice) and keeps that when
-it is faster per step; with two steps per launch chosen, it then times whole
+also times two steps per launch (the two-step region's launch, with flag
+2048 the z-slabs' two-step launch, the interior around them and the shell of
+the paired steps, each with its own best choice) and keeps that when it is
+faster per step; with two steps per launch chosen, it then times whole
 steps with the two-step launch on a second stream beside the first step's
 other launches (flag 1024) against the same launches in one stream, and keeps
 the faster.  Every split gives bitwise the same fields, so tuning only
@@ -41,13 +42,13 @@ SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b) for z in (8, 10, 16, 32) 
                                             for b in (0, 2))
 INTERIOR_FLAGS = (0, 16, 32, 16 | 32)          # cooperative, no prefetch
 # settings swept for two steps per launch (plans with time blocking): z-planes
-# per tile and flags from {1, 128: x-shell cuts as above; 2: 8 waves per
-# block; 256: tiles that meet only the x-slabs run with the single-step
-# interior around the two-step region, with the x-axis CPML code}.  The
-# two-step launch itself barely depends on the z-chunk (its wavefront
-# recomputes two planes below each tile); the shell does.
+# per tile and flags from {1, 128: x-shell cuts as above (with two steps per
+# launch, 128 cuts whole 60-cell two-step strips); 2: 8 waves per block;
+# 2048: the z-slabs under the two-step region take two steps per launch
+# too}.  (Flag 256, the tiles that meet only the x-slabs run with the
+# interior around the two-step region, measured slower and is left out.)
 PAIR_SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b | c) for z in (8, 10, 16) for a in (0, 1, 128)
-                                                 for b in (0, 2) for c in (0, 256))
+                                                 for b in (0, 2) for c in (0, 2048))
 SHELL_FLAGS = tuple(a | b | c for a in (0, 4) for b in (0, 8) for c in (0, 64))
 _lock = threading.Lock()
 
@@ -158,13 +159,16 @@ def tune(plan, which: int = YO_BOTH, shared: Optional[Iterable] = None, n_launch
             t2 = _time(plan, zc2, fl0, 2, which, n_launch, stream)
             if t2 <= 0.0:
                 break               # no two-step region on this grid
+            # the z-slabs' two-step launch (0: none, without 2048 or where
+            # planes cut the region) and the shell of the paired steps
+            t4 = _time(plan, zc2, fl0, 4, which, n_launch, stream)
             tf = {f: _time(plan, zc2, fl0 | f, 3, which, n_launch, stream) for f in (0, 32)}
-            ts = {f: _time(plan, zc2, fl0 | f, 1, which, n_launch, stream) for f in SHELL_FLAGS}
+            ts = {f: _time(plan, zc2, fl0 | f, 5, which, n_launch, stream) for f in SHELL_FLAGS}
             ff = min(tf, key=tf.get)
             fs = min(ts, key=ts.get)
-            per_step = 0.5 * t2 + tf[ff] + ts[fs]
+            per_step = 0.5 * (t2 + t4) + tf[ff] + ts[fs]
             fl = fl0 | ff | fs
-            timings[f"pairs_z{zc2}f{base}"] = dict(two_step=round(t2, 4),
+            timings[f"pairs_z{zc2}f{base}"] = dict(two_step=round(t2, 4), zslab_two_step=round(t4, 4),
                                                    frame={str(k): round(v, 4) for k, v in tf.items()},
                                                    shell={str(k): round(v, 4) for k, v in ts.items()},
                                                    best=fl, ms=round(per_step, 4))

@@ -33,9 +33,11 @@ struct YoRhsD {
     // s is in F[s % nbuf]; nbuf = 3 (a third buffer) when the plan may
     // advance its interior two steps per sweep, else 2 (F[2] null)
     float *F[3];
-    // CPML memories: per axis a, at float offset psi_off[a] of the plan, six
-    // arrays of psi_n[a] floats: E (2 components), Ht step parity 0 (2),
-    // Ht parity 1 (2); each [2 comps] of the axis' slab layout
+    // CPML memories: per axis a, at float offset psi_off[a] of the plan,
+    // arrays of psi_n[a] floats, two components per slot: with nbuf = 2 six
+    // (E one slot, Ht two by step parity), with nbuf = 3 twelve (E three
+    // slots, Ht three, the step's in slot step % 3); each [2 comps] of the
+    // axis' slab layout
     // (x [nz][ny][Wx], y [nz][Wy][nxp], z [Wz][ny][nxp])
     float *psi;
     float2 *dft_box;         // [3][bz][by][bx]
@@ -165,8 +167,9 @@ struct YoChainBufs {
 // rows); prefetch: operands of the next plane loaded during this one
 hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &args, int blocks,
                           hipStream_t s);
-// two steps per sweep over the tiles of the two-step region (independent waves)
-hipError_t yo_launch_step2(const YoStepArgs &args, int blocks, hipStream_t s);
+// two steps per sweep over the tiles of the two-step region (independent
+// waves); zslab: the tiles of the z-slabs under it, with z-axis CPML code
+hipError_t yo_launch_step2(bool zslab, const YoStepArgs &args, int blocks, hipStream_t s);
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);

@@ -94,7 +94,8 @@ enum {
     YO_TILE_XINT = 256,       // tiles inside the x-slabs only run in the interior launch (x CPML code)
     YO_TILE_PAIRS = 512,      // the two-step region advances two steps per sweep (yo_set_time_blocking)
     YO_TILE_OVERLAP = 1024,   // with 512: the two-step launch runs beside the first step's frame and shell
-    YO_TILE_ALL = 2047
+    YO_TILE_ZPAIRS = 2048,    // with 512: the z-slabs under the two-step region take two steps per launch too
+    YO_TILE_ALL = 4095
 };
 
 struct yo_plan {
@@ -155,6 +156,10 @@ struct yo_plan {
     int tsteps = 1, nbuf = 2;
     int r2[6] = {0, 0, 0, 0, 0, 0};
     int n2 = 0, nfr = 0;
+    // YO_TILE_ZPAIRS: the z-slab tiles under R2 ([n_tiles + n2 + nfr, + nz2)),
+    // and the shell's tiles they replace in steps that go in pairs (its last
+    // n_c4 tiles, those of class 4)
+    int nz2 = 0, n_c4 = 0;
     bool bg_set = false, design_set = false;
     double beta = 0;
     int steps_done = 0;
@@ -182,8 +187,8 @@ struct yo_plan {
     // every part); tm_ev[q] holds the event pairs of part q (see part_range)
     // recorded since yo_set_timing (tm_done[q] of them), created as needed
     int tm_part = 0, tm_n = 0;
-    int tm_done[4] = {0, 0, 0, 0};
-    std::vector<hipEvent_t> tm_ev[4];
+    int tm_done[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<hipEvent_t> tm_ev[6];
 };
 
 namespace {
@@ -292,6 +297,27 @@ size_t morph_bytes(const yo_plan *p, size_t n, size_t t)
     return sizeof(float) * (pad((n + 1) * UV) + pad(n * DD) + pad(DD) + pad(2 * DD) + pad(DD) + pad(2 * t));
 }
 
+
+// CPML slabs (per right-hand side): per axis, 2 components per slot, three
+// slots (E one, Ht two) with two state buffers, six (three each) with three;
+// false when they would pass 2 GiB (32-bit buffer offsets).
+static bool set_psi_layout(yo_plan *p)
+{
+    const yo_grid &g = p->grid;
+    const size_t W[3] = {(size_t)p->plo[0] + p->phi[0], (size_t)p->plo[1] + p->phi[1],
+                         (size_t)p->plo[2] + p->phi[2]};
+    const size_t slab[3] = {(size_t)g.nz * g.ny * W[0], (size_t)g.nz * W[1] * p->nxp,
+                            W[2] * g.ny * p->nxp};
+    const size_t arrays = p->nbuf == 3 ? 12 : 6;
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        p->psi_axis_off[a] = off;
+        p->psi_axis_n[a] = slab[a];
+        off += arrays * slab[a];
+    }
+    p->psi_per_rhs = off;
+    return off * sizeof(float) < ((size_t)1 << 31);
+}
 
 // Workspace regions (fields, CPML memories and descriptors per stepped
 // right-hand side; DFT results per output right-hand side).
@@ -546,6 +572,41 @@ void build_pair_tiles(yo_plan *p, const int lo[3], const int hi[3])
         for (int t = 0; t < p->n_int; ++t)
             if (p->tiles_host[t].w == 1) p->tiles_host.push_back(p->tiles_host[t]);
     p->nfr = (int)p->tiles_host.size() - p->n_tiles - p->n2;
+    // YO_TILE_ZPAIRS: when R2 is the whole interior (no plane cuts it, so the
+    // frame is empty and the shell's class-4 tiles are exactly the z-slabs
+    // under R2), those z-slabs go two steps per launch too, in strips of 60
+    // cells, YO_TY rows and at most kc planes
+    bool whole = (p->tflags & YO_TILE_ZPAIRS) && (p->plo[2] > 0 || p->phi[2] > 0);
+    for (int a = 0; a < 3; ++a) whole = whole && r[2 * a] == lo[a] && r[2 * a + 1] == hi[a];
+    if (!whole) return;
+    split_axis(n[0], r[0], r[1], 60, ax, ix);
+    split_axis(n[1], r[2], r[3], YO_TY, ay, iy);
+    az.clear();
+    const int zs[2][2] = {{0, lo[2]}, {hi[2], n[2]}};
+    for (const auto &z : zs) {
+        const int len = z[1] - z[0];
+        if (len <= 0) continue;
+        const int np = (len + p->kc - 1) / p->kc;
+        int st = z[0];
+        for (int q = 0; q < np; ++q) {
+            const int sz = len / np + (q < len % np ? 1 : 0);
+            az.emplace_back(st, sz);
+            st += sz;
+        }
+    }
+    const size_t z2_0 = p->tiles_host.size();
+    for (size_t k = 0; k < az.size(); ++k)
+        for (size_t j = 0; j < ay.size(); ++j)
+            for (size_t i = 0; i < ax.size(); ++i) {
+                if (!(ix[i] && iy[j])) continue;
+                int4 t;
+                t.x = ax[i].first | (ax[i].second << 16);
+                t.y = ay[j].first | (ay[j].second << 16);
+                t.z = az[k].first | ((az[k].first + az[k].second) << 16);
+                t.w = 4;
+                p->tiles_host.push_back(t);
+            }
+    p->nz2 = (int)(p->tiles_host.size() - z2_0);
 }
 
 // Tile table: the interior tiles, then the CPML shell, each in space order
@@ -626,7 +687,13 @@ void build_tiles(yo_plan *p)
     p->n_int = (int)p->tiles_host.size();
     emit(true, (p->tflags & YO_TILE_COOP_SHELL) ? YO_TY * wpb : YO_TY, p->tiles_host);
     p->n_tiles = (int)p->tiles_host.size();
-    p->n2 = p->nfr = 0;
+    p->n2 = p->nfr = p->nz2 = p->n_c4 = 0;
+    if (pr && (p->tflags & YO_TILE_ZPAIRS)) {
+        // the shell's class-4 tiles (z-slabs only) last, in order
+        auto mid = std::stable_partition(p->tiles_host.begin() + p->n_int, p->tiles_host.end(),
+                                         [](const int4 &t) { return t.w != 4; });
+        p->n_c4 = (int)(p->tiles_host.end() - mid);
+    }
     for (int i = 0; i < 6; ++i) p->r2[i] = 0;
     if (p->tsteps == 2 && (p->tflags & YO_TILE_PAIRS)) build_pair_tiles(p, lo, hi);
 }
@@ -792,19 +859,7 @@ yo_status yo_plan_create(const yo_grid *grid, const yo_design *des, int n_steps,
         delete p;
         return fail(YO_EUNSUPPORTED, "one state array (6 components) must stay below 2 GiB");
     }
-    // CPML slabs (per right-hand side): per axis, E 2 comps + H 2 buffers x 2 comps
-    const size_t W[3] = {(size_t)p->plo[0] + p->phi[0], (size_t)p->plo[1] + p->phi[1],
-                         (size_t)p->plo[2] + p->phi[2]};
-    const size_t slab[3] = {(size_t)g.nz * g.ny * W[0], (size_t)g.nz * W[1] * p->nxp,
-                            W[2] * g.ny * p->nxp};
-    size_t off = 0;
-    for (int a = 0; a < 3; ++a) {
-        p->psi_axis_off[a] = off;
-        p->psi_axis_n[a] = slab[a];
-        off += 6 * slab[a];
-    }
-    p->psi_per_rhs = off;
-    if (off * sizeof(float) >= ((size_t)1 << 31)) {
+    if (!set_psi_layout(p)) {
         delete p;
         return fail(YO_EUNSUPPORTED, "the CPML memories of one right-hand side must stay below 2 GiB");
     }
@@ -877,7 +932,7 @@ void yo_plan_destroy(yo_plan *p)
     if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
     if (p->ov_fork) (void)hipEventDestroy(p->ov_fork);
     if (p->ov_join) (void)hipEventDestroy(p->ov_join);
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 6; ++q)
         for (hipEvent_t e : p->tm_ev[q]) (void)hipEventDestroy(e);
     delete p;
 }
@@ -1232,9 +1287,15 @@ yo_status yo_set_time_blocking(yo_plan *p, int steps)
     if (!p) return fail(YO_EINVAL, "null argument");
     if (p->ws) return fail(YO_ESTATE, "set the time blocking before binding a workspace");
     if (steps != 1 && steps != 2) return fail(YO_EINVAL, "steps per sweep must be 1 or 2");
-    p->tsteps = steps;
+    const int nbuf_was = p->nbuf;
     p->nbuf = steps == 2 ? 3 : 2;
-    if (steps == 1) p->tflags &= ~(YO_TILE_PAIRS | YO_TILE_OVERLAP);
+    if (!set_psi_layout(p)) {
+        p->nbuf = nbuf_was;
+        set_psi_layout(p);
+        return fail(YO_EUNSUPPORTED, "the CPML memories of one right-hand side must stay below 2 GiB");
+    }
+    p->tsteps = steps;
+    if (steps == 1) p->tflags &= ~(YO_TILE_PAIRS | YO_TILE_OVERLAP | YO_TILE_ZPAIRS);
     // the two-step and frame tiles can add up to twice the single-step count
     p->tiles_cap = tiles_capacity(p->grid, 4, 4) * (steps == 2 ? 3 : 1);
     build_tiles(p);
@@ -1296,6 +1357,8 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
         return fail(YO_EINVAL, "flag 512 does not combine with flag 16");
     if ((flags & YO_TILE_OVERLAP) && !(flags & YO_TILE_PAIRS))
         return fail(YO_EINVAL, "flag 1024 needs flag 512");
+    if ((flags & YO_TILE_ZPAIRS) && !(flags & YO_TILE_PAIRS))
+        return fail(YO_EINVAL, "flag 2048 needs flag 512");
     p->kc = zchunk;
     p->tflags = flags;
     build_tiles(p);
@@ -1523,14 +1586,18 @@ static void aux_args(yo_plan *const *plans, const int *which, int cnt, bool dft,
 // Fill the step-kernel arguments of tile class `cls` for a plan list;
 // returns the number of blocks (0: no plan has tiles of that class).
 // tiles of launch part `part`: 0 interior, 1 CPML shell, 2 two-step region,
-// 3 the interior around it (single steps)
+// 3 the interior around it (single steps), 4 the z-slabs under the two-step
+// region (two steps, YO_TILE_ZPAIRS), 5 the CPML shell of steps that go in
+// pairs (without the tiles of part 4)
 static void part_range(const yo_plan *p, int part, int &t0, int &t1)
 {
     switch (part) {
     case 0: t0 = 0; t1 = p->n_int; break;
     case 1: t0 = p->n_int; t1 = p->n_tiles; break;
     case 2: t0 = p->n_tiles; t1 = p->n_tiles + p->n2; break;
-    default: t0 = p->n_tiles + p->n2; t1 = t0 + p->nfr; break;
+    case 3: t0 = p->n_tiles + p->n2; t1 = t0 + p->nfr; break;
+    case 4: t0 = p->n_tiles + p->n2 + p->nfr; t1 = t0 + p->nz2; break;
+    default: t0 = p->n_int; t1 = p->n_tiles - (p->nz2 ? p->n_c4 : 0); break;
     }
 }
 
@@ -1541,8 +1608,9 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int part,
     memset(&a, 0, sizeof(YoStepArgs));
     a.n_slots = cnt;
     const int wpb = (plans[0]->tflags & YO_TILE_WPB8) ? 8 : 4;
-    const bool coop = part < 2 &&
-                      (plans[0]->tflags & (part ? YO_TILE_COOP_SHELL : YO_TILE_COOP_INT)) != 0;
+    const int f = plans[0]->tflags;
+    const bool coop = part == 0 ? (f & YO_TILE_COOP_INT) != 0
+                                : (part == 1 || part == 5) && (f & YO_TILE_COOP_SHELL) != 0;
     int tot = 0;
     for (int i = 0; i < cnt; ++i) {
         yo_plan *p = plans[i];
@@ -1572,7 +1640,7 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int part,
 static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, int blocks, hipStream_t s)
 {
     const int f = p0->tflags;
-    if (part == 2) return yo_launch_step2(a, blocks, s);
+    if (part == 2 || part == 4) return yo_launch_step2(part == 4, a, blocks, s);
     if (part == 3)
         return yo_launch_step((f & YO_TILE_XINT) ? 1 : 0, false, !(f & YO_TILE_NOPF_INT), a, blocks, s);
     if (part == 0)
@@ -1605,9 +1673,9 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
     const bool overlap = pairs && (p0->tflags & YO_TILE_OVERLAP) && p0->side_stream;
     for (int base = 0; base < n; base += YO_MAX_SLOTS) {
         const int cnt = std::min(YO_MAX_SLOTS, n - base);
-        static thread_local YoStepArgs A[4];
-        int blocks[4] = {0, 0, 0, 0};
-        for (int part = 0; part < (pairs ? 4 : 2); ++part)
+        static thread_local YoStepArgs A[6];
+        int blocks[6] = {0, 0, 0, 0, 0, 0};
+        for (int part = 0; part < (pairs ? 6 : 2); ++part)
             blocks[part] = step_args(plans + base, which + base, cnt, part, A[part]);
         YoAuxArgs ad, as;
         aux_args(plans + base, which + base, cnt, true, ad);
@@ -1640,18 +1708,20 @@ static yo_status launch_steps(yo_plan *const *plans, const int *which, int n, in
                 HIPCHK(yo_launch_dft(ad, s));
             }
             if (pairs && k + 1 < n_launch) {
+                // the two-step launches (R2, and with YO_TILE_ZPAIRS the
+                // z-slabs under it: part 5 is then the shell without them)
+                hipStream_t s2 = overlap ? p0->side_stream : s;
                 if (overlap) {
                     HIPCHK(hipEventRecord(p0->ov_fork, s));
-                    HIPCHK(hipStreamWaitEvent(p0->side_stream, p0->ov_fork, 0));
-                    if ((st = launch(2, k, p0->side_stream))) return st;
-                    HIPCHK(hipEventRecord(p0->ov_join, p0->side_stream));
-                } else if ((st = launch(2, k, s))) {
-                    return st;
+                    HIPCHK(hipStreamWaitEvent(s2, p0->ov_fork, 0));
                 }
+                if ((st = launch(2, k, s2))) return st;
+                if ((st = launch(4, k, s2))) return st;
+                if (overlap) HIPCHK(hipEventRecord(p0->ov_join, s2));
                 for (int q = 0; q < 2; ++q) {
                     if (q == 1 && overlap) HIPCHK(hipStreamWaitEvent(s, p0->ov_join, 0));
                     if ((st = launch(3, k + q, s))) return st;
-                    if ((st = launch(1, k + q, s))) return st;
+                    if ((st = launch(5, k + q, s))) return st;
                     as.k_offset = k + q;
                     HIPCHK(yo_launch_source(as, s));
                 }
@@ -1997,14 +2067,14 @@ yo_status yo_set_timing(yo_plan *p, int part, int n_last)
     // starting clears what was recorded; stopping (n_last = 0) keeps it for
     // yo_get_timing
     if (n_last > 0)
-        for (int q = 0; q < 4; ++q) p->tm_done[q] = 0;
+        for (int q = 0; q < 6; ++q) p->tm_done[q] = 0;
     return YO_OK;
 }
 
 yo_status yo_get_timing(yo_plan *p, int part, float *avg_ms, int *count)
 {
     if (!p || !avg_ms || !count) return fail(YO_EINVAL, "null argument");
-    if (part < 0 || part > 3) return fail(YO_EINVAL, "part must be 0, 1, 2 or 3");
+    if (part < 0 || part > 5) return fail(YO_EINVAL, "part must be 0 to 5");
     *avg_ms = 0.0f;
     const int n = p->tm_done[part];
     *count = n;
@@ -2026,9 +2096,9 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
 {
     if (!p || !avg_ms || !bytes || !cells) return fail(YO_EINVAL, "null argument");
     if (yo_status st_ = ws_check(p)) return st_;
-    if (cls < 0 || cls > 3 || n_launch < 1) return fail(YO_EINVAL, "bad part or count");
+    if (cls < 0 || cls > 5 || n_launch < 1) return fail(YO_EINVAL, "bad part or count");
     if (!p->active) return fail(YO_ESTATE, "yo_reset first");
-    if (cls == 2 && p->steps_done + 2 > p->n_steps)
+    if ((cls == 2 || cls == 4) && p->steps_done + 2 > p->n_steps)
         return fail(YO_ESTATE, "the two-step launch needs two steps left in the run");
     hipStream_t s = (hipStream_t)stream;
     int r0, r1;
@@ -2059,7 +2129,7 @@ yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, doubl
     const double R = r1 - r0;
     // the two-step launch advances its cells two steps: twice the bytes
     // two one-step sweeps must move
-    const double steps = cls == 2 ? 2.0 : 1.0;
+    const double steps = (cls == 2 || cls == 4) ? 2.0 : 1.0;
     *bytes = steps * (own * (48.0 * R + 12.0) + 32.0 * R * in_pml);
     *cells = steps * own * R;
     if (!blocks || r1 <= r0) {

@@ -123,6 +123,7 @@ struct CpmlCtx {
     int nx, ny, nz, nxp;
     int plo[3], phi[3], W[3];
     int off[3], n[3];        // CPML memory layout (floats), see YoRhsD
+    int qEo, qEn, qHo, qHn;  // memories (first component) read and written this step, E and Ht
     Rsrc ps;                 // this right-hand side's CPML memories
     Cpml cyE, cyH;           // lane l: row j0 - 1 + l
     Cpml czE, czH;           // lane l: plane k0 - 1 + l
@@ -142,8 +143,32 @@ __device__ __forceinline__ Cpml lane_cpml(const Cpml &c, int l)
     return o;
 }
 
-// Byte offsets of CPML memory q (0, 1: E components; 2 + 2 par + c: Ht) of
-// axis A at site (x, j, k): the lane part (voff) and the wave-uniform part
+// CPML memory slots of each axis, as first components (two components per
+// slot): with two state buffers, E one slot (0) read and written in place
+// and Ht two (2, 4) by step parity, since halo rows recompute Ht from the
+// old step's memory while its owner writes the new one; with three state
+// buffers (two steps per launch) three slots each, E at 0, 2, 4 and Ht at
+// 6, 8, 10, the step's memories in slot step % 3: a two-step launch reads
+// slot n % 3 around its cells and writes slot (n + 2) % 3 of its own while
+// single steps write (n + 1) % 3.
+__device__ __forceinline__ void cpml_slots(int nbuf, int step, int &qEo, int &qEn, int &qHo, int &qHn)
+{
+    if (nbuf == 3) {
+        const int s0 = step % 3, s1 = (step + 1) % 3;
+        qEo = 2 * s0;
+        qEn = 2 * s1;
+        qHo = 6 + 2 * s0;
+        qHn = 6 + 2 * s1;
+    } else {
+        const int par = step & 1;
+        qEo = qEn = 0;
+        qHo = 2 + 2 * par;
+        qHn = 2 + 2 * (par ^ 1);
+    }
+}
+
+// Byte offsets of CPML memory q (a slot's first component + c, see
+// cpml_slots) of axis A at site (x, j, k): the lane part (voff) and the wave-uniform part
 // (soff); false when the site is outside the axis' slabs.
 template <int A>
 __device__ __forceinline__ bool psi_at(const CpmlCtx &C, int q, int x, int j, int k, int pxs,
@@ -168,13 +193,13 @@ __device__ __forceinline__ bool psi_at(const CpmlCtx &C, int q, int x, int j, in
 
 // CPML corrections of the six differences of one Ht site row (x = this
 // lane, row j, plane k): each difference inside an absorbing slab of its
-// axis becomes d/kp + psi with psi <- b psi + c d.  Ht's memories are
-// double-buffered by step parity (halo rows recompute Ht, reading psi of
-// the old step); only the owner writes the new value.  PRE: the old values
-// were loaded with the plane's fields (q[axis][component]); else they are
-// loaded here.
+// axis becomes d/kp + psi with psi <- b psi + c d.  Ht's memories are read
+// from one slot and written to another (halo rows recompute Ht, reading psi
+// of the old step); only the owner writes the new value.  PRE: the old
+// values were loaded with the plane's fields (q[axis][component]); else they
+// are loaded here.
 template <int PM, bool PRE>
-__device__ __forceinline__ void h_cpml(const CpmlCtx &C, int par, int x, int j, int k, int pxs,
+__device__ __forceinline__ void h_cpml(const CpmlCtx &C, int x, int j, int k, int pxs,
                                        const Cpml &cxH, bool own, const float (&q)[3][2],
                                        float &dxEz, float &dxEy, float &dyEz, float &dyEx,
                                        float &dzEy, float &dzEx)
@@ -182,7 +207,7 @@ __device__ __forceinline__ void h_cpml(const CpmlCtx &C, int par, int x, int j, 
     const bool xin = (x >= 0) && (x < C.nx);
     const bool jin = (j >= 0) && (j < C.ny);
     if (!(jin && xin && k >= 0)) return;
-    const int qo = 2 + 2 * par, qn = 2 + 2 * (par ^ 1);
+    const int qo = C.qHo, qn = C.qHn;
     int v, s0, s1, t0, t1;
     if ((PM & 1) && psi_at<0>(C, qo, x, j, k, pxs, v, s0)) {
         psi_at<0>(C, qo + 1, x, j, k, pxs, v, s1);
@@ -224,44 +249,52 @@ __device__ __forceinline__ void h_cpml(const CpmlCtx &C, int par, int x, int j, 
     }
 }
 
-// CPML corrections of the six differences of one owned E site (single
-// buffered: each E memory is read and written by its owner only).  PRE as
-// for h_cpml.
+// CPML corrections of the six differences of one owned E site (each E
+// memory is read and written by its owner only: one slot, read and written
+// in place, or with three state buffers the slot of the step read and the
+// next one written).  PRE as for h_cpml.
 template <int PM, bool PRE>
 __device__ __forceinline__ void e_cpml(const CpmlCtx &C, int x, int j, int k, int pxs, const Cpml &cxE,
                                        const float (&q)[3][2], float &dxHz, float &dxHy, float &dyHz,
                                        float &dyHx, float &dzHy, float &dzHx)
 {
-    int v, s0, s1;
-    if ((PM & 1) && psi_at<0>(C, 0, x, j, k, pxs, v, s0)) {
-        psi_at<0>(C, 1, x, j, k, pxs, v, s1);
+    const int qo = C.qEo, qn = C.qEn;
+    int v, s0, s1, t0, t1;
+    if ((PM & 1) && psi_at<0>(C, qo, x, j, k, pxs, v, s0)) {
+        psi_at<0>(C, qo + 1, x, j, k, pxs, v, s1);
         float n0, n1;
         dxHz = pml_diff(dxHz, cxE, PRE ? q[0][0] : bload(C.ps, v, s0), n0);   // Ey
         dxHy = pml_diff(dxHy, cxE, PRE ? q[0][1] : bload(C.ps, v, s1), n1);   // Ez
-        bstore(n0, C.ps, v, s0);
-        bstore(n1, C.ps, v, s1);
+        psi_at<0>(C, qn, x, j, k, pxs, v, t0);
+        psi_at<0>(C, qn + 1, x, j, k, pxs, v, t1);
+        bstore(n0, C.ps, v, t0);
+        bstore(n1, C.ps, v, t1);
     }
-    if ((PM & 2) && psi_at<1>(C, 0, x, j, k, pxs, v, s0)) {
-        psi_at<1>(C, 1, x, j, k, pxs, v, s1);
+    if ((PM & 2) && psi_at<1>(C, qo, x, j, k, pxs, v, s0)) {
+        psi_at<1>(C, qo + 1, x, j, k, pxs, v, s1);
         const Cpml cy = lane_cpml(C.cyE, j - C.j0m);
         float n0, n1;
         dyHz = pml_diff(dyHz, cy, PRE ? q[1][0] : bload(C.ps, v, s0), n0);   // Ex
         dyHx = pml_diff(dyHx, cy, PRE ? q[1][1] : bload(C.ps, v, s1), n1);   // Ez
-        bstore(n0, C.ps, v, s0);
-        bstore(n1, C.ps, v, s1);
+        psi_at<1>(C, qn, x, j, k, pxs, v, t0);
+        psi_at<1>(C, qn + 1, x, j, k, pxs, v, t1);
+        bstore(n0, C.ps, v, t0);
+        bstore(n1, C.ps, v, t1);
     }
-    if ((PM & 4) && psi_at<2>(C, 0, x, j, k, pxs, v, s0)) {
-        psi_at<2>(C, 1, x, j, k, pxs, v, s1);
+    if ((PM & 4) && psi_at<2>(C, qo, x, j, k, pxs, v, s0)) {
+        psi_at<2>(C, qo + 1, x, j, k, pxs, v, s1);
         const Cpml cz = lane_cpml(C.czE, k - C.k0m);
         float n0, n1;
         dzHy = pml_diff(dzHy, cz, PRE ? q[2][0] : bload(C.ps, v, s0), n0);   // Ex
         dzHx = pml_diff(dzHx, cz, PRE ? q[2][1] : bload(C.ps, v, s1), n1);   // Ey
-        bstore(n0, C.ps, v, s0);
-        bstore(n1, C.ps, v, s1);
+        psi_at<2>(C, qn, x, j, k, pxs, v, t0);
+        psi_at<2>(C, qn + 1, x, j, k, pxs, v, t1);
+        bstore(n0, C.ps, v, t0);
+        bstore(n1, C.ps, v, t1);
     }
 }
 
-// Old CPML memories q (0, 1: E; 2 + 2 par + c: Ht) of every axis in PM at one
+// Old CPML memories q (a slot's first component, see cpml_slots) of every axis in PM at one
 // site, or 0 where `use` is false or the site is outside the slab (such a
 // lane's offset is past the buffer, so the load moves no data and the
 // loads need no branch).
@@ -319,7 +352,6 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
     const int rows = ny + 2;
     const size_t groups = (size_t)(nz + 2) * rows;           // row groups (j, k)
     const int rowb = nxp * (int)sizeof(float);                // one component row, bytes
-    const int par = step & 1;
     // state: 6 component rows per group (E then Ht); kappa: 3
     const Rsrc Fo = rsrc_of(R.F[step % P.nbuf], 6 * groups * nxp);
     const Rsrc Fn = rsrc_of(R.F[(step + 1) % P.nbuf], 6 * groups * nxp);
@@ -375,6 +407,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             C.n[a] = P.psi_n[a];
         }
         C.ps = rsrc_of(R.psi, (size_t)P.psi_total);
+        cpml_slots(P.nbuf, step, C.qEo, C.qEn, C.qHo, C.qHn);
         C.j0m = j0 - 1;
         C.k0m = k0 - 1;
         const Cpml one = {1.0f, 0.0f, 1.0f};
@@ -487,12 +520,12 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             for (int r = 0; r <= TY; ++r) {
                 const int j = j0 - 1 + r;
                 const bool use = (r > 0 || bottom) && xin && lane_used && kin && j >= 0 && j < ny;
-                psi_preload<PM>(C, 2 + 2 * par, x, j, k, pxs, use, qH[r]);
+                psi_preload<PM>(C, C.qHo, x, j, k, pxs, use, qH[r]);
             }
 #pragma unroll
             for (int r = 1; r <= TY; ++r) {
                 const bool use = own_x && k >= k0 && r <= jn;
-                psi_preload<PM>(C, 0, x, j0 - 1 + r, k, pxs, use, qE[r - 1]);
+                psi_preload<PM>(C, C.qEo, x, j0 - 1 + r, k, pxs, use, qE[r - 1]);
             }
         }
         const int pp = k & 1;
@@ -517,7 +550,7 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
             float dyEx = Ec[0][r + 1] - Ec[0][r];
             const bool own = own_x && own_k && (r >= 1) && (r <= jn);
             if (PM)
-                h_cpml<PM, PRE>(C, par, lane_used ? x : -1, j, k, pxs, cxH, own, qH[r], dxEz, dxEy,
+                h_cpml<PM, PRE>(C, lane_used ? x : -1, j, k, pxs, cxH, own, qH[r], dxEz, dxEy,
                                 dyEz, dyEx, dzEy, dzEx);
             const float hx = Ho_[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
             const float hy = Ho_[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
@@ -687,7 +720,14 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
 // (buffer (n+1) % 3): the single steps of the tiles around R2 read it.
 // Every value is computed with the expression and the operand order of the
 // single-step kernel, so the two paths give bitwise the same fields.
-template <int TY>
+// ZP: the tiles of the z-slabs under R2's x-y footprint (planes down to 0 and
+// up to nz - 1), with the z-axis CPML code of the single-step kernel: a wave
+// reads the memories of slot n % 3 around its cells, keeps step n+1's new
+// ones in registers for the second step, and writes slot (n+2) % 3 of its own
+// cells and, for R2's outermost layer, the Ht memories of step n+1 (slot
+// (n+1) % 3), which the single steps around read.  Planes past the grid are
+// the perfect conductor's zeros.
+template <int TY, bool ZP>
 __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, const int step,
                                            const int4 t, const int lane)
 {
@@ -712,6 +752,15 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
     // R2's outermost layer, whose step-n+1 state the tiles around R2 read
     const int ra0 = P.r2[0], ra1 = P.r2[1], rb0 = P.r2[2], rb1 = P.r2[3], rc0 = P.r2[4], rc1 = P.r2[5];
     const bool rim_x = own_x && (x == ra0 || x == ra1 - 1);
+    // z-axis CPML memories (ZP): slots as in cpml_slots, byte offsets of
+    // component c of slot q at row j of slab plane pz
+    const int nz = P.nz, zlo = P.plo[2], zhi = P.phi[2];
+    const Rsrc PS = rsrc_of(R.psi, (size_t)P.psi_total);
+    const int s0 = step % 3, s1 = (step + 1) % 3, s2 = (step + 2) % 3;
+    const int xv = clampi(x, 0, nx - 1) * (int)sizeof(float);
+    auto zo = [&](int q, int pz, int j) -> int {
+        return (P.psi_off[2] + q * P.psi_n[2] + (pz * ny + j) * nxp) * (int)sizeof(float);
+    };
     auto ro = [&](int j, int k) -> int {
         return ((k + 1) * rows + (clampi(j, -1, ny) + 1)) * 6 * rowb;
     };
@@ -727,8 +776,20 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
     float Kc[3][NH], Kp[3][NH];    // kappa at planes k and k-1 (rows 1..TY+2)
     float E1c[3][NH], E1p[3][NH];  // E^{n+1} at planes k and k-1 (rows 1..TY+2)
     float H2[3][NH], H2p[2][NH];   // Ht^{n+3/2} at planes k-1 and k-2 (rows 1..TY+1)
+    // ZP: z memories of step n+1 (Ht rows 0..TY+2, E rows 1..TY+2) at
+    // planes k and k-1, with the planes' coefficients
+    float qH1[2][NH], qH1p[2][NH], qE1[2][NH], qE1p[2][NH];
+    Cpml czH = {1.0f, 0.0f, 1.0f}, czE = czH, czHp = czH, czEp = czH;
+    int pzp = -1;
 
     auto load_e = [&](int k, float (&e)[3][NE]) {
+        if (ZP && (k < -1 || k > nz)) {   // past the ghost planes
+#pragma unroll
+            for (int r = 0; r < NE; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) e[c][r] = 0.0f;
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < NE; ++r) {
             const int o = ro(j0 - 2 + r, k);
@@ -745,15 +806,32 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
 #pragma unroll
         for (int r = 0; r < NH; ++r) Hhp[c][r] = E1p[c][r] = Kp[c][r] = H2[c][r] = 0.0f;
 #pragma unroll
-    for (int r = 0; r < NH; ++r) H2p[0][r] = H2p[1][r] = 0.0f;
+    for (int r = 0; r < NH; ++r) {
+        H2p[0][r] = H2p[1][r] = 0.0f;
+        qH1[0][r] = qH1[1][r] = qE1[0][r] = qE1[1][r] = 0.0f;
+    }
 
     for (int k = k0 - 2; k <= k1; ++k) {
         load_e(k + 1, Enx);
+        if (ZP && k < -1) {
 #pragma unroll
-        for (int r = 0; r < NH; ++r) {
-            const int o = ro(j0 - 2 + r, k);
+            for (int r = 0; r < NH; ++r)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Ho[c][r] = bload(FA, xo, hb + c * rowb + o);
+                for (int c = 0; c < 3; ++c) Ho[c][r] = 0.0f;
+        } else {
+#pragma unroll
+            for (int r = 0; r < NH; ++r) {
+                const int o = ro(j0 - 2 + r, k);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Ho[c][r] = bload(FA, xo, hb + c * rowb + o);
+            }
+        }
+        // ZP: plane k's z coefficients (its memories of step n, slot n % 3,
+        // are loaded where used)
+        const int pz = ZP ? slab_index(k, nz, zlo, zhi) : -1;
+        if (ZP && pz >= 0) {
+            czH = cpml_at(P.prof[2], nz, 3, k);
+            czE = cpml_at(P.prof[2], nz, 0, k);
         }
         const bool do_e1 = k >= k0 - 1;
         if (do_e1) {
@@ -775,9 +853,16 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
             const float dxEz = ez_i1 - Ec[2][r];
             const float dxEy = ey_i1 - Ec[1][r];
             const float dyEx = Ec[0][r + 1] - Ec[0][r];
-            Hh[0][r] = Ho[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
-            Hh[1][r] = Ho[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
+            float dzEy_ = dzEy, dzEx_ = dzEx;
+            if (ZP && pz >= 0) {
+                const int o = zo(6 + 2 * s0, pz, j0 - 2 + r);
+                dzEy_ = pml_diff(dzEy, czH, bload(PS, xv, o), qH1[0][r]);                       // Hx
+                dzEx_ = pml_diff(dzEx, czH, bload(PS, xv, o + P.psi_n[2] * 4), qH1[1][r]);   // Hy
+            }
+            Hh[0][r] = Ho[0][r] - fmaf(sy, dyEz, -(sz * dzEy_));
+            Hh[1][r] = Ho[1][r] - fmaf(sz, dzEx_, -(sx * dxEz));
             Hh[2][r] = Ho[2][r] - fmaf(sx, dxEy, -(sy * dyEx));
+            if (ZP && k < 0) Hh[0][r] = Hh[1][r] = Hh[2][r] = 0.0f;   // ghost plane
         }
         if (do_e1) {
             // ---- step n+1's E at plane k, rows 1..TY+2 ----
@@ -794,12 +879,19 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
                 const float dxHz = Hh[2][r] - hz_im;
                 const float dxHy = Hh[1][r] - hy_im;
                 const float dyHx = Hh[0][r] - Hh[0][r - 1];
-                float ex = fmaf(Kc[0][r], fmaf(sy, dyHz, -(sz * dzHy)), Ec[0][r]);
-                float ey = fmaf(Kc[1][r], fmaf(sz, dzHx, -(sx * dxHz)), Ec[1][r]);
+                float dzHy_ = dzHy, dzHx_ = dzHx;
+                if (ZP && pz >= 0) {
+                    const int o = zo(2 * s0, pz, j);
+                    dzHy_ = pml_diff(dzHy, czE, bload(PS, xv, o), qE1[0][r]);                       // Ex
+                    dzHx_ = pml_diff(dzHx, czE, bload(PS, xv, o + P.psi_n[2] * 4), qE1[1][r]);   // Ey
+                }
+                float ex = fmaf(Kc[0][r], fmaf(sy, dyHz, -(sz * dzHy_)), Ec[0][r]);
+                float ey = fmaf(Kc[1][r], fmaf(sz, dzHx_, -(sx * dxHz)), Ec[1][r]);
                 float ez = fmaf(Kc[2][r], fmaf(sx, dxHy, -(sy * dyHx)), Ec[2][r]);
                 ex = (j == 0 || k == 0) ? 0.0f : ex;
                 ey = (x == 0 || k == 0) ? 0.0f : ey;
                 ez = (x == 0 || j == 0) ? 0.0f : ez;
+                if (ZP && (k < 0 || k >= nz)) ex = ey = ez = 0.0f;   // ghost planes stay zero
                 E1c[0][r] = ex;
                 E1c[1][r] = ey;
                 E1c[2][r] = ez;
@@ -813,6 +905,10 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
                     bstore_nt(Hh[0][r], FB, xo, hb + o);
                     bstore_nt(Hh[1][r], FB, xo, hb + rowb + o);
                     bstore_nt(Hh[2][r], FB, xo, hb + 2 * rowb + o);
+                    if (ZP && pz >= 0) {
+                        bstore(qH1[0][r], PS, xv, zo(6 + 2 * s1, pz, j));
+                        bstore(qH1[1][r], PS, xv, zo(6 + 2 * s1 + 1, pz, j));
+                    }
                 }
             }
         }
@@ -829,9 +925,21 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
                 const float dxEz = ez_i1 - E1p[2][r];
                 const float dxEy = ey_i1 - E1p[1][r];
                 const float dyEx = E1p[0][r + 1] - E1p[0][r];
-                H2[0][r] = Hhp[0][r] - fmaf(sy, dyEz, -(sz * dzEy));
-                H2[1][r] = Hhp[1][r] - fmaf(sz, dzEx, -(sx * dxEz));
+                float dzEy_ = dzEy, dzEx_ = dzEx;
+                if (ZP && pzp >= 0) {
+                    float n0, n1;
+                    dzEy_ = pml_diff(dzEy, czHp, qH1p[0][r], n0);   // Hx
+                    dzEx_ = pml_diff(dzEx, czHp, qH1p[1][r], n1);   // Hy
+                    if (own_x && r >= 2 && r - 2 < jn && km >= k0 && km < k1) {
+                        const int j = j0 - 2 + r;
+                        bstore(n0, PS, xv, zo(6 + 2 * s2, pzp, j));
+                        bstore(n1, PS, xv, zo(6 + 2 * s2 + 1, pzp, j));
+                    }
+                }
+                H2[0][r] = Hhp[0][r] - fmaf(sy, dyEz, -(sz * dzEy_));
+                H2[1][r] = Hhp[1][r] - fmaf(sz, dzEx_, -(sx * dxEz));
                 H2[2][r] = Hhp[2][r] - fmaf(sx, dxEy, -(sy * dyEx));
+                if (ZP && km < 0) H2[0][r] = H2[1][r] = H2[2][r] = 0.0f;   // ghost plane
             }
             if (km >= k0) {
 #pragma unroll
@@ -846,8 +954,18 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
                     const float dxHz = H2[2][r] - hz_im;
                     const float dxHy = H2[1][r] - hy_im;
                     const float dyHx = H2[0][r] - H2[0][r - 1];
-                    float ex = fmaf(Kp[0][r], fmaf(sy, dyHz, -(sz * dzHy)), E1p[0][r]);
-                    float ey = fmaf(Kp[1][r], fmaf(sz, dzHx, -(sx * dxHz)), E1p[1][r]);
+                    float dzHy_ = dzHy, dzHx_ = dzHx;
+                    if (ZP && pzp >= 0) {
+                        float n0, n1;
+                        dzHy_ = pml_diff(dzHy, czEp, qE1p[0][r], n0);   // Ex
+                        dzHx_ = pml_diff(dzHx, czEp, qE1p[1][r], n1);   // Ey
+                        if (own_x) {
+                            bstore(n0, PS, xv, zo(2 * s2, pzp, j));
+                            bstore(n1, PS, xv, zo(2 * s2 + 1, pzp, j));
+                        }
+                    }
+                    float ex = fmaf(Kp[0][r], fmaf(sy, dyHz, -(sz * dzHy_)), E1p[0][r]);
+                    float ey = fmaf(Kp[1][r], fmaf(sz, dzHx_, -(sx * dxHz)), E1p[1][r]);
                     float ez = fmaf(Kp[2][r], fmaf(sx, dxHy, -(sy * dyHx)), E1p[2][r]);
                     ex = (j == 0 || km == 0) ? 0.0f : ex;
                     ey = (x == 0 || km == 0) ? 0.0f : ey;
@@ -880,9 +998,22 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
                 Kp[c][r] = Kc[c][r];
             }
         }
+        if (ZP) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < NH; ++r) {
+                    qH1p[c][r] = qH1[c][r];
+                    qE1p[c][r] = qE1[c][r];
+                }
+            czHp = czH;
+            czEp = czE;
+            pzp = pz;
+        }
     }
 }
 
+template <bool ZP>
 __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step2(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -905,7 +1036,7 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step2(const YoStepArgs 
     const int r = sl.rhs0 + in_grp / wpb;
     const int ti = grp * wpb + in_grp % wpb;
     if (ti >= sl.ntile) return;
-    wave_step2<YO_TY>(P, P.rhs[r], step, sl.tiles[ti], lane);
+    wave_step2<YO_TY, ZP>(P, P.rhs[r], step, sl.tiles[ti], lane);
 }
 
 // locate point q of slot s in the aux work list
@@ -1062,11 +1193,14 @@ hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &ar
     return hipGetLastError();
 }
 
-hipError_t yo_launch_step2(const YoStepArgs &args, int blocks, hipStream_t s)
+hipError_t yo_launch_step2(bool zslab, const YoStepArgs &args, int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_yee_step2, dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+    if (zslab)
+        hipLaunchKernelGGL(k_yee_step2<true>, dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+    else
+        hipLaunchKernelGGL(k_yee_step2<false>, dim3(blocks), dim3(64 * args.wpb), 0, s, args);
     return hipGetLastError();
 }
 

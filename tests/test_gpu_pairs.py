@@ -58,7 +58,8 @@ def test_pairs_bitwise_equal_single_steps_with_cpml_and_source(steps):
                               (2, 10, 512 | 1 | 64 | 8, True), (2, 10, 512 | 128, False),
                               (2, 4, 512 | 32, True), (2, 10, 512 | 256 | 1 | 64, True),
                               (2, 8, 512 | 256 | 128 | 2, False), (2, 10, 512 | 1024 | 1 | 8, True),
-                              (2, 8, 512 | 1024 | 128, False)]:
+                              (2, 8, 512 | 1024 | 128, False), (2, 10, 512 | 2048 | 128 | 8, True),
+                              (2, 4, 512 | 2048 | 128, False), (2, 16, 512 | 2048 | 1024 | 128 | 2, True)]:
         say(f"pairs box steps={steps} tb={tb} tiling=(4,{zc},{fl}) graph={graph}")
         p = _box_plan(steps, tb)
         p.set_tiling(4, zc, fl)
@@ -75,7 +76,10 @@ def test_pairs_bitwise_equal_single_steps_with_cpml_and_source(steps):
 
 
 def test_two_step_region_is_used():
-    """The two-step launch has tiles (the region is not empty) and times."""
+    """The two-step launch has tiles (the region is not empty) and times;
+    with flag 2048 (and the two-step strips cut clear of the source plane by
+    flag 128) the z-slabs under it take two steps too, and the pair-step
+    shell launch holds the rest of the shell."""
     p = _box_plan(100, 2)
     p.set_tiling(4, 16, 512)
     p.reset(1)
@@ -84,6 +88,17 @@ def test_two_step_region_is_used():
     ms3, b3, c3 = p.time_kernel(3, 2)
     say(f"two-step launch {ms:.4f} ms for {c:.0f} cell-updates; frame {ms3:.4f} ms, {c3:.0f}")
     assert c > 0 and ms > 0 and c3 > 0
+    assert p.time_kernel(4, 1)[2] == 0.0
+    p.set_tiling(4, 16, 512 | 2048 | 128)
+    p.reset(1)
+    p.advance(1, 4)
+    c1 = p.time_kernel(1, 1)[2]
+    ms4, b4, c4 = p.time_kernel(4, 2)
+    ms5, b5, c5 = p.time_kernel(5, 2)
+    say(f"z-slab two-step launch {ms4:.4f} ms for {c4:.0f}; pair-step shell {ms5:.4f} ms, {c5:.0f}")
+    assert c4 > 0 and ms4 > 0 and c5 > 0
+    assert c4 / 2 + c5 == pytest.approx(c1)       # the z-slabs' cells move from the shell
+    assert p.time_kernel(3, 1)[2] == 0.0           # R2 is the whole interior: no frame
     p.close()
 
 
@@ -95,7 +110,7 @@ def test_pairs_bitwise_equal_with_window_and_several_wavelengths():
     dev = configs.micro(n_steps=400, nx=150, ny=40, nz=30, md=10, nd=10, mc=5, nc=5,
                         wavelengths=[0.78e-6, 0.8e-6, 0.82e-6])
     res = {}
-    for tb, fl in [(1, 0), (2, 512), (2, 512 | 73), (2, 512 | 1024 | 73)]:
+    for tb, fl in [(1, 0), (2, 512), (2, 512 | 73), (2, 512 | 1024 | 73), (2, 512 | 2048 | 128 | 8)]:
         say(f"pairs micro tb={tb} flags={fl}")
         p = plan_for(dev, time_blocking=tb)
         p.set_tiling(4, 10, fl)
@@ -118,7 +133,7 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
     from paper_2505_03352_amd.plan import advance_many, plan_for
     devs = [configs.micro_demux(n_steps=2600), configs.micro(n_steps=1300, nx=90, ny=34, nz=24)]
     res = {}
-    for tb, fl in ((1, 0), (2, 512), (2, 512 | 1024)):
+    for tb, fl in ((1, 0), (2, 512), (2, 512 | 1024), (2, 512 | 2048 | 128)):
         say(f"pairs pulse + shared launches tb={tb} flags={fl}")
         plans = []
         for d in devs:
@@ -136,7 +151,7 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
             out += [p.get_dft(r, 0).cpu().numpy() for r in range(p.n_rhs)] + [a.cpu().numpy()]
             p.close()
         res[fl] = out
-    for fl in (512, 512 | 1024):
+    for fl in (512, 512 | 1024, 512 | 2048 | 128):
         for x, y in zip(res[fl], res[0]):
             assert np.array_equal(x, y), fl
 
@@ -185,7 +200,7 @@ def test_pairs_bitwise_equal_with_two_term_ports():
     from paper_2505_03352_amd.plan import plan_for
     dev = configs.micro(n_steps=400, nx=150, ny=40, nz=30, md=10, nd=10, mc=5, nc=5)
     res = {}
-    for tb, fl in [(1, 0), (2, 512 | 128), (2, 512 | 73), (2, 512 | 1024 | 128 | 8)]:
+    for tb, fl in [(1, 0), (2, 512 | 128), (2, 512 | 73), (2, 512 | 1024 | 128 | 8), (2, 512 | 2048 | 128)]:
         say(f"pairs two-term tb={tb} flags={fl}")
         p = plan_for(dev, two_term=True, time_blocking=tb)
         p.set_tiling(4, 10, fl)
