@@ -31,7 +31,7 @@ METRIC = "Gcell-updates/s + % HBM peak; adjoint gradients/hour; p50/p99 solve la
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2505_03352_amd/csrc/yo_step.hip", "paper_2505_03352_amd/csrc/yo_internal.h"]
 PROFILES = os.path.join(ROOT, "profiles")
-PART_NAMES = ("interior", "shell", "two_step", "frame")
+PART_NAMES = ("interior", "shell", "two_step", "frame", "zslab_two_step", "shell_paired")
 
 
 def log(*a):
@@ -51,14 +51,17 @@ def kernel_sha() -> str:
 # blocks, no interior prefetch), the CPML shell (the x-shell layouts, 8 waves
 # per block, cooperative shell blocks, per-class code, no shell prefetch),
 # the two-step launch (x-shell layouts, 8 waves per block) and the interior
-# around it (the same and no prefetch); 512 (two steps per launch) in all
-SPLIT_BITS = (1 | 2 | 16 | 32 | 128 | 256 | 512, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512,
-              1 | 2 | 128 | 256 | 512, 1 | 2 | 32 | 128 | 256 | 512)
+# around it (the same and no prefetch), the z-slabs' two-step launch and the
+# shell of paired steps (2048 decides which tiles each holds); 512 (two
+# steps per launch) in all
+SPLIT_BITS = (1 | 2 | 16 | 32 | 128 | 256 | 512, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512 | 2048,
+              1 | 2 | 128 | 256 | 512, 1 | 2 | 32 | 128 | 256 | 512,
+              1 | 2 | 128 | 256 | 512 | 2048, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512 | 2048)
 
 
 def part_split(tiling, part: int) -> str:
     """rows,z-chunk,flag bits of a (rows, zchunk, flags) tiling that shape
-    launch `part` (0 interior, 1 CPML shell)."""
+    launch `part` (see PART_NAMES)."""
     rows, zc, flags = tiling
     return f"{rows},{zc},{flags & SPLIT_BITS[part]}"
 
@@ -172,6 +175,8 @@ def main():
     ap.add_argument("--no-realistic", action="store_true",
                     help="multiport: leave out the realistic device's whole gradients")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="multi-port and realistic: sweep the splits instead of applying the shipped ones")
     ap.add_argument("--tiling", default=None,
                     help="multi-port: rows,zchunk,flags of the step launches instead of the autotuner's")
     ap.add_argument("--eager", action="store_true",
@@ -242,7 +247,9 @@ def calibration_copy(torch):
 
 KERNEL_OF_PART = ("k_yee_step interior tiles", "k_yee_step CPML shell tiles",
                   "k_yee_step2 two-step region (two steps per launch)",
-                  "k_yee_step interior tiles around the two-step region")
+                  "k_yee_step interior tiles around the two-step region",
+                  "k_yee_step2 z-slabs under the two-step region (two steps per launch)",
+                  "k_yee_step CPML shell tiles of the steps in pairs")
 
 
 def part_rooflines(plan, timed, tiling, workload, sha):
@@ -286,7 +293,7 @@ def realistic_gradients(args, torch, n_timed=1):
     from workloads import configs
     dev = configs.realistic()
     plan = plan_for(dev, device="cuda:0", time_blocking=2)
-    tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
+    tuned = autotune.tune(plan, YO_BOTH, use_cache=False, shipped=not args.retune)
     tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"])
     C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
 
@@ -318,7 +325,7 @@ def realistic_gradients(args, torch, n_timed=1):
         grad(True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / n_timed
-    timed = [plan.timing(q) for q in range(4)]
+    timed = [plan.timing(q) for q in range(6)]
     plan.set_timing(0, 0)
     plan.reset(YO_BOTH)
     plan.advance(YO_BOTH, 4)
@@ -363,9 +370,9 @@ def bench_headline(args):
         log(f"tiling (given): rows {tiling[0]} zchunk {tiling[1]} flags {tiling[2]}")
     else:
         if not args.no_autotune:
-            tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
-            log(f"autotune: rows {tuned['rows']} zchunk {tuned['zchunk']} flags {tuned['flags']} "
-                f"({tuned['ms_per_step']:.3f} ms per step)")
+            tuned = autotune.tune(plan, YO_BOTH, use_cache=False, shipped=not args.retune)
+            log(f"autotune{' (shipped split)' if tuned.get('shipped') else ''}: rows {tuned['rows']} "
+                f"zchunk {tuned['zchunk']} flags {tuned['flags']} ({tuned['ms_per_step']:.3f} ms per step)")
         tiling = (tuned["rows"], tuned["zchunk"], tuned["flags"]) if tuned else (4, 16, 0)
     C = torch.as_tensor(dev.C, dtype=torch.float32, device="cuda:0")
     state = {"block": 0, "grads": []}
@@ -412,7 +419,7 @@ def bench_headline(args):
         bench_step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    timed = [plan.timing(q) for q in range(4)]
+    timed = [plan.timing(q) for q in range(6)]
     plan.set_timing(0, 0)
     ms = (t1 - t0) / args.steps * 1e3
     cells_per_step = plan.n_rhs * dev.cells * block

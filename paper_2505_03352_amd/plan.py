@@ -277,8 +277,9 @@ class Plan:
     def time_kernel(self, cls: int = 0, n_launch: int = 20, stream=None):
         """(avg ms per launch, algorithmic bytes per launch, cell-updates per
         launch) of one part of the time-stepping kernel (0: interior tiles,
-        1: CPML shell), by HIP events on the stream.  An empty part gives
-        zeros."""
+        1: CPML shell, 2: the two-step region, 3: the interior around it, 4:
+        the z-slabs under it, 5: the shell of paired steps), by HIP events on
+        the stream.  An empty part gives zeros."""
         ms, b, c = ct.c_float(), ct.c_double(), ct.c_double()
         call("yo_time_kernel", self._h, int(cls), int(n_launch), ct.byref(ms), ct.byref(b),
              ct.byref(c), _stream(stream))
@@ -298,8 +299,8 @@ class Plan:
         call("yo_set_timing", self._h, int(part), int(n_last))
 
     def timing(self, part: int = 0):
-        """(mean ms per timed launch, launches timed) of part 0 or 1 since the
-        last set_timing."""
+        """(mean ms per timed launch, launches timed) of launch part `part`
+        (0 to 5, see time_kernel) since the last set_timing."""
         ms, n = ct.c_float(), ct.c_int()
         call("yo_get_timing", self._h, int(part), ct.byref(ms), ct.byref(n))
         return float(ms.value), int(n.value)
