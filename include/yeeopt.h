@@ -319,6 +319,8 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
  *       planes lie in the shell strips), the z-slabs under it also go two
  *       steps per launch, with the z-axis CPML code; the shell launch of
  *       those steps then covers the x- and y-slabs only
+ * 4096  with 512 (else YO_EINVAL): the two-step region's tiles have 6 rows
+ *       instead of 4 (fewer halo rows re-read, fewer waves per SIMD)
  * Other bits: YO_EINVAL.  Results do not depend on the split (bitwise).
  * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);

@@ -10,6 +10,7 @@
 #define YO_MAX_SLOTS 32
 #define YO_TX 62          // owned x-cells per wave (lanes 1..62; lanes 0 and 63 are halo)
 #define YO_TY 4           // rows per wave
+#define YO_TY2 6          // rows per wave of the two-step region's taller tiles
 #define YO_MAX_WPB 8      // waves per block of the step kernel: 4 or 8
 
 // Field arrays carry one ghost layer on every face and keep the components
@@ -168,8 +169,9 @@ struct YoChainBufs {
 hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &args, int blocks,
                           hipStream_t s);
 // two steps per sweep over the tiles of the two-step region (independent
-// waves); zslab: the tiles of the z-slabs under it, with z-axis CPML code
-hipError_t yo_launch_step2(bool zslab, const YoStepArgs &args, int blocks, hipStream_t s);
+// waves); zslab: the tiles of the z-slabs under it, with z-axis CPML code;
+// rows: rows per tile, YO_TY, or YO_TY2 for the region itself
+hipError_t yo_launch_step2(bool zslab, int rows, const YoStepArgs &args, int blocks, hipStream_t s);
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);

@@ -95,7 +95,8 @@ enum {
     YO_TILE_PAIRS = 512,      // the two-step region advances two steps per sweep (yo_set_time_blocking)
     YO_TILE_OVERLAP = 1024,   // with 512: the two-step launch runs beside the first step's frame and shell
     YO_TILE_ZPAIRS = 2048,    // with 512: the z-slabs under the two-step region take two steps per launch too
-    YO_TILE_ALL = 4095
+    YO_TILE_PAIR6 = 4096,     // with 512: the two-step region's tiles have YO_TY2 rows (else YO_TY)
+    YO_TILE_ALL = 8191
 };
 
 struct yo_plan {
@@ -519,7 +520,7 @@ void build_pair_tiles(yo_plan *p, const int lo[3], const int hi[3])
     std::vector<std::pair<int, int>> ax, ay, az;
     std::vector<char> ix, iy, iz;
     split_axis(n[0], r[0], r[1], 60, ax, ix);
-    split_axis(n[1], r[2], r[3], YO_TY, ay, iy);
+    split_axis(n[1], r[2], r[3], (p->tflags & YO_TILE_PAIR6) ? YO_TY2 : YO_TY, ay, iy);
     split_axis(n[2], r[4], r[5], p->kc, az, iz);
     for (size_t k = 0; k < az.size(); ++k)
         for (size_t j = 0; j < ay.size(); ++j)
@@ -1295,7 +1296,7 @@ yo_status yo_set_time_blocking(yo_plan *p, int steps)
         return fail(YO_EUNSUPPORTED, "the CPML memories of one right-hand side must stay below 2 GiB");
     }
     p->tsteps = steps;
-    if (steps == 1) p->tflags &= ~(YO_TILE_PAIRS | YO_TILE_OVERLAP | YO_TILE_ZPAIRS);
+    if (steps == 1) p->tflags &= ~(YO_TILE_PAIRS | YO_TILE_OVERLAP | YO_TILE_ZPAIRS | YO_TILE_PAIR6);
     // the two-step and frame tiles can add up to twice the single-step count
     p->tiles_cap = tiles_capacity(p->grid, 4, 4) * (steps == 2 ? 3 : 1);
     build_tiles(p);
@@ -1359,6 +1360,8 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
         return fail(YO_EINVAL, "flag 1024 needs flag 512");
     if ((flags & YO_TILE_ZPAIRS) && !(flags & YO_TILE_PAIRS))
         return fail(YO_EINVAL, "flag 2048 needs flag 512");
+    if ((flags & YO_TILE_PAIR6) && !(flags & YO_TILE_PAIRS))
+        return fail(YO_EINVAL, "flag 4096 needs flag 512");
     p->kc = zchunk;
     p->tflags = flags;
     build_tiles(p);
@@ -1640,7 +1643,8 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int part,
 static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, int blocks, hipStream_t s)
 {
     const int f = p0->tflags;
-    if (part == 2 || part == 4) return yo_launch_step2(part == 4, a, blocks, s);
+    if (part == 2) return yo_launch_step2(false, (f & YO_TILE_PAIR6) ? YO_TY2 : YO_TY, a, blocks, s);
+    if (part == 4) return yo_launch_step2(true, YO_TY, a, blocks, s);
     if (part == 3)
         return yo_launch_step((f & YO_TILE_XINT) ? 1 : 0, false, !(f & YO_TILE_NOPF_INT), a, blocks, s);
     if (part == 0)

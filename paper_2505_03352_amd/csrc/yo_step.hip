@@ -1013,7 +1013,7 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
     }
 }
 
-template <bool ZP>
+template <bool ZP, int TY>
 __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step2(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -1036,7 +1036,7 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step2(const YoStepArgs 
     const int r = sl.rhs0 + in_grp / wpb;
     const int ti = grp * wpb + in_grp % wpb;
     if (ti >= sl.ntile) return;
-    wave_step2<YO_TY, ZP>(P, P.rhs[r], step, sl.tiles[ti], lane);
+    wave_step2<TY, ZP>(P, P.rhs[r], step, sl.tiles[ti], lane);
 }
 
 // locate point q of slot s in the aux work list
@@ -1193,14 +1193,18 @@ hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &ar
     return hipGetLastError();
 }
 
-hipError_t yo_launch_step2(bool zslab, const YoStepArgs &args, int blocks, hipStream_t s)
+hipError_t yo_launch_step2(bool zslab, int rows, const YoStepArgs &args, int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
-    if (zslab)
-        hipLaunchKernelGGL(k_yee_step2<true>, dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+    if (zslab && rows == YO_TY)
+        hipLaunchKernelGGL((k_yee_step2<true, YO_TY>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+    else if (!zslab && rows == YO_TY)
+        hipLaunchKernelGGL((k_yee_step2<false, YO_TY>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+    else if (!zslab && rows == YO_TY2)
+        hipLaunchKernelGGL((k_yee_step2<false, YO_TY2>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
     else
-        hipLaunchKernelGGL(k_yee_step2<false>, dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -59,7 +59,8 @@ def test_pairs_bitwise_equal_single_steps_with_cpml_and_source(steps):
                               (2, 4, 512 | 32, True), (2, 10, 512 | 256 | 1 | 64, True),
                               (2, 8, 512 | 256 | 128 | 2, False), (2, 10, 512 | 1024 | 1 | 8, True),
                               (2, 8, 512 | 1024 | 128, False), (2, 10, 512 | 2048 | 128 | 8, True),
-                              (2, 4, 512 | 2048 | 128, False), (2, 16, 512 | 2048 | 1024 | 128 | 2, True)]:
+                              (2, 4, 512 | 2048 | 128, False), (2, 16, 512 | 2048 | 1024 | 128 | 2, True),
+                              (2, 8, 512 | 4096 | 128 | 8, True), (2, 10, 512 | 4096 | 2048 | 128, False)]:
         say(f"pairs box steps={steps} tb={tb} tiling=(4,{zc},{fl}) graph={graph}")
         p = _box_plan(steps, tb)
         p.set_tiling(4, zc, fl)
@@ -110,7 +111,8 @@ def test_pairs_bitwise_equal_with_window_and_several_wavelengths():
     dev = configs.micro(n_steps=400, nx=150, ny=40, nz=30, md=10, nd=10, mc=5, nc=5,
                         wavelengths=[0.78e-6, 0.8e-6, 0.82e-6])
     res = {}
-    for tb, fl in [(1, 0), (2, 512), (2, 512 | 73), (2, 512 | 1024 | 73), (2, 512 | 2048 | 128 | 8)]:
+    for tb, fl in [(1, 0), (2, 512), (2, 512 | 73), (2, 512 | 1024 | 73), (2, 512 | 2048 | 128 | 8),
+                   (2, 512 | 4096 | 128 | 8)]:
         say(f"pairs micro tb={tb} flags={fl}")
         p = plan_for(dev, time_blocking=tb)
         p.set_tiling(4, 10, fl)
@@ -133,7 +135,7 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
     from paper_2505_03352_amd.plan import advance_many, plan_for
     devs = [configs.micro_demux(n_steps=2600), configs.micro(n_steps=1300, nx=90, ny=34, nz=24)]
     res = {}
-    for tb, fl in ((1, 0), (2, 512), (2, 512 | 1024), (2, 512 | 2048 | 128)):
+    for tb, fl in ((1, 0), (2, 512), (2, 512 | 1024), (2, 512 | 2048 | 128), (2, 512 | 4096)):
         say(f"pairs pulse + shared launches tb={tb} flags={fl}")
         plans = []
         for d in devs:
@@ -151,7 +153,7 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
             out += [p.get_dft(r, 0).cpu().numpy() for r in range(p.n_rhs)] + [a.cpu().numpy()]
             p.close()
         res[fl] = out
-    for fl in (512, 512 | 1024, 512 | 2048 | 128):
+    for fl in (512, 512 | 1024, 512 | 2048 | 128, 512 | 4096):
         for x, y in zip(res[fl], res[0]):
             assert np.array_equal(x, y), fl
 
