@@ -51,7 +51,7 @@ INTERIOR_FLAGS = (0, 16, 32, 16 | 32)          # cooperative, no prefetch
 # launch, 128 cuts whole 60-cell two-step strips); 2: 8 waves per block;
 # 2048: the z-slabs under the two-step region take two steps per launch
 # too}; for each, the two-step launch is timed with 4- and 6-row tiles
-# (flag 4096) and the faster kept.  (Flag 256, the tiles that meet only the
+# (flag 4096), independent or cooperative (8192), and the fastest kept.  (Flag 256, the tiles that meet only the
 # x-slabs run with the interior around the two-step region, measured slower
 # and is left out.)
 PAIR_SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b | c) for z in (8, 10, 16) for a in (0, 1, 128)
@@ -186,10 +186,12 @@ def tune(plan, which: int = YO_BOTH, shared: Optional[Iterable] = None, n_launch
             t2 = _time(plan, zc2, fl0, 2, which, n_launch, stream)
             if t2 <= 0.0:
                 break               # no two-step region on this grid
-            # 6-row two-step tiles (flag 4096) where that launch runs faster
-            t2b = _time(plan, zc2, fl0 | 4096, 2, which, n_launch, stream)
-            if t2b < t2:
-                fl0, t2 = fl0 | 4096, t2b
+            # 6-row two-step tiles (flag 4096) and cooperative two-step
+            # blocks (8192) where that launch runs faster
+            for v in (4096, 8192, 4096 | 8192):
+                t2b = _time(plan, zc2, (base | 512) | v, 2, which, n_launch, stream)
+                if t2b < t2:
+                    fl0, t2 = (base | 512) | v, t2b
             # the z-slabs' two-step launch (0: none, without 2048 or where
             # planes cut the region) and the shell of the paired steps
             t4 = _time(plan, zc2, fl0, 4, which, n_launch, stream)

@@ -170,8 +170,10 @@ hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &ar
                           hipStream_t s);
 // two steps per sweep over the tiles of the two-step region (independent
 // waves); zslab: the tiles of the z-slabs under it, with z-axis CPML code;
-// rows: rows per tile, YO_TY, or YO_TY2 for the region itself
-hipError_t yo_launch_step2(bool zslab, int rows, const YoStepArgs &args, int blocks, hipStream_t s);
+// rows: rows per wave, YO_TY, or YO_TY2 for the region itself; coop: one
+// tile per block, its waves stacked in y and sharing rows through LDS
+hipError_t yo_launch_step2(bool zslab, int rows, bool coop, const YoStepArgs &args, int blocks,
+                           hipStream_t s);
 hipError_t yo_launch_dft(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_source(const YoAuxArgs &args, hipStream_t s);
 hipError_t yo_launch_ctr(const YoCtrArgs &args, int set_value, hipStream_t s);

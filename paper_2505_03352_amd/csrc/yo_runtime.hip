@@ -96,7 +96,8 @@ enum {
     YO_TILE_OVERLAP = 1024,   // with 512: the two-step launch runs beside the first step's frame and shell
     YO_TILE_ZPAIRS = 2048,    // with 512: the z-slabs under the two-step region take two steps per launch too
     YO_TILE_PAIR6 = 4096,     // with 512: the two-step region's tiles have YO_TY2 rows (else YO_TY)
-    YO_TILE_ALL = 8191
+    YO_TILE_COOP_PAIRS = 8192,  // with 512: the two-step region in cooperative blocks
+    YO_TILE_ALL = 16383
 };
 
 struct yo_plan {
@@ -520,7 +521,12 @@ void build_pair_tiles(yo_plan *p, const int lo[3], const int hi[3])
     std::vector<std::pair<int, int>> ax, ay, az;
     std::vector<char> ix, iy, iz;
     split_axis(n[0], r[0], r[1], 60, ax, ix);
-    split_axis(n[1], r[2], r[3], (p->tflags & YO_TILE_PAIR6) ? YO_TY2 : YO_TY, ay, iy);
+    // rows per tile: per wave (YO_TY or YO_TY2), times the waves of a
+    // block in the cooperative layout
+    const int wpb = (p->tflags & YO_TILE_WPB8) ? 8 : 4;
+    split_axis(n[1], r[2], r[3],
+               ((p->tflags & YO_TILE_PAIR6) ? YO_TY2 : YO_TY) * ((p->tflags & YO_TILE_COOP_PAIRS) ? wpb : 1),
+               ay, iy);
     split_axis(n[2], r[4], r[5], p->kc, az, iz);
     for (size_t k = 0; k < az.size(); ++k)
         for (size_t j = 0; j < ay.size(); ++j)
@@ -1296,7 +1302,8 @@ yo_status yo_set_time_blocking(yo_plan *p, int steps)
         return fail(YO_EUNSUPPORTED, "the CPML memories of one right-hand side must stay below 2 GiB");
     }
     p->tsteps = steps;
-    if (steps == 1) p->tflags &= ~(YO_TILE_PAIRS | YO_TILE_OVERLAP | YO_TILE_ZPAIRS | YO_TILE_PAIR6);
+    if (steps == 1)
+        p->tflags &= ~(YO_TILE_PAIRS | YO_TILE_OVERLAP | YO_TILE_ZPAIRS | YO_TILE_PAIR6 | YO_TILE_COOP_PAIRS);
     // the two-step and frame tiles can add up to twice the single-step count
     p->tiles_cap = tiles_capacity(p->grid, 4, 4) * (steps == 2 ? 3 : 1);
     build_tiles(p);
@@ -1362,6 +1369,8 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
         return fail(YO_EINVAL, "flag 2048 needs flag 512");
     if ((flags & YO_TILE_PAIR6) && !(flags & YO_TILE_PAIRS))
         return fail(YO_EINVAL, "flag 4096 needs flag 512");
+    if ((flags & YO_TILE_COOP_PAIRS) && !(flags & YO_TILE_PAIRS))
+        return fail(YO_EINVAL, "flag 8192 needs flag 512");
     p->kc = zchunk;
     p->tflags = flags;
     build_tiles(p);
@@ -1612,8 +1621,9 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int part,
     a.n_slots = cnt;
     const int wpb = (plans[0]->tflags & YO_TILE_WPB8) ? 8 : 4;
     const int f = plans[0]->tflags;
-    const bool coop = part == 0 ? (f & YO_TILE_COOP_INT) != 0
-                                : (part == 1 || part == 5) && (f & YO_TILE_COOP_SHELL) != 0;
+    const bool coop = part == 0   ? (f & YO_TILE_COOP_INT) != 0
+                      : part == 2 ? (f & YO_TILE_COOP_PAIRS) != 0
+                                  : (part == 1 || part == 5) && (f & YO_TILE_COOP_SHELL) != 0;
     int tot = 0;
     for (int i = 0; i < cnt; ++i) {
         yo_plan *p = plans[i];
@@ -1643,8 +1653,10 @@ static int step_args(yo_plan *const *plans, const int *which, int cnt, int part,
 static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, int blocks, hipStream_t s)
 {
     const int f = p0->tflags;
-    if (part == 2) return yo_launch_step2(false, (f & YO_TILE_PAIR6) ? YO_TY2 : YO_TY, a, blocks, s);
-    if (part == 4) return yo_launch_step2(true, YO_TY, a, blocks, s);
+    if (part == 2)
+        return yo_launch_step2(false, (f & YO_TILE_PAIR6) ? YO_TY2 : YO_TY, (f & YO_TILE_COOP_PAIRS) != 0, a,
+                               blocks, s);
+    if (part == 4) return yo_launch_step2(true, YO_TY, false, a, blocks, s);
     if (part == 3)
         return yo_launch_step((f & YO_TILE_XINT) ? 1 : 0, false, !(f & YO_TILE_NOPF_INT), a, blocks, s);
     if (part == 0)

@@ -727,9 +727,16 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
 // cells and, for R2's outermost layer, the Ht memories of step n+1 (slot
 // (n+1) % 3), which the single steps around read.  Planes past the grid are
 // the perfect conductor's zeros.
-template <int TY, bool ZP>
+// COOP: the tile is the block's, its waves stacked in y (wave w owns rows
+// J0 + w TY ...); each wave loads its own rows of step n and the rows it
+// shares with the waves below and above come through LDS (E^n of the two
+// rows below and above, Ht^{n-1/2} of the two below and one above; one
+// barrier per plane, two parities), so only the block's bottom and top
+// waves load the block's halo rows.
+template <int TY, bool ZP, bool COOP = false>
 __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, const int step,
-                                           const int4 t, const int lane)
+                                           const int4 t, const int w, const int wpb, const int lane,
+                                           float *xs)
 {
     const int nx = P.nx, ny = P.ny, nxp = P.nxp;
     const int rows = ny + 2;
@@ -744,8 +751,24 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
     const float sx = P.sx, sy = P.sy, sz = P.sz;
 
     const int x0 = t.x & 0xffff, xn = t.x >> 16;
-    const int j0 = t.y & 0xffff, jn = t.y >> 16;
+    const int J0 = t.y & 0xffff, JN = t.y >> 16;
     const int k0 = t.z & 0xffff, k1 = t.z >> 16;
+    const int j0 = COOP ? J0 + w * TY : J0;
+    const int jn = COOP ? clampi(JN - w * TY, 0, TY) : JN;
+    const bool bottom = !COOP || w == 0;
+    const bool top = !COOP || JN - w * TY <= TY;        // no rows of the tile above this wave
+    if (COOP && jn == 0) {
+        // past the tile's last row: nothing to compute, but keep the barriers
+        for (int k = k0 - 2; k <= k1; ++k) block_sync_lds();
+        return;
+    }
+    // exchange slots of this wave (20 per parity: E^n rows TY, TY+1 and Ht
+    // rows TY, TY+1 for the wave above; E^n row 2, row 3's Ex and Ez, and Ht
+    // row 2 for the wave below); a neighbour's are 20 * 64 floats away
+    float *const xme = COOP ? xs + w * 20 * 64 + lane : nullptr;
+    auto xslot = [&](int pp, int dw, int q) -> float & {
+        return xme[(pp * wpb + dw) * 20 * 64 + q * 64];
+    };
     const int x = x0 - 2 + lane;
     const int xo = (clampi(x, -1, nx) + 1) * (int)sizeof(float);
     const bool own_x = (lane >= 2) && (lane < 2 + xn);
@@ -782,7 +805,9 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
     Cpml czH = {1.0f, 0.0f, 1.0f}, czE = czH, czHp = czH, czEp = czH;
     int pzp = -1;
 
-    auto load_e = [&](int k, float (&e)[3][NE]) {
+    // all: every row from memory; else (COOP) the rows a neighbour passes on
+    // are left for the exchange
+    auto load_e = [&](int k, float (&e)[3][NE], bool all) {
         if (ZP && (k < -1 || k > nz)) {   // past the ghost planes
 #pragma unroll
             for (int r = 0; r < NE; ++r)
@@ -792,6 +817,7 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
         }
 #pragma unroll
         for (int r = 0; r < NE; ++r) {
+            if (COOP && !all && ((r < 2 && !bottom) || (r >= TY + 2 && !top))) continue;
             const int o = ro(j0 - 2 + r, k);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -800,7 +826,7 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
             }
         }
     };
-    load_e(k0 - 2, Ec);
+    load_e(k0 - 2, Ec, true);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -812,7 +838,7 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
     }
 
     for (int k = k0 - 2; k <= k1; ++k) {
-        load_e(k + 1, Enx);
+        load_e(k + 1, Enx, false);
         if (ZP && k < -1) {
 #pragma unroll
             for (int r = 0; r < NH; ++r)
@@ -821,9 +847,45 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
         } else {
 #pragma unroll
             for (int r = 0; r < NH; ++r) {
+                if (COOP && ((r < 2 && !bottom) || (r >= TY + 2 && !top))) continue;
                 const int o = ro(j0 - 2 + r, k);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Ho[c][r] = bload(FA, xo, hb + c * rowb + o);
+            }
+        }
+        if (COOP) {
+            // the rows the neighbours share, then theirs
+            const int pp = k & 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xslot(pp, 0, c) = Enx[c][TY];
+                xslot(pp, 0, 3 + c) = Enx[c][TY + 1];
+                xslot(pp, 0, 6 + c) = Ho[c][TY];
+                xslot(pp, 0, 9 + c) = Ho[c][TY + 1];
+                xslot(pp, 0, 12 + c) = Enx[c][2];
+                xslot(pp, 0, 17 + c) = Ho[c][2];
+            }
+            xslot(pp, 0, 15) = Enx[0][3];
+            xslot(pp, 0, 16) = Enx[2][3];
+            block_sync_lds();
+            if (!bottom) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    Enx[c][0] = xslot(pp, -1, c);
+                    Enx[c][1] = xslot(pp, -1, 3 + c);
+                    Ho[c][0] = xslot(pp, -1, 6 + c);
+                    Ho[c][1] = xslot(pp, -1, 9 + c);
+                }
+            }
+            if (!top) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    Enx[c][TY + 2] = xslot(pp, 1, 12 + c);
+                    Ho[c][TY + 2] = xslot(pp, 1, 17 + c);
+                }
+                Enx[0][TY + 3] = xslot(pp, 1, 15);
+                Enx[1][TY + 3] = 0.0f;
+                Enx[2][TY + 3] = xslot(pp, 1, 16);
             }
         }
         // ZP: plane k's z coefficients (its memories of step n, slot n % 3,
@@ -1013,7 +1075,7 @@ __device__ __forceinline__ void wave_step2(const YoPlanD &P, const YoRhsD &R, co
     }
 }
 
-template <bool ZP, int TY>
+template <bool ZP, int TY, bool COOP>
 __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step2(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -1031,12 +1093,25 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step2(const YoStepArgs 
     // the host schedules a pair only where both steps remain
     if (step + 1 >= P.n_steps) return;
     const int local = wave - a.prefix[s];
+    if (COOP) {
+        // one tile per block; consecutive blocks take the same tile for the
+        // next right-hand sides (every early exit above is uniform over the
+        // block, as the barriers require)
+        extern __shared__ float xs2[];
+        const int blk = local / wpb;
+        const int w = local - blk * wpb;
+        const int r = sl.rhs0 + blk % sl.nrhs;
+        const int ti = blk / sl.nrhs;
+        if (ti >= sl.ntile) return;
+        wave_step2<TY, ZP, true>(P, P.rhs[r], step, sl.tiles[ti], w, wpb, lane, xs2);
+        return;
+    }
     const int grp = local / (wpb * sl.nrhs);
     const int in_grp = local - grp * (wpb * sl.nrhs);
     const int r = sl.rhs0 + in_grp / wpb;
     const int ti = grp * wpb + in_grp % wpb;
     if (ti >= sl.ntile) return;
-    wave_step2<TY, ZP>(P, P.rhs[r], step, sl.tiles[ti], lane);
+    wave_step2<TY, ZP, false>(P, P.rhs[r], step, sl.tiles[ti], 0, wpb, lane, nullptr);
 }
 
 // locate point q of slot s in the aux work list
@@ -1193,16 +1268,24 @@ hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &ar
     return hipGetLastError();
 }
 
-hipError_t yo_launch_step2(bool zslab, int rows, const YoStepArgs &args, int blocks, hipStream_t s)
+hipError_t yo_launch_step2(bool zslab, int rows, bool coop, const YoStepArgs &args, int blocks,
+                           hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
-    if (zslab && rows == YO_TY)
-        hipLaunchKernelGGL((k_yee_step2<true, YO_TY>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
-    else if (!zslab && rows == YO_TY)
-        hipLaunchKernelGGL((k_yee_step2<false, YO_TY>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
-    else if (!zslab && rows == YO_TY2)
-        hipLaunchKernelGGL((k_yee_step2<false, YO_TY2>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+    const dim3 g(blocks), b(64 * args.wpb);
+    // cooperative: 20 exchange slots of 64 floats per wave and parity
+    const size_t lds = (size_t)2 * args.wpb * 20 * 64 * sizeof(float);
+    if (zslab && rows == YO_TY && !coop)
+        hipLaunchKernelGGL((k_yee_step2<true, YO_TY, false>), g, b, 0, s, args);
+    else if (!zslab && rows == YO_TY && !coop)
+        hipLaunchKernelGGL((k_yee_step2<false, YO_TY, false>), g, b, 0, s, args);
+    else if (!zslab && rows == YO_TY2 && !coop)
+        hipLaunchKernelGGL((k_yee_step2<false, YO_TY2, false>), g, b, 0, s, args);
+    else if (!zslab && rows == YO_TY && coop)
+        hipLaunchKernelGGL((k_yee_step2<false, YO_TY, true>), g, b, lds, s, args);
+    else if (!zslab && rows == YO_TY2 && coop)
+        hipLaunchKernelGGL((k_yee_step2<false, YO_TY2, true>), g, b, lds, s, args);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
