@@ -400,6 +400,15 @@ yo_status yo_model_bytes(const yo_plan *plan, int which, double *bytes_per_step,
 yo_status yo_time_kernel(yo_plan *plan, int cls, int n_launch, float *avg_ms, double *bytes,
                          double *cells, yo_stream stream);
 
+/* The tiles of one launch part (as yo_time_kernel numbers them, 0 to 5)
+ * under the plan's current tiling: *n = their number, and the first
+ * min(n, cap) written to host memory `out` as 7 ints each: x0, x1, y0, y1,
+ * z0, z1 (the cells [x0, x1) x [y0, y1) x [z0, z1) the tile owns) and its
+ * CPML class (bit a: the tile meets the absorbing slab of axis a).  Host
+ * only; needs no workspace.  For checking a split: in single steps parts 0
+ * and 1 own every cell once, in steps that go in pairs parts 2 to 5. */
+yo_status yo_tile_table(const yo_plan *plan, int part, int *out, int cap, int *n);
+
 /* Unbinarity (Sec. 4): the fraction of the design area's high-resolution
  * sub-pixels whose final density rho lies strictly between lo and hi
  * (0 <= lo < hi <= 1), for the design last set; FP32 written to dev_u[0]

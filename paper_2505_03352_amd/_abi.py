@@ -96,6 +96,7 @@ _SIGS = {
     "yo_set_fields": [_P, _I, _P, _P, _S],
     "yo_get_fields": [_P, _I, _P, _P, _S],
     "yo_get_kappa": [_P, _P, _S],
+    "yo_tile_table": [_P, _I, ct.POINTER(ct.c_int), _I, ct.POINTER(ct.c_int)],
     "yo_time_kernel": [_P, _I, _I, ct.POINTER(ct.c_float), ct.POINTER(ct.c_double),
                        ct.POINTER(ct.c_double), _S],
     "yo_model_bytes": [_P, _I, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)],

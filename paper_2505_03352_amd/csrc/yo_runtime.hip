@@ -2107,6 +2107,27 @@ yo_status yo_get_timing(yo_plan *p, int part, float *avg_ms, int *count)
     return YO_OK;
 }
 
+yo_status yo_tile_table(const yo_plan *p, int part, int *out, int cap, int *n)
+{
+    if (!p || !n || (cap > 0 && !out)) return fail(YO_EINVAL, "null argument");
+    if (part < 0 || part > 5) return fail(YO_EINVAL, "part must be 0 to 5");
+    int t0, t1;
+    part_range(p, part, t0, t1);
+    *n = t1 - t0;
+    for (int t = t0; t < t1 && t - t0 < cap; ++t) {
+        const int4 tt = p->tiles_host[t];
+        int *o = out + 7 * (t - t0);
+        o[0] = tt.x & 0xffff;
+        o[1] = o[0] + (tt.x >> 16);
+        o[2] = tt.y & 0xffff;
+        o[3] = o[2] + (tt.y >> 16);
+        o[4] = tt.z & 0xffff;
+        o[5] = tt.z >> 16;
+        o[6] = tt.w;
+    }
+    return YO_OK;
+}
+
 yo_status yo_time_kernel(yo_plan *p, int cls, int n_launch, float *avg_ms, double *bytes,
                          double *cells, yo_stream stream)
 {

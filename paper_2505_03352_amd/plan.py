@@ -285,6 +285,17 @@ class Plan:
              ct.byref(c), _stream(stream))
         return float(ms.value), float(b.value), float(c.value)
 
+    def tile_table(self, part: int):
+        """The tiles of launch part `part` (see time_kernel) under the current
+        tiling: an int array [n][7] of x0, x1, y0, y1, z0, z1, CPML class
+        (host only)."""
+        n = ct.c_int()
+        call("yo_tile_table", self._h, int(part), None, 0, ct.byref(n))
+        out = (ct.c_int * (7 * max(n.value, 1)))()
+        call("yo_tile_table", self._h, int(part), out, n.value, ct.byref(n))
+        import numpy as np
+        return np.ctypeslib.as_array(out)[: 7 * n.value].reshape(n.value, 7).copy()
+
     def unbinarity(self, lo: float = 0.01, hi: float = 0.99, stream=None) -> torch.Tensor:
         """Fraction of grey design sub-pixels (lo < rho < hi) of the design
         last set, as a one-element device tensor."""
