@@ -510,8 +510,8 @@ def bench_batch(args):
     devs = configs.batch(8)
     log("batch: " + ", ".join(f"{d.nx}x{d.ny}x{d.nz}/{d.n_steps}" for d in devs))
     cells = sum(2 * d.cells * d.n_steps for d in devs)
-    plans = [plan_for(d, device="cuda:0") for d in devs]
-    batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS, zchunk=batch.DEFAULT_ZCHUNK)
+    plans = [plan_for(d, device="cuda:0", time_blocking=2) for d in devs]
+    batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS_PAIRS, zchunk=batch.DEFAULT_ZCHUNK)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.solve(plans, chunk=args.chunk, use_graph=True)
@@ -567,8 +567,9 @@ class PlainOneAtATime:
     """The serving baseline of plain solves: requests in arrival order, one
     at a time; each wavelength of a request is its own plan (one forward and
     one adjoint right-hand side, the request's steps and windows), run as a
-    forward solve and then an adjoint solve with plain launches and no graph;
-    the request's gradient is the sum over its wavelengths."""
+    forward solve and then an adjoint solve with plain launches and no graph,
+    with the served side's split and two steps per launch; the request's
+    gradient is the sum over its wavelengths."""
 
     def __init__(self, torch, chunk):
         self.torch = torch
@@ -589,7 +590,8 @@ class PlainOneAtATime:
             alphas, g_sum = [], None
             for lam in lams:
                 dev = configs.serving_request(i, cls, [lam], n_steps=n_steps)
-                p = plan_for(dev, device="cuda:0")
+                p = plan_for(dev, device="cuda:0", time_blocking=2)
+                p.set_tiling(4, 10, 200 | 512)      # the served side's split
                 p.run(1, chunk=self.chunk, use_graph=False)
                 p.run(2, chunk=self.chunk, use_graph=False)
                 a = p.alpha()
@@ -793,7 +795,7 @@ def bench_broadband(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / n, a.cpu().numpy(), g.cpu().numpy()
 
-    ph = plan_for(dev, device="cuda:0")
+    ph = plan_for(dev, device="cuda:0", time_blocking=2)
     th = autotune.tune(ph, YO_BOTH, use_cache=False)
     s_h, a_h, g_h = timed(ph, args.steps)
     ph.close()
@@ -801,7 +803,7 @@ def bench_broadband(args):
     n_h = ph.n_rhs
     dp = make(n_steps=args.pulse_steps or (7000 if args.device == "realistic" else 12000))
     w0, sig, t0 = dp.pulse(k=0.4 if args.pulse_k is None else args.pulse_k)
-    pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0, args.dft_stride))
+    pp = plan_for(dp, device="cuda:0", pulse=(w0 / dp.dt(), sig, t0, args.dft_stride), time_blocking=2)
     tp = autotune.tune(pp, YO_BOTH, use_cache=False)
     s_p, a_p, g_p = timed(pp, args.steps)
     ea = float(np.abs(a_p - a_h).max() / np.abs(a_h).max())
@@ -846,7 +848,7 @@ def bench_optimize(args):
     dev = configs.demux()
     T = np.array([[[1.0, 0.0], [0.0, 1.0]]])     # [source][port][wavelength]: demux, no crosstalk
     log(f"demux: {dev.nx}x{dev.ny}x{dev.nz}, {dev.n_steps} steps, {dev.mc}x{dev.nc} controls")
-    plan = plan_for(dev, device="cuda:0")
+    plan = plan_for(dev, device="cuda:0", time_blocking=2)
     tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
     extra = {}
     run_dev, how = dev, f"1 forward + 2 adjoint per wavelength, {dev.n_steps} steps"
@@ -869,7 +871,8 @@ def bench_optimize(args):
         plan.close()
         run_dev = configs.demux(n_steps=args.pulse_steps or 12000)
         w0, sig, t0 = run_dev.pulse(k=1.0 if args.pulse_k is None else args.pulse_k)
-        plan = plan_for(run_dev, device="cuda:0", pulse=(w0 / run_dev.dt(), sig, t0, args.dft_stride))
+        plan = plan_for(run_dev, device="cuda:0", pulse=(w0 / run_dev.dt(), sig, t0, args.dft_stride),
+                        time_blocking=2)
         tuned = autotune.tune(plan, YO_BOTH, use_cache=False)
         s_p, a_p, g_p = one(plan)
         ea = float(np.abs(a_p - a_h).max() / np.abs(a_h).max())

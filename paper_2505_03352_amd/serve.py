@@ -295,14 +295,19 @@ class GpuExecutor:
     progress.  The default split is the batch executor's (rows 4, 10
     z-planes per tile, flags 200), since admitted requests share launches."""
 
-    def __init__(self, build: Callable, device="cuda:0", tiling=(4, 10, 200), use_graph=False,
-                 chunk: int = 100, pulse_multi: bool = False, dft_stride: int = 4):
+    def __init__(self, build: Callable, device="cuda:0", tiling=None, use_graph=False,
+                 chunk: int = 100, pulse_multi: bool = False, dft_stride: int = 4,
+                 time_blocking: int = 2):
         import torch
         from . import _abi  # noqa: F401  (fails loudly without the library)
         self.torch = torch
         self.build = build                 # payload -> workloads.Device-like description
         self.device = torch.device(device)
-        self.tiling = tiling
+        # plans take two steps per launch over their interior by default
+        # (bitwise the same results); the split: whole interior x-strips,
+        # per-class shell code without prefetch, 10-plane tiles
+        self.time_blocking = int(time_blocking)
+        self.tiling = tiling if tiling is not None else (4, 10, 200 | (512 if self.time_blocking == 2 else 0))
         self.use_graph = use_graph
         self.chunk = chunk
         self.pulse_multi = pulse_multi
@@ -331,7 +336,8 @@ class GpuExecutor:
         grid, design = grid_design_of(dev)
         plan = Plan(grid, design, dev.n_steps, freqs_of(dev), [m.plane for m in dev.sources],
                     [m.plane for m in dev.ports], device=self.device,
-                    pulse=None if pulse is None else tuple(pulse[:3]) + (self.dft_stride,))
+                    pulse=None if pulse is None else tuple(pulse[:3]) + (self.dft_stride,),
+                    time_blocking=self.time_blocking)
         plan.set_tiling(*self.tiling)
         host = dict(kappa=self.torch.as_tensor(dev.kappa_bg, dtype=self.torch.float32),
                     mask=self.torch.as_tensor(dev.mask_hr, dtype=self.torch.float32),

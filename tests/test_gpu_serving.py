@@ -50,6 +50,14 @@ def test_batch_solve_matches_individual_runs():
         assert np.array_equal(a.cpu().numpy(), a0)
         assert np.array_equal(g.cpu().numpy(), g0)
         p.close()
+    say("batch.solve with two steps per launch (the bench's batch split)")
+    plans = [plan_for(d, time_blocking=2) for d in devs]
+    batch.shared_tiling(plans, 4, batch.DEFAULT_FLAGS_PAIRS, zchunk=8)
+    batch.solve(plans, chunk=64, use_graph=True)
+    for p, (a0, g0), (a, g) in zip(plans, alone, batch.gradients(plans)):
+        assert np.array_equal(a.cpu().numpy(), a0)
+        assert np.array_equal(g.cpu().numpy(), g0)
+        p.close()
 
 
 def _serve(payloads, arrivals, max_slots, chunk=100, pulse=False):
@@ -59,7 +67,8 @@ def _serve(payloads, arrivals, max_slots, chunk=100, pulse=False):
         i, cls, lams, steps = p
         return configs.serving_request(i, cls, lams, n_steps=steps)
 
-    ex = GpuExecutor(build, tiling=(4, 16, 1), chunk=chunk, pulse_multi=pulse)
+    # two steps per launch over each request's interior (the executor's default)
+    ex = GpuExecutor(build, tiling=(4, 16, 1 | 512), chunk=chunk, pulse_multi=pulse)
     reqs = [Request(i, t, p) for i, (t, p) in enumerate(zip(arrivals, payloads))]
     st = Scheduler(ex, max_slots=max_slots, chunk=chunk, prep_workers=2).run(reqs)
     torch.cuda.synchronize()
