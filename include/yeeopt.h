@@ -307,7 +307,11 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
  *       allows (needs yo_set_time_blocking(plan, 2); not with 16): its
  *       tiles are strips of at most 60 cells, 4 rows and zchunk planes, and
  *       the rest of the interior runs as single-step tiles around it (with
- *       256, together with the tiles that meet only the x-slabs)
+ *       256, together with the tiles that meet only the x-slabs).  The
+ *       region clear of the slabs then starts two cells inside them (the
+ *       two-step region's margin; the shell takes the layer between), and
+ *       with 128 the two-step strips are whole 60-cell strips between the
+ *       x-normal source and port planes, the shell strips the rest
  * 1024  with 512 (else YO_EINVAL): the two-step launch of a pair of steps
  *       runs on a second stream of the plan (created at its first advance,
  *       default priority), concurrently with the first step's other
