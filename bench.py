@@ -53,10 +53,11 @@ def kernel_sha() -> str:
 # the two-step launch (x-shell layouts, 8 waves per block) and the interior
 # around it (the same and no prefetch), the z-slabs' two-step launch and the
 # shell of paired steps (2048 decides which tiles each holds; 4096 and 8192
-# the two-step tiles' rows and blocks); 512 (two steps per launch) in all
-SPLIT_BITS = (1 | 2 | 16 | 32 | 128 | 256 | 512, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512 | 2048,
+# the two-step tiles' rows and blocks; 16384 the shell tiles' rows); 512
+# (two steps per launch) in all
+SPLIT_BITS = (1 | 2 | 16 | 32 | 128 | 256 | 512, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512 | 2048 | 16384,
               1 | 2 | 128 | 256 | 512 | 4096 | 8192, 1 | 2 | 32 | 128 | 256 | 512,
-              1 | 2 | 128 | 256 | 512 | 2048, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512 | 2048)
+              1 | 2 | 128 | 256 | 512 | 2048, 1 | 2 | 4 | 8 | 64 | 128 | 256 | 512 | 2048 | 16384)
 
 
 def part_split(tiling, part: int) -> str:

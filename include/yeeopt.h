@@ -327,6 +327,8 @@ yo_status yo_steps_done(const yo_plan *plan, int *steps);
  *       instead of 4 (fewer halo rows re-read, fewer waves per SIMD)
  * 8192  with 512 (else YO_EINVAL): the two-step region in cooperative
  *       blocks (waves stacked in y pass the rows they share through LDS)
+ * 16384 the CPML shell's tiles have 6 rows instead of 4 (not with 4:
+ *       YO_EINVAL)
  * Other bits: YO_EINVAL.  Results do not depend on the split (bitwise).
  * With a workspace bound, synchronises the device. */
 yo_status yo_set_tiling(yo_plan *plan, int rows, int zchunk, int flags);

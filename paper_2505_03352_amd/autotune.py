@@ -56,7 +56,10 @@ INTERIOR_FLAGS = (0, 16, 32, 16 | 32)          # cooperative, no prefetch
 # and is left out.)
 PAIR_SHARED: Tuple[Tuple[int, int], ...] = tuple((z, a | b | c) for z in (8, 10, 16) for a in (0, 1, 128)
                                                  for b in (0, 2) for c in (0, 2048))
-SHELL_FLAGS = tuple(a | b | c for a in (0, 4) for b in (0, 8) for c in (0, 64))
+# shell choices: cooperative blocks (4), per-class code (8), no prefetch
+# (64), 6-row tiles (16384; not cooperative)
+SHELL_FLAGS = tuple(a | b | c | d for a in (0, 4) for b in (0, 8) for c in (0, 64) for d in (0, 16384)
+                    if not (a and d))
 _lock = threading.Lock()
 
 

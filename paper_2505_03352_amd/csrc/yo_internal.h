@@ -166,8 +166,9 @@ struct YoChainBufs {
 // three axes, 8 = CPML tiles each running its own class's code (int4 .w);
 // coop: one tile per block, its waves stacked in y (tiles of YO_TY * wpb
 // rows); prefetch: operands of the next plane loaded during this one
+// rows: rows per wave, YO_TY, or YO_TY2 for the shell (pm 7 or 8, not coop)
 hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &args, int blocks,
-                          hipStream_t s);
+                          hipStream_t s, int rows = YO_TY);
 // two steps per sweep over the tiles of the two-step region (independent
 // waves); zslab: the tiles of the z-slabs under it, with z-axis CPML code;
 // rows: rows per wave, YO_TY, or YO_TY2 for the region itself; coop: one

@@ -97,7 +97,8 @@ enum {
     YO_TILE_ZPAIRS = 2048,    // with 512: the z-slabs under the two-step region take two steps per launch too
     YO_TILE_PAIR6 = 4096,     // with 512: the two-step region's tiles have YO_TY2 rows (else YO_TY)
     YO_TILE_COOP_PAIRS = 8192,  // with 512: the two-step region in cooperative blocks
-    YO_TILE_ALL = 16383
+    YO_TILE_SHELL6 = 16384,   // the CPML shell's tiles have YO_TY2 rows (not with 4)
+    YO_TILE_ALL = 32767
 };
 
 struct yo_plan {
@@ -692,7 +693,8 @@ void build_tiles(yo_plan *p)
     p->tiles_host.clear();
     emit(false, (p->tflags & YO_TILE_COOP_INT) ? YO_TY * wpb : YO_TY, p->tiles_host);
     p->n_int = (int)p->tiles_host.size();
-    emit(true, (p->tflags & YO_TILE_COOP_SHELL) ? YO_TY * wpb : YO_TY, p->tiles_host);
+    emit(true, (p->tflags & YO_TILE_COOP_SHELL) ? YO_TY * wpb : ((p->tflags & YO_TILE_SHELL6) ? YO_TY2 : YO_TY),
+         p->tiles_host);
     p->n_tiles = (int)p->tiles_host.size();
     p->n2 = p->nfr = p->nz2 = p->n_c4 = 0;
     if (pr && (p->tflags & YO_TILE_ZPAIRS)) {
@@ -1371,6 +1373,8 @@ yo_status yo_set_tiling(yo_plan *p, int rows, int zchunk, int flags)
         return fail(YO_EINVAL, "flag 4096 needs flag 512");
     if ((flags & YO_TILE_COOP_PAIRS) && !(flags & YO_TILE_PAIRS))
         return fail(YO_EINVAL, "flag 8192 needs flag 512");
+    if ((flags & YO_TILE_SHELL6) && (flags & YO_TILE_COOP_SHELL))
+        return fail(YO_EINVAL, "flag 16384 does not combine with flag 4");
     p->kc = zchunk;
     p->tflags = flags;
     build_tiles(p);
@@ -1663,7 +1667,7 @@ static hipError_t launch_part(const yo_plan *p0, int part, const YoStepArgs &a, 
         return yo_launch_step((f & YO_TILE_XINT) ? 1 : 0, (f & YO_TILE_COOP_INT) != 0,
                               !(f & YO_TILE_NOPF_INT), a, blocks, s);
     return yo_launch_step((f & YO_TILE_CLASS_CODE) ? 8 : 7, (f & YO_TILE_COOP_SHELL) != 0,
-                          !(f & YO_TILE_NOPF_SHELL), a, blocks, s);
+                          !(f & YO_TILE_NOPF_SHELL), a, blocks, s, (f & YO_TILE_SHELL6) ? YO_TY2 : YO_TY);
 }
 
 // Launch `n_launch` steps (k_offset 0..n_launch-1) of a plan list, then add

@@ -638,27 +638,28 @@ __device__ __forceinline__ void wave_step(const YoPlanD &P, const YoRhsD &R, con
 // PM = YO_PM_ANY: tiles of every CPML class in one launch, each tile's class
 // (int4 .w) selecting its code.
 #define YO_PM_ANY 8
-template <int PM, bool COOP, bool PF>
+template <int PM, bool COOP, bool PF, int TY>
 __device__ __forceinline__ void tile_step(const YoPlanD &P, const YoRhsD &R, int step, const int4 t,
                                           int w, int lane, float *xs)
 {
     if constexpr (PM == YO_PM_ANY) {
         switch (t.w) {
-        case 1: wave_step<YO_TY, 1, COOP, PF>(P, R, step, t, w, lane, xs); break;
-        case 2: wave_step<YO_TY, 2, COOP, PF>(P, R, step, t, w, lane, xs); break;
-        case 3: wave_step<YO_TY, 3, COOP, PF>(P, R, step, t, w, lane, xs); break;
-        case 4: wave_step<YO_TY, 4, COOP, PF>(P, R, step, t, w, lane, xs); break;
-        case 5: wave_step<YO_TY, 5, COOP, PF>(P, R, step, t, w, lane, xs); break;
-        case 6: wave_step<YO_TY, 6, COOP, PF>(P, R, step, t, w, lane, xs); break;
-        case 7: wave_step<YO_TY, 7, COOP, PF>(P, R, step, t, w, lane, xs); break;
-        default: wave_step<YO_TY, 0, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 1: wave_step<TY, 1, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 2: wave_step<TY, 2, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 3: wave_step<TY, 3, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 4: wave_step<TY, 4, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 5: wave_step<TY, 5, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 6: wave_step<TY, 6, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        case 7: wave_step<TY, 7, COOP, PF>(P, R, step, t, w, lane, xs); break;
+        default: wave_step<TY, 0, COOP, PF>(P, R, step, t, w, lane, xs); break;
         }
     } else {
-        wave_step<YO_TY, PM, COOP, PF>(P, R, step, t, w, lane, xs);
+        wave_step<TY, PM, COOP, PF>(P, R, step, t, w, lane, xs);
     }
 }
 
-template <int PM, bool COOP, bool PF>
+// TY: rows per wave (YO_TY; YO_TY2 for the taller shell tiles)
+template <int PM, bool COOP, bool PF, int TY = YO_TY>
 __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a)
 {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
         const int r = sl.rhs0 + blk % sl.nrhs;
         const int ti = blk / sl.nrhs;
         if (ti >= sl.ntile) return;
-        tile_step<PM, true, PF>(P, P.rhs[r], step, sl.tiles[ti], w, lane, xs);
+        tile_step<PM, true, PF, TY>(P, P.rhs[r], step, sl.tiles[ti], w, lane, xs);
     } else {
         // A block's waves take consecutive tiles (neighbouring x-strips of
         // the same rows) of one right-hand side, so together they stream
@@ -700,7 +701,7 @@ __global__ __launch_bounds__(64 * YO_MAX_WPB) void k_yee_step(const YoStepArgs a
         const int r = sl.rhs0 + in_grp / wpb;
         const int ti = grp * wpb + in_grp % wpb;
         if (ti >= sl.ntile) return;
-        tile_step<PM, false, PF>(P, P.rhs[r], step, sl.tiles[ti], 0, lane, nullptr);
+        tile_step<PM, false, PF, TY>(P, P.rhs[r], step, sl.tiles[ti], 0, lane, nullptr);
     }
 }
 
@@ -1235,10 +1236,10 @@ __global__ void k_ctr(const YoCtrArgs a, int set_value)
 
 }  // namespace
 
-template <int PM, bool COOP, bool PF>
+template <int PM, bool COOP, bool PF, int TY = YO_TY>
 static void launch_one(const YoStepArgs &args, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_yee_step<PM, COOP, PF>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
+    hipLaunchKernelGGL((k_yee_step<PM, COOP, PF, TY>), dim3(blocks), dim3(64 * args.wpb), 0, s, args);
 }
 
 template <int PM>
@@ -1254,10 +1255,21 @@ static void launch_pm(bool coop, bool pf, const YoStepArgs &args, int blocks, hi
 }
 
 hipError_t yo_launch_step(int pm, bool coop, bool prefetch, const YoStepArgs &args, int blocks,
-                          hipStream_t s)
+                          hipStream_t s, int rows)
 {
     if (blocks <= 0) return hipSuccess;
     if (args.wpb != 4 && args.wpb != 8) return hipErrorInvalidValue;
+    if (rows == YO_TY2) {
+        // taller tiles: the CPML shell's independent waves only
+        if (coop) return hipErrorInvalidValue;
+        if (pm == YO_PM_ANY && prefetch) launch_one<YO_PM_ANY, false, true, YO_TY2>(args, blocks, s);
+        else if (pm == YO_PM_ANY) launch_one<YO_PM_ANY, false, false, YO_TY2>(args, blocks, s);
+        else if (pm == 7 && prefetch) launch_one<7, false, true, YO_TY2>(args, blocks, s);
+        else if (pm == 7) launch_one<7, false, false, YO_TY2>(args, blocks, s);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    if (rows != YO_TY) return hipErrorInvalidValue;
     switch (pm) {
     case 0: launch_pm<0>(coop, prefetch, args, blocks, s); break;
     case 1: launch_pm<1>(coop, prefetch, args, blocks, s); break;

@@ -279,7 +279,9 @@ def test_time_blocking_arguments_and_workspace():
     assert L.yo_set_tiling(p.handle, 4, 16, 4096) == _abi.YO_EINVAL         # needs 512
     assert L.yo_set_tiling(p.handle, 4, 16, 512 | 8192) == _abi.YO_OK
     assert L.yo_set_tiling(p.handle, 4, 16, 8192) == _abi.YO_EINVAL         # needs 512
-    assert L.yo_set_tiling(p.handle, 4, 16, 16384) == _abi.YO_EINVAL
+    assert L.yo_set_tiling(p.handle, 4, 16, 16384) == _abi.YO_OK
+    assert L.yo_set_tiling(p.handle, 4, 16, 16384 | 4) == _abi.YO_EINVAL     # not cooperative
+    assert L.yo_set_tiling(p.handle, 4, 16, 32768) == _abi.YO_EINVAL
     assert L.yo_set_time_blocking(p.handle, 1) == _abi.YO_OK
     assert L.yo_workspace_bytes(p.handle, ct.byref(nb)) == _abi.YO_OK and nb.value == b1
     p.close()

@@ -62,7 +62,8 @@ def test_pairs_bitwise_equal_single_steps_with_cpml_and_source(steps):
                               (2, 4, 512 | 2048 | 128, False), (2, 16, 512 | 2048 | 1024 | 128 | 2, True),
                               (2, 8, 512 | 4096 | 128 | 8, True), (2, 10, 512 | 4096 | 2048 | 128, False),
                               (2, 8, 512 | 8192 | 128 | 8, True), (2, 10, 512 | 8192 | 2, False),
-                              (2, 8, 512 | 8192 | 4096 | 2048 | 128, True)]:
+                              (2, 8, 512 | 8192 | 4096 | 2048 | 128, True),
+                              (2, 16, 512 | 16384 | 4096 | 1 | 2 | 8 | 64, True), (2, 10, 512 | 16384 | 128, False)]:
         say(f"pairs box steps={steps} tb={tb} tiling=(4,{zc},{fl}) graph={graph}")
         p = _box_plan(steps, tb)
         p.set_tiling(4, zc, fl)
@@ -114,7 +115,7 @@ def test_pairs_bitwise_equal_with_window_and_several_wavelengths():
                         wavelengths=[0.78e-6, 0.8e-6, 0.82e-6])
     res = {}
     for tb, fl in [(1, 0), (2, 512), (2, 512 | 73), (2, 512 | 1024 | 73), (2, 512 | 2048 | 128 | 8),
-                   (2, 512 | 4096 | 128 | 8), (2, 512 | 8192 | 73)]:
+                   (2, 512 | 4096 | 128 | 8), (2, 512 | 8192 | 73), (2, 512 | 16384 | 73)]:
         say(f"pairs micro tb={tb} flags={fl}")
         p = plan_for(dev, time_blocking=tb)
         p.set_tiling(4, 10, fl)
@@ -138,7 +139,7 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
     devs = [configs.micro_demux(n_steps=2600), configs.micro(n_steps=1300, nx=90, ny=34, nz=24)]
     res = {}
     for tb, fl in ((1, 0), (2, 512), (2, 512 | 1024), (2, 512 | 2048 | 128), (2, 512 | 4096),
-                   (2, 512 | 8192)):
+                   (2, 512 | 8192), (2, 512 | 16384)):
         say(f"pairs pulse + shared launches tb={tb} flags={fl}")
         plans = []
         for d in devs:
@@ -156,7 +157,7 @@ def test_pairs_bitwise_equal_under_a_pulse_and_in_shared_launches():
             out += [p.get_dft(r, 0).cpu().numpy() for r in range(p.n_rhs)] + [a.cpu().numpy()]
             p.close()
         res[fl] = out
-    for fl in (512, 512 | 1024, 512 | 2048 | 128, 512 | 4096, 512 | 8192):
+    for fl in (512, 512 | 1024, 512 | 2048 | 128, 512 | 4096, 512 | 8192, 512 | 16384):
         for x, y in zip(res[fl], res[0]):
             assert np.array_equal(x, y), fl
 

@@ -169,7 +169,7 @@ def test_fields_match_oracle_with_cpml_and_source():
     # blocks on the y-slabs of 7 rows leave idle waves
     for rows, zc, fl in [(4, 16, 0), (4, 8, 1), (4, 4, 2), (4, 48, 3), (4, 16, 4), (4, 16, 13),
                          (4, 8, 70), (4, 4, 23), (4, 16, 45), (4, 8, 122), (4, 16, 77),
-                         (4, 8, 53)]:
+                         (4, 8, 53), (4, 16, 16384 | 73), (4, 10, 16384 | 2)]:
         say(f"cpml+source fields tiling=({rows},{zc},{fl})")
         p = Plan(grid, design, steps, [f], [pl], [], device="cuda")
         p.bind()

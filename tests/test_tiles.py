@@ -10,7 +10,7 @@ import pytest
 from paper_2505_03352_amd.plan import Plan, freqs_of, grid_design_of
 from workloads import configs
 
-SINGLE = [0, 1, 128, 2 | 4, 16 | 32, 256, 8 | 64, 1 | 2 | 8 | 64]
+SINGLE = [0, 1, 128, 2 | 4, 16 | 32, 256, 8 | 64, 1 | 2 | 8 | 64, 16384 | 1 | 8]
 PAIRS = [512, 512 | 128, 512 | 1, 512 | 2048 | 128, 512 | 4096 | 128, 512 | 8192 | 2, 512 | 256,
          512 | 1024 | 8, 512 | 4096 | 8192 | 1 | 2]
 
