@@ -96,3 +96,23 @@ def test_tile_classes_name_the_slabs_a_tile_meets():
                     # hold more: strips cut wider than the slab run its code)
                     assert t[6] != 0 and (t[6] & cls) == cls, (fl, t)
     p.close()
+
+
+@pytest.mark.parametrize("zc", [4, 63])
+def test_extreme_z_chunks_still_own_every_cell_once(zc):
+    """The shortest and longest z-chunks the library accepts, with the
+    shipped splits' other choices: the launches of one step and of a pair
+    of steps still cover the realistic grid once."""
+    dev = configs.realistic()
+    shape = (dev.nz, dev.ny, dev.nx)
+    p = _plan(dev, 2)
+    for fl in (8777, 21067, 16384 | 1 | 8):
+        p.set_tiling(4, zc, fl)
+        cov = _cover(p, (0, 1), shape)
+        assert cov.min() == 1 and cov.max() == 1, (zc, fl, "single")
+        if fl & 512:
+            cov = _cover(p, (2, 3, 4, 5), shape)
+            assert cov.min() == 1 and cov.max() == 1, (zc, fl, "pairs")
+            z = p.tile_table(2)[:, 5] - p.tile_table(2)[:, 4]
+            assert z.max() <= zc
+    p.close()
