@@ -12,7 +12,7 @@ from workloads import configs
 
 SINGLE = [0, 1, 128, 2 | 4, 16 | 32, 256, 8 | 64, 1 | 2 | 8 | 64, 16384 | 1 | 8]
 PAIRS = [512, 512 | 128, 512 | 1, 512 | 2048 | 128, 512 | 4096 | 128, 512 | 8192 | 2, 512 | 256,
-         512 | 1024 | 8, 512 | 4096 | 8192 | 1 | 2]
+         512 | 1024 | 8, 512 | 4096 | 8192 | 1 | 2, 512 | 2048 | 16384 | 128]
 
 
 def _plan(dev, tb):
