@@ -1,7 +1,8 @@
 """End-to-end parity at full size: the 320x240x96 realistic device at one
 wavelength (1.55 um: one forward and one adjoint right-hand side, 10 000
-steps), run through the C ABI in the headline bench's launch configuration
-(rows 4, 10 z-planes per tile, flags 73, hipGraph chunks of 100 steps), and
+steps), run through the C ABI in the bench's launch configuration for this
+grid (two steps per launch with its shipped split: cooperative two-step
+blocks, 16 z-planes per tile; hipGraph chunks of 100 steps), and
 the FP64 oracle computing everything from the same controls (its own chain,
 its own kappa): DFT phasors of the design box and the port plane (relative
 L2 <= 1e-4), alpha (<= 1e-4) and dF/dC (relative L2 <= 1e-3)."""
@@ -42,9 +43,13 @@ def test_realistic_one_wavelength_end_to_end_matches_oracle():
     from paper_2505_03352_amd.plan import plan_for
     dev = configs.realistic(wavelengths=[1.55e-6])
     assert dev.n_steps == 10000
-    say("realistic end to end: GPU (2 right-hand sides x 10000 steps)")
-    p = plan_for(dev)
-    p.set_tiling(4, 10, 73)
+    from paper_2505_03352_amd import autotune
+    recs = [v for k, v in autotune.shipped_splits().items() if "|ny240|nz96|" in k and k.endswith("|tb2")]
+    assert len(recs) == 1
+    rec = recs[0]
+    say(f"realistic end to end: GPU (2 right-hand sides x 10000 steps), split {rec}")
+    p = plan_for(dev, time_blocking=2)
+    p.set_tiling(rec["rows"], rec["zchunk"], rec["flags"])
     p.run(YO_BOTH, chunk=100, use_graph=True)
     alpha = p.alpha()
     g = p.gradient(torch.conj(alpha).resolve_conj().contiguous())

@@ -63,7 +63,8 @@ def test_pairs_bitwise_equal_single_steps_with_cpml_and_source(steps):
                               (2, 8, 512 | 4096 | 128 | 8, True), (2, 10, 512 | 4096 | 2048 | 128, False),
                               (2, 8, 512 | 8192 | 128 | 8, True), (2, 10, 512 | 8192 | 2, False),
                               (2, 8, 512 | 8192 | 4096 | 2048 | 128, True),
-                              (2, 16, 512 | 16384 | 4096 | 1 | 2 | 8 | 64, True), (2, 10, 512 | 16384 | 128, False)]:
+                              (2, 16, 512 | 16384 | 4096 | 1 | 2 | 8 | 64, True), (2, 10, 512 | 16384 | 128, False),
+                              (2, 10, 512 | 16384 | 2048 | 128 | 8, True)]:
         say(f"pairs box steps={steps} tb={tb} tiling=(4,{zc},{fl}) graph={graph}")
         p = _box_plan(steps, tb)
         p.set_tiling(4, zc, fl)

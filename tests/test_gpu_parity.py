@@ -355,10 +355,11 @@ def test_batched_advance_matches_individual_runs():
 
 
 def test_realistic_full_size_short_run_fields_match_oracle():
-    """The 320x240x96 grid in the headline bench's launch configuration
-    (the split its autotuner picks: rows 4, 10 z-planes per tile, flags 73),
-    150 steps from rest with the input source on: every field value against
-    the oracle."""
+    """The 320x240x96 grid one step per launch (rows 4, 10 z-planes per
+    tile, flags 73: strips, 8-wave blocks, per-class shell code), 150 steps
+    from rest with the input source on: every field value against the
+    oracle.  (The bench's two-steps-per-launch split of this grid is
+    checked end to end in test_gpu_fullsize.py.)"""
     from paper_2505_03352_amd.plan import plan_for
     dev = configs.realistic(n_steps=150, wavelengths=[1.55e-6])
     say("realistic full-size fields: GPU")
@@ -382,20 +383,31 @@ def test_realistic_full_size_short_run_fields_match_oracle():
     assert eE < 1e-4 and eH < 1e-4
 
 
+def shipped_split(shape: str) -> dict:
+    """The shipped two-steps-per-launch split of a grid shape (the one the
+    bench applies), e.g. shape "ny400|nz120"."""
+    from paper_2505_03352_amd import autotune
+    recs = [v for k, v in autotune.shipped_splits().items() if f"|{shape}|" in k and k.endswith("|tb2")]
+    assert len(recs) == 1, shape
+    return recs[0]
+
+
 def test_multiport_full_size_short_run_fields_match_oracle():
     """The 600x400x120 multi-port grid (1 wavelength: 1 forward + 4 adjoint
-    right-hand sides), 100 steps from rest with the input source on, in the
-    headline bench's work split (rows 4, 10 z-planes per tile, flags 73;
-    the 103 planes between the z-slabs make 11 tiles of 9 and 10 planes):
-    every field value of the forward right-hand side against the oracle."""
+    right-hand sides), 101 steps from rest with the input source on, in the
+    headline bench's launch configuration (two steps per launch, its shipped
+    split: 6-row two-step and shell tiles, 16 z-planes per tile; the odd
+    last step and the DFT window one step per launch): every field value
+    of the forward right-hand side against the oracle."""
     from paper_2505_03352_amd.plan import plan_for
     from oracle import ports
-    dev = configs.multiport(n_steps=100, wavelengths=[1.55e-6])
-    say("multi-port full-size fields: GPU")
-    p = plan_for(dev)
-    p.set_tiling(4, 10, 73)
+    dev = configs.multiport(n_steps=101, wavelengths=[1.55e-6])
+    rec = shipped_split("ny400|nz120")
+    say(f"multi-port full-size fields: GPU, split {rec}")
+    p = plan_for(dev, time_blocking=2)
+    p.set_tiling(rec["rows"], rec["zchunk"], rec["flags"])
     p.reset(3)
-    p.advance(3, 100)
+    p.advance(3, 101)
     E, H = p.get_fields(0)
     E, H = E.cpu().numpy(), H.cpu().numpy()
     kap = p.get_kappa().cpu().numpy().astype(np.float64)
