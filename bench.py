@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-realistic", action="store_true",
                     help="multiport: leave out the realistic device's whole gradients")
+    ap.add_argument("--realistic-only", action="store_true",
+                    help="the realistic device's whole gradients alone, as their own line "
+                         "(a short run for counter collection)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--retune", action="store_true",
                     help="multi-port and realistic: sweep the splits instead of applying the shipped ones")
@@ -228,8 +231,22 @@ def main():
         return bench_broadband(args)
     if args.workload == "batch-fd":
         return bench_batch_fd(args)
+    if args.realistic_only:
+        return bench_realistic_only(args)
 
     return bench_headline(args)
+
+
+def bench_realistic_only(args):
+    """The realistic device's whole gradients (the headline line's extra
+    keys) without the multi-port solve, after the same calibration copy."""
+    import torch
+    torch.cuda.set_device(0)
+    calibration_copy(torch)
+    res = realistic_gradients(args, torch)
+    _line("Gcell-updates/s (realistic device, whole gradients)", res["gcell_updates_per_s"],
+          "Gcell-updates/s", res["s_per_gradient"] * 1e3, args,
+          {"workload": res["workload"], "tiling": res["tiling"]}, {"realistic": res})
 
 
 def calibration_copy(torch):
