@@ -116,3 +116,47 @@ def test_extreme_z_chunks_still_own_every_cell_once(zc):
             z = p.tile_table(2)[:, 5] - p.tile_table(2)[:, 4]
             assert z.max() <= zc
     p.close()
+
+
+def _tuner_space():
+    """Every (z-chunk, flags) the autotuner can apply: the single-step
+    sweep (shared choice | interior flags | shell flags) and the pairs
+    sweep (shared choice | 512 | two-step variant | frame flag | shell
+    flags, with or without the side stream)."""
+    from paper_2505_03352_amd import autotune as at
+    out = set()
+    for zc, base in at.SHARED:
+        for fi in at.INTERIOR_FLAGS:
+            for fs in at.SHELL_FLAGS:
+                out.add((zc, base | fi | fs))
+    for zc, base in at.PAIR_SHARED:
+        for v in (0, 4096, 8192, 4096 | 8192):
+            for ff in (0, 32):
+                for fs in at.SHELL_FLAGS:
+                    for ov in (0, 1024):
+                        out.add((zc, base | 512 | v | ff | fs | ov))
+    return sorted(out)
+
+
+def test_every_split_the_tuner_can_pick_is_valid_and_owns_every_cell_once():
+    """The library accepts every split in the tuner's search space (no
+    YO_EINVAL mid-sweep), and each owns every cell once: all of them on
+    the micro device, a seeded sample of 60 on the realistic one."""
+    import random
+    from paper_2505_03352_amd import autotune as at
+    space = _tuner_space()
+    assert len(space) > 1000
+    for name, n in (("micro", None), ("realistic", 60)):
+        dev = getattr(configs, name)()
+        shape = (dev.nz, dev.ny, dev.nx)
+        p = _plan(dev, 2)
+        for zc, fl in space:
+            p.set_tiling(at.ROWS, zc, fl)
+        for zc, fl in (space if n is None else random.Random(0).sample(space, n)):
+            p.set_tiling(at.ROWS, zc, fl)
+            cov = _cover(p, (0, 1), shape)
+            assert cov.min() == 1 and cov.max() == 1, (name, zc, fl, "single")
+            if fl & 512:
+                cov = _cover(p, (2, 3, 4, 5), shape)
+                assert cov.min() == 1 and cov.max() == 1, (name, zc, fl, "pairs")
+        p.close()
